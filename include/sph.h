@@ -1,0 +1,182 @@
+/*
+ * libsph_hip — cell-based SPH neighbour interactions on one MI355X (gfx950).
+ *
+ * The calls follow the SPH statement of Schaller et al., "SWIFT: Using
+ * task-based parallelism, fully asynchronous communication, and graph
+ * partition-based domain decomposition for strong scaling on more than
+ * 100 000 cores" (PASC'16), Sec. 2 (equations (rho), (dvdt), (dudt) with
+ * P = (gamma-1) rho u and Omega = 1 + h/(3 rho) d rho/d h) and the cell / task
+ * decomposition of Sec. 3.1: cells of edge at least the largest smoothing
+ * length, recursively split while they hold more than a set number of
+ * particles, self and pair interactions, a sort stage before the density
+ * stage, a ghost stage between density and force, and an integrator stage
+ * after the force.
+ *
+ * Notation: H is the paper's smoothing length h, the radius of the sphere
+ * within which neighbours contribute (compact support of the cubic-spline
+ * kernel W(r,H) = 8/(pi H^3) w(r/H)).  The smoothing length of every particle
+ * is solved so that rho_i H_i^3 = (kernel_gamma * eta)^3 m_i.
+ *
+ * Conventions of every call:
+ *   - Returns sph_status; never throws, never aborts.  Argument errors and
+ *     HIP launch errors are reported synchronously.  Conditions found on the
+ *     device (non-convergence, H too large for the box) are reported by the
+ *     call that observes them (the density call synchronises its stream once
+ *     per smoothing-length sweep).
+ *   - All particle arrays are DEVICE pointers owned by the caller, length n,
+ *     structure-of-arrays, float64 unless stated.  The library never frees
+ *     them.  It keeps its own scratch buffers (device memory allocated with
+ *     hipMalloc inside sph_build_cells when they need to grow) and frees them
+ *     in sph_destroy.
+ *   - Work is enqueued on the HIP stream given to sph_create.
+ *   - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef SPH_H
+#define SPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPH_OK = 0,
+    SPH_ERR_INVALID = -1,        /* bad argument, NaN/Inf input, position outside its box */
+    SPH_ERR_HIP = -2,            /* a HIP runtime call or kernel launch failed */
+    SPH_ERR_NOT_CONVERGED = -3,  /* smoothing lengths not converged in max_h_iter sweeps */
+    SPH_ERR_H_EXCEEDS_CELL = -4, /* a smoothing length outgrew the cell grid (rebuild) */
+    SPH_ERR_BOX_TOO_SMALL = -5,  /* a smoothing length exceeds 1/3 of its box edge */
+    SPH_ERR_ALLOC = -6,          /* device allocation failed */
+    SPH_ERR_STATE = -7           /* call out of order (e.g. force before ghost) */
+} sph_status;
+
+enum { SPH_FP64 = 0, SPH_FP32C = 1, SPH_FP32 = 2 };      /* sph_params.precision */
+enum { SPH_EXEC_GRID = 0, SPH_EXEC_PERSISTENT = 1 };     /* sph_params.exec_mode */
+
+typedef struct {
+    double gamma;        /* adiabatic index, 5/3 */
+    double eta;          /* resolution parameter (Dehnen-Aly), 1.2348 ~ 48 neighbours */
+    double kernel_gamma; /* H / h_DA for the cubic spline, sqrt(10/3) */
+    double h_tol;        /* converged when |rho H^3 - C| <= h_tol * C (FP64 test) */
+    int max_h_iter;      /* smoothing-length sweeps per density call */
+    int n_split;         /* split cells holding more than this many particles (<= 64) */
+    int precision;       /* SPH_FP64, SPH_FP32C (cell-relative FP32, compensated sums)
+                            or SPH_FP32 (cell-relative FP32, plain sums) */
+    int exec_mode;       /* SPH_EXEC_GRID: one workgroup slot per cell;
+                            SPH_EXEC_PERSISTENT: resident workgroups drain a
+                            cost-ordered device task queue */
+    int n_domains;       /* number of independent periodic boxes (>= 1) */
+    int persistent_wgs;  /* resident workgroups for the persistent mode (0: auto) */
+    int waves_per_wg;    /* waves per workgroup in the interaction kernels (1..4, 0: 4) */
+    int pad;
+    const double* boxes; /* HOST pointer, n_domains x 3 box edge lengths; copied */
+} sph_params;
+
+typedef struct {
+    int64_t n;
+    double *x, *y, *z;       /* positions, inside [0, L) of their box (in/out) */
+    double *vx, *vy, *vz;    /* velocities (in/out) */
+    double *u;               /* specific internal energy (in/out) */
+    double *m;               /* masses (in) */
+    double *H;               /* smoothing lengths: initial guess in, converged out */
+    double *rho, *drho_dH;   /* density and its H-derivative at the converged H (out) */
+    double *omega, *P;       /* grad-h term Omega and pressure (out, ghost) */
+    double *ax, *ay, *az;    /* acceleration dv/dt (out, force) */
+    double *dudt;            /* du/dt (out, force) */
+    int64_t *id;             /* optional: carried through the permutation (may be NULL) */
+    int32_t *domain;         /* box index of each particle; NULL when n_domains == 1 */
+    int32_t *nngb;           /* optional: #{j : r_ij < H_i}, self included, at the
+                                converged H (out, density; may be NULL) */
+} sph_particles;
+
+typedef struct {
+    int64_t n;               /* particles */
+    int64_t n_leaves;        /* leaf cells (self tasks) */
+    int64_t n_nodes;         /* cells of all levels */
+    int64_t n_list;          /* neighbour-cell entries (ordered pairs incl. self) */
+    int64_t n_pair_tasks;    /* unordered pair tasks (B > A) */
+    int64_t n_dens;          /* sum_i #{j : r_ij < H_i}, self included, last density call */
+    int64_t n_force;         /* #{unordered i != j : r_ij < max(H_i,H_j)}, last force call */
+    int32_t sweeps;          /* density sweeps of the last density call */
+    int32_t n_unconverged;   /* particles left unconverged by the last density call */
+    int32_t relists;         /* neighbour-list rebuilds inside the last density call */
+    int32_t rebuilds;        /* full cell rebuilds since create */
+    int32_t depth;           /* deepest cell level */
+    int32_t key_bits;        /* bits sorted by the Morton radix sort */
+    double conserved[5];     /* FP64 totals after the last step: M, Px, Py, Pz, E */
+    double t_density_ms;     /* stream time of the last density call (all sweeps) */
+    double t_ghost_ms;
+    double t_force_ms;
+    double t_build_ms;       /* last build_cells + sort_cells */
+} sph_stats;
+
+typedef struct sph_ctx sph_ctx;
+
+/* Create a context.  `params` is copied (including the boxes array).
+ * hip_stream: a hipStream_t (NULL = default stream). */
+sph_status sph_create(const sph_params* params, void* hip_stream, sph_ctx** out);
+
+/* Release every buffer the context owns.  Safe on NULL. */
+sph_status sph_destroy(sph_ctx* ctx);
+
+/* Cell construction (Sec. 3.1: a grid of cells of edge >= the largest H per
+ * box, recursively split while a cell holds more than n_split particles;
+ * self and pair interactions between cells within range).  Binds `p` to the
+ * context, permutes every non-NULL particle array in place into Morton order
+ * of the cells, and builds the neighbour-cell lists.  Particles must lie in
+ * [0, L) of their box.  Errors: SPH_ERR_INVALID (NaN, non-positive H or m,
+ * out-of-box position), SPH_ERR_BOX_TOO_SMALL (max H > L/3). */
+sph_status sph_build_cells(sph_ctx* ctx, const sph_particles* p);
+
+/* Sort stage (Sec. 3.1 "sorted" cells): for every leaf cell and each of the
+ * 13 axis directions between neighbouring cells, the particles' projections
+ * sorted ascending; used to skip pair candidates whose projections differ by
+ * at least the interaction range.  Requires sph_build_cells. */
+sph_status sph_sort_cells(sph_ctx* ctx);
+
+/* Density stage, eq. (rho): sweeps over self and pair interactions computing
+ * rho_i, d rho_i/d H_i and the neighbour count at the current H, each
+ * followed by an FP64 Newton-Raphson update of H toward rho H^3 = C inside a
+ * bracket; repeats for the unconverged particles until all pass the FP64
+ * test or max_h_iter sweeps are done (SPH_ERR_NOT_CONVERGED).  Writes H, rho,
+ * drho_dH.  Requires sph_sort_cells. */
+sph_status sph_density(sph_ctx* ctx);
+
+/* Ghost stage (Sec. 3.1, with the closing relations of Sec. 2): Omega_i, P_i
+ * = (gamma-1) rho_i u_i and A_i = P_i/(Omega_i rho_i^2).  Writes omega, P.
+ * Requires sph_density. */
+sph_status sph_ghost(sph_ctx* ctx);
+
+/* Force stage, eqs. (dvdt) and (dudt): every unordered pair with r_ij <
+ * max(H_i, H_j) evaluated once and applied to both particles.  Writes ax,
+ * ay, az, dudt.  Requires sph_ghost. */
+sph_status sph_force(sph_ctx* ctx);
+
+/* One kick-drift-kick step of length dt (integrator stage, Sec. 3.1):
+ * half kick of v and u with the current forces, drift with periodic wrap,
+ * cell rebuild and sort, density with H warm-started, ghost with the
+ * predicted u, force with the predicted v, second half kick, FP64
+ * conservation sums.  Requires a previous sph_force (forces of the current
+ * positions). */
+sph_status sph_step(sph_ctx* ctx, double dt);
+
+/* Copy counters and timings to *out (synchronises the stream). */
+sph_status sph_get_stats(sph_ctx* ctx, sph_stats* out);
+
+/* FP64 per-box totals of the bound particles (synchronises the stream):
+ * out[5*b + k] = (M, Px, Py, Pz, E)_k of box b, out has 5*n_domains doubles
+ * (HOST pointer). */
+sph_status sph_domain_sums(sph_ctx* ctx, double* out);
+
+/* Human-readable name of a status code (static string). */
+const char* sph_status_str(sph_status s);
+
+/* Library build description (static string). */
+const char* sph_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -69,7 +69,7 @@ def lib():
                                      _I64, _D, _D, _I64, _I32, _I64]
         L.oracle_ghost.argtypes = [P, C.c_int64, _D, _D, _D, _D, _D, _D, _D, _D]
         L.oracle_force.argtypes = [P, C.c_void_p, C.c_int64, _D, _D, _D, _D, _D, _D, _D, _D, _D,
-                                   C.c_int64, _I64, _D, _D, _D, _D, _I64]
+                                   C.c_int64, _I64, _D, _D, _D, _D, _I64, _D, _D]
         L.oracle_step.argtypes = [P, C.c_int, C.c_int64] + [_D] * 9 + [_D] * 4 + [_D] * 5 + \
                                  [_I64, _I64, C.c_double]
         L.oracle_conserved.argtypes = [C.c_int64, _D, _D, _D, _D, _D, _D]
@@ -182,20 +182,21 @@ def ghost(rho, drho, H, u, gamma=5.0 / 3.0):
 
 def force(x, y, z, vx, vy, vz, m, H, A, box, tree=True, idx=None):
     """a (3 arrays), du/dt and the per-particle count of j with
-    r_ij < max(H_i, H_j) (eqs. (dvdt), (dudt))."""
+    r_ij < max(H_i, H_j) (eqs. (dvdt), (dudt)), plus the magnitude scales
+    sa = sum_j m_j |A_i dW_i + A_j dW_j| and su = sum_j |A_i m_j dW_i v_ij.r_ij/r|."""
     x, y, z, vx, vy, vz, m, H, A = map(_f64, (x, y, z, vx, vy, vz, m, H, A))
     n = x.size
     p = params(box)
     t = Tree(x, y, z, box) if tree is True else (tree or None)
-    ax, ay, az, du = (np.zeros(n) for _ in range(4))
+    ax, ay, az, du, sa, su = (np.zeros(n) for _ in range(6))
     fc = np.zeros(n, dtype=np.int64)
     ni, ia, ip = _idx(idx)
     st = lib().oracle_force(C.byref(p), t.h if t else None, n, _d(x), _d(y), _d(z), _d(vx),
                             _d(vy), _d(vz), _d(m), _d(H), _d(A), ni, ip, _d(ax), _d(ay), _d(az),
-                            _d(du), fc.ctypes.data_as(_I64))
+                            _d(du), fc.ctypes.data_as(_I64), _d(sa), _d(su))
     if st != 0:
         raise RuntimeError("oracle_force status %d" % st)
-    return dict(ax=ax, ay=ay, az=az, dudt=du, fcnt=fc)
+    return dict(ax=ax, ay=ay, az=az, dudt=du, fcnt=fc, sa=sa, su=su)
 
 
 def full(d, tree=True, h_tol=1e-10, max_iter=50, gamma=5.0 / 3.0, idx=None, eta=ETA):

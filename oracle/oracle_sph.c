@@ -254,6 +254,7 @@ typedef struct {
     int64_t cnt;
     double ax, ay, az, du;
     int64_t fcnt;
+    double sa, su;
 } acc_t;
 
 /* ------------------------------------------------------------------ */
@@ -444,6 +445,9 @@ static void force_pair(int64_t i, int64_t j, double dx, double dy, double dz, do
                        const double* H, const double* A, acc_t* a)
 {
     double Hi = H[i], Hj = H[j];
+    a->fcnt++;
+    /* the kernel gradient vanishes at r = 0: coincident particles exert no force */
+    if (r2 <= 0.0) return;
     double r = sqrt(r2);
     double dWi = (r < Hi) ? oracle_dWdr(r, Hi) : 0.0;
     double dWj = (r < Hj) ? oracle_dWdr(r, Hj) : 0.0;
@@ -451,7 +455,9 @@ static void force_pair(int64_t i, int64_t j, double dx, double dy, double dz, do
     a->ax -= f * dx; a->ay -= f * dy; a->az -= f * dz;
     double dvdr = (vx[i] - vx[j]) * dx + (vy[i] - vy[j]) * dy + (vz[i] - vz[j]) * dz;
     a->du += A[i] * m[j] * dWi * dvdr / r;
-    a->fcnt++;
+    /* error scales: sums of term magnitudes (no cancellation) */
+    a->sa += m[j] * fabs(A[i] * dWi + A[j] * dWj);
+    a->su += fabs(A[i] * m[j] * dWi * dvdr / r);
 }
 
 static void force_one_bf(const oracle_params* p, int64_t n, const double* x, const double* y,
@@ -507,12 +513,14 @@ static void force_one_tree(const kd_tree* t, const double* x, const double* y, c
 }
 
 /* Accelerations and du/dt for particles idx (all if NULL).  fcnt[i] = number
- * of j != i with r_ij < max(H_i, H_j). */
+ * of j != i with r_ij < max(H_i, H_j); sa[i] = sum_j m_j |A_i dW_i + A_j dW_j|
+ * and su[i] = sum_j |A_i m_j dW_i (v_i - v_j).r_ij/r| are the per-particle
+ * magnitude scales used to normalise force errors (optional, may be NULL). */
 int oracle_force(const oracle_params* p, void* tree, int64_t n, const double* x, const double* y,
                  const double* z, const double* vx, const double* vy, const double* vz,
                  const double* m, const double* H, const double* A, int64_t n_idx,
                  const int64_t* idx, double* ax, double* ay, double* az, double* dudt,
-                 int64_t* fcnt)
+                 int64_t* fcnt, double* sa, double* su)
 {
     if (!p || n <= 0) return ORACLE_ERR_INVALID;
     kd_tree* t = (kd_tree*)tree;
@@ -527,6 +535,8 @@ int oracle_force(const oracle_params* p, void* tree, int64_t n, const double* x,
         else force_one_bf(p, n, x, y, z, vx, vy, vz, m, H, A, i, &a);
         ax[i] = a.ax; ay[i] = a.ay; az[i] = a.az; dudt[i] = a.du;
         if (fcnt) fcnt[i] = a.fcnt;
+        if (sa) sa[i] = a.sa;
+        if (su) su[i] = a.su;
     }
     return ORACLE_OK;
 }
@@ -568,7 +578,8 @@ int oracle_step(const oracle_params* p, int use_tree, int64_t n, double* x, doub
     int st = oracle_solve_h(p, t, n, x, y, z, m, H, 0, NULL, rho, drho, cnt, NULL, &nf);
     if (st == ORACLE_OK) {
         oracle_ghost(p, n, rho, drho, H, us, omega, P, A, NULL);
-        oracle_force(p, t, n, x, y, z, vxs, vys, vzs, m, H, A, 0, NULL, ax, ay, az, dudt, fcnt);
+        oracle_force(p, t, n, x, y, z, vxs, vys, vzs, m, H, A, 0, NULL, ax, ay, az, dudt, fcnt,
+                     NULL, NULL);
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; i++) {
             vx[i] += ax[i] * hdt; vy[i] += ay[i] * hdt; vz[i] += az[i] * hdt;

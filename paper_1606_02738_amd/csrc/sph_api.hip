@@ -1,0 +1,199 @@
+// C-ABI of libsph_hip: context lifetime, argument checks, stage ordering,
+// statistics.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "sph_ctx.h"
+
+sph_status buf_ensure(DevBuf& b, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    if (b.cap >= bytes) return SPH_OK;
+    if (b.p) {
+        if (hipFree(b.p) != hipSuccess) return SPH_ERR_HIP;
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    size_t want = bytes + bytes / 8 + 256;
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return SPH_ERR_ALLOC;
+    }
+    b.cap = want;
+    return SPH_OK;
+}
+
+void buf_free(DevBuf& b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+extern "C" {
+
+const char* sph_status_str(sph_status s)
+{
+    switch (s) {
+    case SPH_OK: return "ok";
+    case SPH_ERR_INVALID: return "invalid argument or input";
+    case SPH_ERR_HIP: return "HIP runtime error";
+    case SPH_ERR_NOT_CONVERGED: return "smoothing lengths not converged";
+    case SPH_ERR_H_EXCEEDS_CELL: return "smoothing length exceeds the cell grid";
+    case SPH_ERR_BOX_TOO_SMALL: return "smoothing length exceeds a third of the box";
+    case SPH_ERR_ALLOC: return "device allocation failed";
+    case SPH_ERR_STATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+const char* sph_version(void) { return "libsph_hip 0.1 gfx950 wave64"; }
+
+sph_status sph_create(const sph_params* params, void* hip_stream, sph_ctx** out)
+{
+    if (!params || !out) return SPH_ERR_INVALID;
+    *out = nullptr;
+    const sph_params& p = *params;
+    if (p.n_domains < 1 || !p.boxes) return SPH_ERR_INVALID;
+    if (!(p.gamma > 1.0) || !(p.eta > 0.0) || !(p.kernel_gamma > 0.0) || !(p.h_tol > 0.0)) return SPH_ERR_INVALID;
+    if (p.max_h_iter < 1 || p.n_split < 1 || p.n_split > SPH_MAX_LEAF) return SPH_ERR_INVALID;
+    if (p.precision < SPH_FP64 || p.precision > SPH_FP32) return SPH_ERR_INVALID;
+    if (p.exec_mode < SPH_EXEC_GRID || p.exec_mode > SPH_EXEC_PERSISTENT) return SPH_ERR_INVALID;
+    for (int k = 0; k < 3 * p.n_domains; k++)
+        if (!(p.boxes[k] > 0.0) || !isfinite(p.boxes[k])) return SPH_ERR_INVALID;
+    sph_ctx* c = new (std::nothrow) sph_ctx();
+    if (!c) return SPH_ERR_ALLOC;
+    c->prm = p;
+    c->boxes.assign(p.boxes, p.boxes + 3 * p.n_domains);
+    c->prm.boxes = nullptr;
+    c->stream = (hipStream_t)hip_stream;
+    sph_status s = SPH_OK;
+    if (s == SPH_OK) s = buf_ensure(c->flags, FI_NFLAGS * sizeof(int));
+    if (s == SPH_OK) s = buf_ensure(c->counters, CNT_N * 8);
+    if (s == SPH_OK) s = buf_ensure(c->dom_d, (size_t)p.n_domains * sizeof(DomainInfo));
+    if (s == SPH_OK) s = buf_ensure(c->dstat, (size_t)p.n_domains * 16);
+    for (int k = 0; k < 8 && s == SPH_OK; k++)
+        if (hipEventCreate(&c->ev[k]) != hipSuccess) s = SPH_ERR_HIP;
+    if (s == SPH_OK && hipMemsetAsync(c->flags.p, 0, FI_NFLAGS * sizeof(int), c->stream) != hipSuccess) s = SPH_ERR_HIP;
+    if (s == SPH_OK && hipMemsetAsync(c->counters.p, 0, CNT_N * 8, c->stream) != hipSuccess) s = SPH_ERR_HIP;
+    if (s != SPH_OK) {
+        sph_destroy(c);
+        return s;
+    }
+    *out = c;
+    return SPH_OK;
+}
+
+sph_status sph_destroy(sph_ctx* c)
+{
+    if (!c) return SPH_OK;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    DevBuf* all[] = {&c->dom_d, &c->dstat, &c->keys[0], &c->keys[1], &c->vals[0], &c->vals[1], &c->okeys[0], &c->okeys[1], &c->ovals[0], &c->ovals[1], &c->dranges, &c->tmp, &c->nodes,
+                     &c->nchild, &c->coff, &c->leafmark, &c->leafscan, &c->leaf_node, &c->l_begin, &c->l_count,
+                     &c->l_origin, &c->l_lo, &c->l_hi, &c->l_hlist, &c->l_dom, &c->l_off, &c->l_active, &c->l_sorted,
+                     &c->l_cnt, &c->l_cost, &c->l_order, &c->list, &c->pos4, &c->fv4, &c->hf, &c->skey, &c->sidx,
+                     &c->hlo, &c->hhi, &c->conv, &c->vpx, &c->vpy, &c->vpz, &c->upr, &c->flags, &c->counters,
+                     &c->scan_tmp, &c->rs_hist, &c->sums, &c->dsum_part};
+    for (DevBuf* b : all) buf_free(*b);
+    for (int k = 0; k < 8; k++)
+        if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+    delete c;
+    return SPH_OK;
+}
+
+sph_status sph_build_cells(sph_ctx* c, const sph_particles* p)
+{
+    if (!c || !p) return SPH_ERR_INVALID;
+    if (p->n <= 0 || p->n >= (int64_t)1 << 31) return SPH_ERR_INVALID;
+    const double* req[] = {p->x, p->y, p->z, p->vx, p->vy, p->vz, p->u, p->m, p->H,
+                           p->rho, p->drho_dH, p->ax, p->ay, p->az, p->dudt};
+    for (const double* a : req)
+        if (!a) return SPH_ERR_INVALID;
+    if (c->prm.n_domains > 1 && !p->domain) return SPH_ERR_INVALID;
+    c->P = *p;
+    c->n = p->n;
+    c->bound = true;
+    c->built = c->sorted = c->dens_done = c->ghost_done = c->force_done = false;
+    SPH_CHECK_HIP(hipEventRecord(c->ev[6], c->stream));
+    sph_status s = build_all(c);
+    if (s == SPH_OK) c->st.rebuilds++;
+    return s;
+}
+
+sph_status sph_sort_cells(sph_ctx* c)
+{
+    if (!c) return SPH_ERR_INVALID;
+    if (!c->built) return SPH_ERR_STATE;
+    SPH_TRY(sort_all(c));
+    SPH_CHECK_HIP(hipEventRecord(c->ev[7], c->stream));
+    return SPH_OK;
+}
+
+sph_status sph_density(sph_ctx* c)
+{
+    if (!c) return SPH_ERR_INVALID;
+    if (!c->sorted) return SPH_ERR_STATE;
+    return density_all(c);
+}
+
+sph_status sph_ghost(sph_ctx* c)
+{
+    if (!c) return SPH_ERR_INVALID;
+    return ghost_all(c);
+}
+
+sph_status sph_force(sph_ctx* c)
+{
+    if (!c) return SPH_ERR_INVALID;
+    return force_all(c);
+}
+
+sph_status sph_step(sph_ctx* c, double dt)
+{
+    if (!c) return SPH_ERR_INVALID;
+    if (!(dt > 0.0) || !isfinite(dt)) return SPH_ERR_INVALID;
+    if (!c->force_done) return SPH_ERR_STATE;
+    return step_all(c, dt);
+}
+
+static double elapsed(hipEvent_t a, hipEvent_t b)
+{
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1.0;
+    }
+    return ms;
+}
+
+sph_status sph_get_stats(sph_ctx* c, sph_stats* out)
+{
+    if (!c || !out) return SPH_ERR_INVALID;
+    SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
+    c->st.n = c->n;
+    c->st.n_leaves = c->n_leaves;
+    c->st.n_nodes = c->n_nodes;
+    c->st.n_list = c->n_list;
+    c->st.n_pair_tasks = c->n_pair_tasks;
+    c->st.depth = c->depth;
+    c->st.key_bits = c->key_bits;
+    c->st.t_density_ms = c->dens_done ? elapsed(c->ev[0], c->ev[1]) : -1.0;
+    c->st.t_ghost_ms = c->ghost_done ? elapsed(c->ev[2], c->ev[3]) : -1.0;
+    c->st.t_force_ms = c->force_done ? elapsed(c->ev[4], c->ev[5]) : -1.0;
+    c->st.t_build_ms = c->sorted ? elapsed(c->ev[6], c->ev[7]) : -1.0;
+    *out = c->st;
+    return SPH_OK;
+}
+
+sph_status sph_domain_sums(sph_ctx* c, double* out)
+{
+    if (!c || !out) return SPH_ERR_INVALID;
+    if (!c->built) return SPH_ERR_STATE;
+    return domain_sums(c, out);
+}
+
+}  // extern "C"

@@ -1,0 +1,819 @@
+// Cell construction and sort stage (Sec. 3.1 of the paper): top-level grid
+// of cells of edge >= the largest smoothing length, Morton keys, radix sort,
+// recursive octree split of cells holding more than n_split particles,
+// leaf cells, neighbour-cell lists between leaves within range, and the
+// per-direction sorted projections used to prune pair candidates.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "sph_ctx.h"
+
+// ---------------------------------------------------------------------------
+// Validation: finite inputs, positive m and H, positions inside [0,L) of the
+// particle's box; per-box largest and smallest H.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_validate(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+                                                  const double* __restrict__ z, const double* __restrict__ H,
+                                                  const double* __restrict__ m, const int32_t* __restrict__ dom,
+                                                  int ndom, const DomainInfo* __restrict__ di,
+                                                  unsigned long long* dstat, int* flags)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool ok = i < n;
+    int d = 0;
+    double h = 0.0;
+    if (ok) {
+        d = dom ? dom[i] : 0;
+        if (d < 0 || d >= ndom) {
+            atomicOr(flags, FLAG_INVALID);
+            ok = false;
+        }
+    }
+    if (ok) {
+        const double* L = di[d].L;
+        const double px = x[i], py = y[i], pz = z[i];
+        h = H[i];
+        const double mm = m[i];
+        bool good = isfinite(px) && isfinite(py) && isfinite(pz) && px >= 0.0 && px < L[0] && py >= 0.0 &&
+                    py < L[1] && pz >= 0.0 && pz < L[2] && isfinite(h) && h > 0.0 && isfinite(mm) && mm > 0.0;
+        if (!good) {
+            atomicOr(flags, FLAG_INVALID);
+            ok = false;
+        }
+    }
+    // wave-level reduction when the whole wave is one box
+    const int d0 = __shfl(d, 0);
+    const unsigned long long act = __ballot(ok);
+    const unsigned long long same = __ballot(ok && d == d0);
+    if (act != 0 && same == act && __shfl(ok ? 1 : 0, 0)) {
+        double hmx = ok ? h : 0.0, hmn = ok ? h : INFINITY;
+        for (int off = 32; off > 0; off >>= 1) {
+            hmx = fmax(hmx, __shfl_xor(hmx, off));
+            hmn = fmin(hmn, __shfl_xor(hmn, off));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomicMax(&dstat[2 * d0], (unsigned long long)__double_as_longlong(hmx));
+            atomicMin(&dstat[2 * d0 + 1], (unsigned long long)__double_as_longlong(hmn));
+        }
+    } else if (ok) {
+        atomicMax(&dstat[2 * d], (unsigned long long)__double_as_longlong(h));
+        atomicMin(&dstat[2 * d + 1], (unsigned long long)__double_as_longlong(h));
+    }
+}
+
+__device__ inline uint64_t spread3(uint32_t v, int bits)
+{
+    uint64_t r = 0;
+    for (int b = 0; b < bits; b++) r |= (uint64_t)((v >> b) & 1u) << (3 * b);
+    return r;
+}
+
+__device__ inline int top_coord(double x, double s0, int nt)
+{
+    int ix = (int)floor(x / s0);
+    return ix < 0 ? 0 : (ix >= nt ? nt - 1 : ix);
+}
+
+// Morton key: global top-cell index in the high bits, D interleaved bits per
+// dimension of the position inside the top cell below.
+__global__ __launch_bounds__(256) void k_keys(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+                                              const double* __restrict__ z, const int32_t* __restrict__ dom,
+                                              const DomainInfo* __restrict__ di, int D, uint64_t* __restrict__ keys,
+                                              uint32_t* __restrict__ vals)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const DomainInfo& I = di[dom ? dom[i] : 0];
+    const double p[3] = {x[i], y[i], z[i]};
+    int t[3];
+    uint32_t q[3];
+    const double scale = (double)(1u << D);
+    for (int a = 0; a < 3; a++) {
+        t[a] = top_coord(p[a], I.s0[a], I.n_top[a]);
+        double f = (p[a] - t[a] * I.s0[a]) / I.s0[a] * scale;
+        long qi = (long)floor(f);
+        if (qi < 0) qi = 0;
+        if (qi > (1l << D) - 1) qi = (1l << D) - 1;
+        q[a] = (uint32_t)qi;
+    }
+    const uint64_t top = (uint64_t)I.top_offset + ((uint64_t)t[0] * I.n_top[1] + t[1]) * I.n_top[2] + t[2];
+    keys[i] = (top << (3 * D)) | (spread3(q[0], D) << 2) | (spread3(q[1], D) << 1) | spread3(q[2], D);
+    vals[i] = (uint32_t)i;
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_gather(int64_t n, const uint32_t* __restrict__ perm, const V* __restrict__ src,
+                                                V* __restrict__ dst)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[perm[i]];
+}
+
+__device__ inline int lower_bound_u64(const uint64_t* a, int lo, int hi, uint64_t v)
+{
+    while (lo < hi) {
+        int mid = lo + (hi - lo) / 2;
+        if (a[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Level-0 cells: the top grid of every box.
+__global__ __launch_bounds__(256) void k_top_nodes(int n_top_total, int ndom, const DomainInfo* __restrict__ di,
+                                                   const uint64_t* __restrict__ keys, int n, int D, Node* nodes)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_top_total) return;
+    int d = 0;
+    while (d + 1 < ndom && di[d + 1].top_offset <= t) d++;
+    const DomainInfo& I = di[d];
+    const int loc = t - I.top_offset;
+    const int tz = loc % I.n_top[2], ty = (loc / I.n_top[2]) % I.n_top[1], tx = loc / (I.n_top[2] * I.n_top[1]);
+    Node nd;
+    nd.key_lo = (uint64_t)t << (3 * D);
+    nd.begin = lower_bound_u64(keys, 0, n, nd.key_lo);
+    nd.count = lower_bound_u64(keys, nd.begin, n, (uint64_t)(t + 1) << (3 * D)) - nd.begin;
+    nd.first_child = -1;
+    nd.n_child = 0;
+    nd.level = 0;
+    nd.domain = d;
+    nd.leaf = -1;
+    nd.top = t;
+    nd.c_lo[0] = tx * I.s0[0]; nd.c_lo[1] = ty * I.s0[1]; nd.c_lo[2] = tz * I.s0[2];
+    for (int a = 0; a < 3; a++) {
+        nd.c_sz[a] = I.s0[a];
+        nd.lo[a] = INFINITY;
+        nd.hi[a] = -INFINITY;
+    }
+    nd.hmax = 0.0;
+    nodes[t] = nd;
+}
+
+// Statistics of one cell (bounding box, largest H) and its number of
+// non-empty children if it is to be split.  One workgroup per cell.
+__global__ __launch_bounds__(256) void k_node_stats(Node* nodes, int level_start, const uint64_t* __restrict__ keys,
+                                                    const double* __restrict__ x, const double* __restrict__ y,
+                                                    const double* __restrict__ z, const double* __restrict__ H, int D,
+                                                    int n_split, int* nchild)
+{
+    __shared__ double red[7][256];
+    __shared__ int bnd[9];
+    const int k = blockIdx.x;
+    Node* nd = &nodes[level_start + k];
+    const int b = nd->begin, c = nd->count, tid = threadIdx.x;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, hm = 0.0;
+    for (int p = b + tid; p < b + c; p += 256) {
+        const double q[3] = {x[p], y[p], z[p]};
+        for (int a = 0; a < 3; a++) {
+            lo[a] = fmin(lo[a], q[a]);
+            hi[a] = fmax(hi[a], q[a]);
+        }
+        hm = fmax(hm, H[p]);
+    }
+    for (int a = 0; a < 3; a++) {
+        red[a][tid] = lo[a];
+        red[3 + a][tid] = hi[a];
+    }
+    red[6][tid] = hm;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+            for (int a = 0; a < 3; a++) {
+                red[a][tid] = fmin(red[a][tid], red[a][tid + s]);
+                red[3 + a][tid] = fmax(red[3 + a][tid], red[3 + a][tid + s]);
+            }
+            red[6][tid] = fmax(red[6][tid], red[6][tid + s]);
+        }
+        __syncthreads();
+    }
+    const bool split = c > n_split && nd->level < D;
+    if (split && tid < 9) {
+        const uint64_t step = 1ull << (3 * (D - nd->level - 1));
+        bnd[tid] = (tid == 0) ? b : (tid == 8 ? b + c : lower_bound_u64(keys, b, b + c, nd->key_lo + step * tid));
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int a = 0; a < 3; a++) {
+            nd->lo[a] = red[a][0];
+            nd->hi[a] = red[3 + a][0];
+        }
+        nd->hmax = red[6][0];
+        int nc = 0;
+        if (split)
+            for (int q = 0; q < 8; q++) nc += (bnd[q + 1] > bnd[q]) ? 1 : 0;
+        nchild[k] = nc;
+        nd->n_child = nc;
+        nd->first_child = -1;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_emit_children(Node* nodes, int level_start, int n_level, const int* __restrict__ coff,
+                                                      int child_base, const uint64_t* __restrict__ keys, int D)
+{
+    const int k = blockIdx.x;
+    if (k >= n_level) return;
+    Node* nd = &nodes[level_start + k];
+    if (nd->n_child == 0) return;
+    __shared__ int bnd[9];
+    const int tid = threadIdx.x;
+    const int b = nd->begin, c = nd->count;
+    const uint64_t step = 1ull << (3 * (D - nd->level - 1));
+    if (tid < 9) bnd[tid] = (tid == 0) ? b : (tid == 8 ? b + c : lower_bound_u64(keys, b, b + c, nd->key_lo + step * tid));
+    __syncthreads();
+    if (tid == 0) {
+        int out = child_base + coff[k];
+        nd->first_child = out;
+        for (int q = 0; q < 8; q++) {
+            if (bnd[q + 1] <= bnd[q]) continue;
+            Node ch;
+            ch.key_lo = nd->key_lo + step * q;
+            ch.begin = bnd[q];
+            ch.count = bnd[q + 1] - bnd[q];
+            ch.first_child = -1;
+            ch.n_child = 0;
+            ch.level = nd->level + 1;
+            ch.domain = nd->domain;
+            ch.leaf = -1;
+            ch.top = nd->top;
+            const int o[3] = {(q >> 2) & 1, (q >> 1) & 1, q & 1};
+            for (int a = 0; a < 3; a++) {
+                ch.c_sz[a] = 0.5 * nd->c_sz[a];
+                ch.c_lo[a] = nd->c_lo[a] + o[a] * ch.c_sz[a];
+                ch.lo[a] = INFINITY;
+                ch.hi[a] = -INFINITY;
+            }
+            ch.hmax = 0.0;
+            nodes[out++] = ch;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mark_leaves(const Node* __restrict__ nodes, int n_nodes, int* leafmark)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_nodes) return;
+    const Node& nd = nodes[k];
+    if (nd.n_child == 0 && nd.count > 0) leafmark[nd.begin] = 1;
+}
+
+__global__ __launch_bounds__(256) void k_leaf_fill(Node* nodes, int n_nodes, const int* __restrict__ leafscan,
+                                                   int* leaf_node, int* l_begin, int* l_count, double* l_origin,
+                                                   double* l_lo, double* l_hi, double* l_hlist, int* l_dom)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_nodes) return;
+    Node& nd = nodes[k];
+    if (!(nd.n_child == 0 && nd.count > 0)) {
+        nd.leaf = -1;
+        return;
+    }
+    const int id = leafscan[nd.begin];
+    nd.leaf = id;
+    leaf_node[id] = k;
+    l_begin[id] = nd.begin;
+    l_count[id] = nd.count;
+    for (int a = 0; a < 3; a++) {
+        l_lo[3 * id + a] = nd.lo[a];
+        l_hi[3 * id + a] = nd.hi[a];
+        l_origin[3 * id + a] = 0.5 * (nd.lo[a] + nd.hi[a]);
+    }
+    l_hlist[id] = nd.hmax;
+    l_dom[id] = nd.domain;
+}
+
+// Cell-relative coordinates (and masses) of every particle in its leaf.
+template <typename T>
+__global__ __launch_bounds__(256) void k_leaf_pos(int n_leaves, const int* __restrict__ l_begin,
+                                                  const int* __restrict__ l_count, const double* __restrict__ l_origin,
+                                                  const double* __restrict__ x, const double* __restrict__ y,
+                                                  const double* __restrict__ z, const double* __restrict__ m,
+                                                  const double* __restrict__ H, typename vec4<T>::type* pos4, T* hf)
+{
+    const int A = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    if (A >= n_leaves) return;
+    const int lane = threadIdx.x & 63;
+    const int b = l_begin[A], c = l_count[A];
+    const double ox = l_origin[3 * A], oy = l_origin[3 * A + 1], oz = l_origin[3 * A + 2];
+    for (int p = b + lane; p < b + c; p += 64) {
+        typename vec4<T>::type v;
+        v.x = (T)(x[p] - ox);
+        v.y = (T)(y[p] - oy);
+        v.z = (T)(z[p] - oz);
+        v.w = (T)m[p];
+        pos4[p] = v;
+        hf[p] = (T)H[p];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Neighbour-cell lists.  For leaf A, every leaf B (with periodic image) whose
+// bounding box lies closer to A's than max(h_A, h_B) -- the largest H of the
+// two cells -- may hold interacting pairs (ranges r < H_i of eq. (rho) and
+// r < max(H_i, H_j) of eq. (dvdt)).  Found by descending the octree from the
+// 27 top cells around A's top cell, pruning cells by box distance against
+// max(h_A, largest H in the subtree).
+// ---------------------------------------------------------------------------
+#define WALK_STACK 160
+
+__device__ inline double box_dist(const double* alo, const double* ahi, const double* blo, const double* bhi,
+                                  const double* s)
+{
+    double d2 = 0.0;
+    for (int a = 0; a < 3; a++) {
+        const double lo = blo[a] + s[a], hi = bhi[a] + s[a];
+        double g = 0.0;
+        if (lo > ahi[a]) g = lo - ahi[a];
+        else if (alo[a] > hi) g = alo[a] - hi;
+        d2 += g * g;
+    }
+    return sqrt(d2);
+}
+
+template <bool FILL>
+__global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restrict__ leaf_node, const Node* __restrict__ nodes,
+                                              const DomainInfo* __restrict__ di, const double* __restrict__ l_hlist,
+                                              int* counts, const int* __restrict__ l_off, ListEntry* __restrict__ list,
+                                              int list_cap, int* flags)
+{
+    const int A = blockIdx.x * blockDim.x + threadIdx.x;
+    if (A >= n_leaves) return;
+    const Node& NA = nodes[leaf_node[A]];
+    const DomainInfo& I = di[NA.domain];
+    const int loc = NA.top - I.top_offset;
+    const int tc[3] = {loc / (I.n_top[2] * I.n_top[1]), (loc / I.n_top[2]) % I.n_top[1], loc % I.n_top[2]};
+    const double hA = l_hlist[A];
+    const double ca[3] = {0.5 * (NA.lo[0] + NA.hi[0]), 0.5 * (NA.lo[1] + NA.hi[1]), 0.5 * (NA.lo[2] + NA.hi[2])};
+    int cnt = 0;
+    int out = FILL ? l_off[A] : 0;
+    const int out_end = FILL ? l_off[A + 1] : 0;
+    int stack[WALK_STACK];
+    for (int sx = -1; sx <= 1; sx++)
+    for (int sy = -1; sy <= 1; sy++)
+    for (int sz = -1; sz <= 1; sz++) {
+        const int o[3] = {sx, sy, sz};
+        int nc[3], ps[3];
+        double sv[3];
+        for (int a = 0; a < 3; a++) {
+            nc[a] = tc[a] + o[a];
+            ps[a] = 0;
+            if (nc[a] < 0) { nc[a] += I.n_top[a]; ps[a] = -1; }
+            else if (nc[a] >= I.n_top[a]) { nc[a] -= I.n_top[a]; ps[a] = 1; }
+            sv[a] = ps[a] * I.L[a];
+        }
+        const int code_shift = shift_index(ps[0], ps[1], ps[2]);
+        int sp = 0;
+        stack[sp++] = I.top_offset + (nc[0] * I.n_top[1] + nc[1]) * I.n_top[2] + nc[2];
+        while (sp > 0) {
+            const Node& nd = nodes[stack[--sp]];
+            if (nd.count == 0) continue;
+            const double d = box_dist(NA.lo, NA.hi, nd.lo, nd.hi, sv);
+            const double R = fmax(hA, nd.hmax) * (1.0 + 1e-12);
+            if (d >= R) continue;
+            if (nd.n_child == 0) {
+                if (FILL) {
+                    if (out < out_end && out < list_cap) {
+                        // sort direction: the one of 13 most aligned with the centre offset
+                        double cv[3];
+                        for (int a = 0; a < 3; a++) cv[a] = 0.5 * (nd.lo[a] + nd.hi[a]) + sv[a] - ca[a];
+                        int best = 0;
+                        double bv = -1.0;
+                        for (int k = 0; k < SPH_NDIR; k++) {
+                            double u[3];
+                            sph_dir(k, u);
+                            const double v = fabs(cv[0] * u[0] + cv[1] * u[1] + cv[2] * u[2]);
+                            if (v > bv) { bv = v; best = k; }
+                        }
+                        ListEntry e;
+                        e.B = nd.leaf;
+                        e.code = code_shift | (best << 8);
+                        e.dist = (float)d;
+                        e.pad = 0.f;
+                        list[out] = e;
+                    } else {
+                        atomicOr(flags, FLAG_INVALID);
+                    }
+                    out++;
+                }
+                cnt++;
+            } else {
+                if (sp + nd.n_child > WALK_STACK) {
+                    atomicOr(flags, FLAG_INVALID);
+                    continue;
+                }
+                for (int q = nd.n_child - 1; q >= 0; q--) stack[sp++] = nd.first_child + q;
+            }
+        }
+    }
+    if (!FILL) counts[A] = cnt;
+}
+
+// Largest H per cell, bottom-up over one level (leaves from particles,
+// internal cells from children).  One wave per cell.
+__global__ __launch_bounds__(256) void k_node_hmax(Node* nodes, int level_start, int n_level, const double* __restrict__ H,
+                                                   double* l_hlist)
+{
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (k >= n_level) return;
+    const int lane = threadIdx.x & 63;
+    Node& nd = nodes[level_start + k];
+    double hm = 0.0;
+    if (nd.n_child == 0) {
+        for (int p = nd.begin + lane; p < nd.begin + nd.count; p += 64) hm = fmax(hm, H[p]);
+    } else if (lane < nd.n_child) {
+        hm = nodes[nd.first_child + lane].hmax;
+    }
+    for (int off = 32; off > 0; off >>= 1) hm = fmax(hm, __shfl_xor(hm, off));
+    if (lane == 0) {
+        nd.hmax = hm;
+        if (nd.leaf >= 0) l_hlist[nd.leaf] = hm;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Sort stage: per leaf and direction, projections of the cell-relative
+// positions sorted ascending (bitonic network across the 64 lanes).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_sort_cells(int n_leaves, int64_t n, const int* __restrict__ l_begin,
+                                                    const int* __restrict__ l_count,
+                                                    const typename vec4<T>::type* __restrict__ pos4,
+                                                    float* __restrict__ skey, uint16_t* __restrict__ sidx, int* l_sorted)
+{
+    const int A = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (A >= n_leaves) return;
+    const int lane = threadIdx.x & 63;
+    const int b = l_begin[A], c = l_count[A];
+    if (c > 64) {
+        if (lane == 0) l_sorted[A] = 0;
+        return;
+    }
+    T px = 0, py = 0, pz = 0;
+    if (lane < c) {
+        const typename vec4<T>::type p = pos4[b + lane];
+        px = p.x; py = p.y; pz = p.z;
+    }
+    for (int d = 0; d < SPH_NDIR; d++) {
+        double u[3];
+        sph_dir(d, u);
+        float key = (lane < c) ? (float)((double)px * u[0] + (double)py * u[1] + (double)pz * u[2]) : INFINITY;
+        int idx = lane;
+        for (int k = 2; k <= 64; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const float pk = __shfl_xor(key, j);
+                const int pi = __shfl_xor(idx, j);
+                const bool up = (lane & k) == 0;
+                const bool lower = (lane & j) == 0;
+                const bool want_min = (lower == up);
+                const bool take = want_min ? (pk < key || (pk == key && pi < idx)) : (pk > key || (pk == key && pi > idx));
+                if (take) {
+                    key = pk;
+                    idx = pi;
+                }
+            }
+        }
+        if (lane < c) {
+            skey[(int64_t)d * n + b + lane] = key;
+            sidx[(int64_t)d * n + b + lane] = (uint16_t)idx;
+        }
+    }
+    if (lane == 0) l_sorted[A] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+static inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
+
+static sph_status read_int(sph_ctx* c, const int* dptr, int* out)
+{
+    SPH_CHECK_HIP(hipMemcpyAsync(out, dptr, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
+    return SPH_OK;
+}
+
+static sph_status permute_all(sph_ctx* c, const uint32_t* perm)
+{
+    const int64_t n = c->n;
+    SPH_TRY(buf_ensure(c->tmp, (size_t)n * 8));
+    double* arrs[] = {c->P.x, c->P.y, c->P.z, c->P.vx, c->P.vy, c->P.vz, c->P.u, c->P.m, c->P.H,
+                      c->P.rho, c->P.drho_dH, c->P.omega, c->P.P, c->P.ax, c->P.ay, c->P.az, c->P.dudt};
+    const int nb = blocks_for(n, 256);
+    for (double* a : arrs) {
+        if (!a) continue;
+        k_gather<double><<<nb, 256, 0, c->stream>>>(n, perm, a, (double*)c->tmp.p);
+        SPH_CHECK_LAUNCH();
+        SPH_CHECK_HIP(hipMemcpyAsync(a, c->tmp.p, (size_t)n * 8, hipMemcpyDeviceToDevice, c->stream));
+    }
+    if (c->P.id) {
+        k_gather<int64_t><<<nb, 256, 0, c->stream>>>(n, perm, c->P.id, (int64_t*)c->tmp.p);
+        SPH_CHECK_LAUNCH();
+        SPH_CHECK_HIP(hipMemcpyAsync(c->P.id, c->tmp.p, (size_t)n * 8, hipMemcpyDeviceToDevice, c->stream));
+    }
+    if (c->P.domain) {
+        k_gather<int32_t><<<nb, 256, 0, c->stream>>>(n, perm, c->P.domain, (int32_t*)c->tmp.p);
+        SPH_CHECK_LAUNCH();
+        SPH_CHECK_HIP(hipMemcpyAsync(c->P.domain, c->tmp.p, (size_t)n * 4, hipMemcpyDeviceToDevice, c->stream));
+    }
+    return SPH_OK;
+}
+
+// Task cost of a leaf (asymptotic model: particles of the cell times the
+// particles of every cell it interacts with) and the descending-cost order
+// in which the persistent kernels drain the leaves.
+__global__ __launch_bounds__(256) void k_leaf_cost(int n_leaves, const int* __restrict__ l_count,
+                                                   const int* __restrict__ l_off, const ListEntry* __restrict__ list,
+                                                   uint64_t* keys, uint32_t* vals)
+{
+    const int A = blockIdx.x * blockDim.x + threadIdx.x;
+    if (A >= n_leaves) return;
+    long long s = 0;
+    for (int e = l_off[A]; e < l_off[A + 1]; e++) s += l_count[list[e].B];
+    long long cost = (long long)l_count[A] * s;
+    const long long cmax = (1ll << 40) - 1;
+    if (cost > cmax) cost = cmax;
+    keys[A] = (uint64_t)(cmax - cost);
+    vals[A] = (uint32_t)A;
+}
+
+static sph_status task_order(sph_ctx* c)
+{
+    const int nL = c->n_leaves;
+    for (int q = 0; q < 2; q++) {
+        SPH_TRY(buf_ensure(c->okeys[q], (size_t)(nL + 1) * 8));
+        SPH_TRY(buf_ensure(c->ovals[q], (size_t)(nL + 1) * 4));
+    }
+    k_leaf_cost<<<blocks_for(nL, 256), 256, 0, c->stream>>>(nL, (const int*)c->l_count.p, (const int*)c->l_off.p,
+                                                          (const ListEntry*)c->list.p, (uint64_t*)c->okeys[0].p,
+                                                          (uint32_t*)c->ovals[0].p);
+    SPH_CHECK_LAUNCH();
+    int res = 0;
+    SPH_TRY(radix_sort(c, nL, 40, c->okeys, c->ovals, &res));
+    SPH_CHECK_HIP(hipMemcpyAsync(c->l_order.p, c->ovals[res].p, (size_t)nL * 4, hipMemcpyDeviceToDevice, c->stream));
+    return SPH_OK;
+}
+
+// Per-box range [begin, end) of the Morton-ordered particles.
+__global__ void k_domain_ranges(int ndom, const DomainInfo* __restrict__ di, const uint64_t* __restrict__ keys, int n,
+                                int D, int* ranges)
+{
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d > ndom) return;
+    if (d == ndom) {
+        ranges[d] = n;
+        return;
+    }
+    const uint64_t k = (uint64_t)di[d].top_offset << (3 * D);
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = lo + (hi - lo) / 2;
+        if (keys[mid] < k) lo = mid + 1;
+        else hi = mid;
+    }
+    ranges[d] = lo;
+}
+
+sph_status domain_ranges(sph_ctx* c)
+{
+    const int nd = c->prm.n_domains;
+    k_domain_ranges<<<blocks_for(nd + 1, 64), 64, 0, c->stream>>>(nd, (const DomainInfo*)c->dom_d.p,
+                                                                 (const uint64_t*)c->keys_sorted, (int)c->n, c->D,
+                                                                 (int*)c->dranges.p);
+    SPH_CHECK_LAUNCH();
+    return SPH_OK;
+}
+
+sph_status relist(sph_ctx* c)
+{
+    // largest H per cell, deepest level first
+    Node* nodes = (Node*)c->nodes.p;
+    for (int l = (int)c->level_off.size() - 2; l >= 0; l--) {
+        const int s = c->level_off[l], nl = c->level_off[l + 1] - s;
+        if (nl <= 0) continue;
+        k_node_hmax<<<blocks_for(nl, 4), 256, 0, c->stream>>>(nodes, s, nl, c->P.H, (double*)c->l_hlist.p);
+        SPH_CHECK_LAUNCH();
+    }
+    const int nL = c->n_leaves;
+    int* counts = (int*)c->l_off.p;
+    int* flags = (int*)c->flags.p;
+    SPH_CHECK_HIP(hipMemsetAsync(counts, 0, (size_t)(nL + 1) * sizeof(int), c->stream));
+    k_walk<false><<<blocks_for(nL, 128), 128, 0, c->stream>>>(nL, (const int*)c->leaf_node.p, nodes,
+                                                             (const DomainInfo*)c->dom_d.p, (const double*)c->l_hlist.p,
+                                                             counts, nullptr, nullptr, 0, flags);
+    SPH_CHECK_LAUNCH();
+    SPH_TRY(scan_exclusive(c, counts, counts, nL + 1, flags + FI_NLIST));
+    int total = 0;
+    SPH_TRY(read_int(c, flags + FI_NLIST, &total));
+    if (total < 0) return SPH_ERR_ALLOC;
+    SPH_TRY(buf_ensure(c->list, (size_t)std::max(total, 1) * sizeof(ListEntry)));
+    k_walk<true><<<blocks_for(nL, 128), 128, 0, c->stream>>>(nL, (const int*)c->leaf_node.p, nodes,
+                                                            (const DomainInfo*)c->dom_d.p, (const double*)c->l_hlist.p,
+                                                            nullptr, (const int*)c->l_off.p, (ListEntry*)c->list.p,
+                                                            total, flags);
+    SPH_CHECK_LAUNCH();
+    c->n_list = total;
+    c->n_pair_tasks = (total - nL) / 2;
+    return task_order(c);
+}
+
+sph_status build_all(sph_ctx* c)
+{
+    const int64_t n = c->n;
+    const int nd = c->prm.n_domains;
+    int* flags = (int*)c->flags.p;
+
+    // 1. validate, per-box H range
+    SPH_CHECK_HIP(hipMemsetAsync(flags, 0, FI_NFLAGS * sizeof(int), c->stream));
+    std::vector<unsigned long long> dstat_h(2 * nd);
+    for (int d = 0; d < nd; d++) {
+        dstat_h[2 * d] = 0ull;
+        double inf = INFINITY;
+        memcpy(&dstat_h[2 * d + 1], &inf, 8);
+    }
+    // box extents are needed for validation before the grid is known
+    c->dom_h.resize(nd);
+    for (int d = 0; d < nd; d++) {
+        DomainInfo& I = c->dom_h[d];
+        memset(&I, 0, sizeof(I));
+        for (int a = 0; a < 3; a++) I.L[a] = c->boxes[3 * d + a];
+    }
+    SPH_CHECK_HIP(hipMemcpyAsync(c->dom_d.p, c->dom_h.data(), nd * sizeof(DomainInfo), hipMemcpyHostToDevice, c->stream));
+    SPH_CHECK_HIP(hipMemcpyAsync(c->dstat.p, dstat_h.data(), 2 * nd * 8, hipMemcpyHostToDevice, c->stream));
+    k_validate<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->P.x, c->P.y, c->P.z, c->P.H, c->P.m, c->P.domain, nd,
+                                                        (const DomainInfo*)c->dom_d.p,
+                                                        (unsigned long long*)c->dstat.p, flags);
+    SPH_CHECK_LAUNCH();
+    int fl = 0;
+    SPH_CHECK_HIP(hipMemcpyAsync(dstat_h.data(), c->dstat.p, 2 * nd * 8, hipMemcpyDeviceToHost, c->stream));
+    SPH_TRY(read_int(c, flags, &fl));
+    if (fl & FLAG_INVALID) return SPH_ERR_INVALID;
+
+    // 2. top grids (edge >= largest H of the box, >= 3 cells per dimension)
+    int top = 0;
+    double min_ratio = INFINITY;
+    c->min_s0 = INFINITY;
+    for (int d = 0; d < nd; d++) {
+        double hmax, hmin;
+        memcpy(&hmax, &dstat_h[2 * d], 8);
+        memcpy(&hmin, &dstat_h[2 * d + 1], 8);
+        DomainInfo& I = c->dom_h[d];
+        if (dstat_h[2 * d] == 0ull) { hmax = 0.0; hmin = INFINITY; }  // empty box
+        for (int a = 0; a < 3; a++) {
+            int nt = (hmax > 0.0) ? (int)floor(I.L[a] / (hmax * (1.0 + 1e-12))) : 3;
+            if (nt < 3) return SPH_ERR_BOX_TOO_SMALL;
+            nt = std::min(nt, 128);
+            I.n_top[a] = nt;
+            I.s0[a] = I.L[a] / nt;
+            c->min_s0 = std::min(c->min_s0, I.s0[a]);
+            if (hmin > 0 && std::isfinite(hmin)) min_ratio = std::min(min_ratio, hmin / I.s0[a]);
+        }
+        I.top_offset = top;
+        top += I.n_top[0] * I.n_top[1] * I.n_top[2];
+    }
+    c->n_top_total = top;
+    int top_bits = 1;
+    while ((1ll << top_bits) < (long long)top) top_bits++;
+    int D = 1;
+    if (std::isfinite(min_ratio) && min_ratio > 0) D = (int)ceil(log2(1.0 / min_ratio)) + 3;
+    D = std::max(1, std::min(D, SPH_MAX_DEPTH));
+    D = std::min(D, (63 - top_bits) / 3);
+    c->D = D;
+    c->key_bits = top_bits + 3 * D;
+    SPH_CHECK_HIP(hipMemcpyAsync(c->dom_d.p, c->dom_h.data(), nd * sizeof(DomainInfo), hipMemcpyHostToDevice, c->stream));
+
+    // 3. Morton keys, radix sort, permutation of the caller's arrays
+    for (int q = 0; q < 2; q++) {
+        SPH_TRY(buf_ensure(c->keys[q], (size_t)n * 8));
+        SPH_TRY(buf_ensure(c->vals[q], (size_t)n * 4));
+    }
+    k_keys<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->P.x, c->P.y, c->P.z, c->P.domain,
+                                                    (const DomainInfo*)c->dom_d.p, D, (uint64_t*)c->keys[0].p,
+                                                    (uint32_t*)c->vals[0].p);
+    SPH_CHECK_LAUNCH();
+    int res = 0;
+    SPH_TRY(radix_sort(c, (int)n, c->key_bits, c->keys, c->vals, &res));
+    const uint64_t* keys = (const uint64_t*)c->keys[res].p;
+    c->keys_sorted = keys;
+    SPH_TRY(permute_all(c, (const uint32_t*)c->vals[res].p));
+    SPH_TRY(buf_ensure(c->dranges, (size_t)(nd + 1) * sizeof(int)));
+    SPH_TRY(domain_ranges(c));
+
+    // 4. octree, level by level
+    size_t cap = std::max<size_t>((size_t)top * 2 + 1024, (size_t)(n / 8) + 1024);
+    SPH_TRY(buf_ensure(c->nodes, cap * sizeof(Node)));
+    SPH_TRY(buf_ensure(c->nchild, (size_t)(top + 1) * sizeof(int)));
+    k_top_nodes<<<blocks_for(top, 256), 256, 0, c->stream>>>(top, nd, (const DomainInfo*)c->dom_d.p, keys, (int)n, D,
+                                                           (Node*)c->nodes.p);
+    SPH_CHECK_LAUNCH();
+    c->level_off.clear();
+    c->level_off.push_back(0);
+    int level_start = 0, n_level = top, n_nodes = top;
+    c->depth = 0;
+    for (int level = 0; level <= D; level++) {
+        SPH_TRY(buf_ensure(c->nchild, (size_t)(n_level + 1) * sizeof(int)));
+        int* nchild = (int*)c->nchild.p;
+        k_node_stats<<<n_level, 256, 0, c->stream>>>((Node*)c->nodes.p, level_start, keys, c->P.x, c->P.y, c->P.z,
+                                                     c->P.H, D, c->prm.n_split, nchild);
+        SPH_CHECK_LAUNCH();
+        SPH_TRY(scan_exclusive(c, nchild, nchild, n_level, flags + FI_NCHILD));
+        int total = 0;
+        SPH_TRY(read_int(c, flags + FI_NCHILD, &total));
+        c->level_off.push_back(n_nodes);
+        if (total == 0) break;
+        if ((size_t)(n_nodes + total) > cap) {
+            size_t ncap = std::max((size_t)(n_nodes + total) * 3 / 2, cap * 2);
+            DevBuf nb2;
+            SPH_TRY(buf_ensure(nb2, ncap * sizeof(Node)));
+            SPH_CHECK_HIP(hipMemcpyAsync(nb2.p, c->nodes.p, (size_t)n_nodes * sizeof(Node), hipMemcpyDeviceToDevice,
+                                         c->stream));
+            SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
+            buf_free(c->nodes);
+            c->nodes = nb2;
+            cap = ncap;
+        }
+        k_emit_children<<<n_level, 64, 0, c->stream>>>((Node*)c->nodes.p, level_start, n_level, nchild, n_nodes, keys, D);
+        SPH_CHECK_LAUNCH();
+        level_start = n_nodes;
+        n_level = total;
+        n_nodes += total;
+        c->depth = level + 1;
+    }
+    c->n_nodes = n_nodes;
+
+    // 5. leaves in Morton order
+    SPH_TRY(buf_ensure(c->leafmark, (size_t)(n + 1) * sizeof(int)));
+    SPH_CHECK_HIP(hipMemsetAsync(c->leafmark.p, 0, (size_t)(n + 1) * sizeof(int), c->stream));
+    k_mark_leaves<<<blocks_for(n_nodes, 256), 256, 0, c->stream>>>((const Node*)c->nodes.p, n_nodes, (int*)c->leafmark.p);
+    SPH_CHECK_LAUNCH();
+    SPH_TRY(buf_ensure(c->leafscan, (size_t)(n + 1) * sizeof(int)));
+    SPH_TRY(scan_exclusive(c, (const int*)c->leafmark.p, (int*)c->leafscan.p, (int)n, flags + FI_NLEAVES));
+    int nL = 0;
+    SPH_TRY(read_int(c, flags + FI_NLEAVES, &nL));
+    c->n_leaves = nL;
+    const size_t L1 = (size_t)nL + 1;
+    SPH_TRY(buf_ensure(c->leaf_node, L1 * 4));
+    SPH_TRY(buf_ensure(c->l_begin, L1 * 4));
+    SPH_TRY(buf_ensure(c->l_count, L1 * 4));
+    SPH_TRY(buf_ensure(c->l_origin, L1 * 24));
+    SPH_TRY(buf_ensure(c->l_lo, L1 * 24));
+    SPH_TRY(buf_ensure(c->l_hi, L1 * 24));
+    SPH_TRY(buf_ensure(c->l_hlist, L1 * 8));
+    SPH_TRY(buf_ensure(c->l_dom, L1 * 4));
+    SPH_TRY(buf_ensure(c->l_off, (L1 + 1) * 4));
+    SPH_TRY(buf_ensure(c->l_active, L1 * 4));
+    SPH_TRY(buf_ensure(c->l_sorted, L1 * 4));
+    SPH_TRY(buf_ensure(c->l_cost, L1 * 8));
+    SPH_TRY(buf_ensure(c->l_order, L1 * 4));
+    k_leaf_fill<<<blocks_for(n_nodes, 256), 256, 0, c->stream>>>(
+        (Node*)c->nodes.p, n_nodes, (const int*)c->leafscan.p, (int*)c->leaf_node.p, (int*)c->l_begin.p,
+        (int*)c->l_count.p, (double*)c->l_origin.p, (double*)c->l_lo.p, (double*)c->l_hi.p, (double*)c->l_hlist.p,
+        (int*)c->l_dom.p);
+    SPH_CHECK_LAUNCH();
+
+    // 6. cell-relative coordinates
+    const int es = c->elem_size();
+    SPH_TRY(buf_ensure(c->pos4, (size_t)n * 4 * es));
+    SPH_TRY(buf_ensure(c->fv4, (size_t)n * 4 * es));
+    SPH_TRY(buf_ensure(c->hf, (size_t)n * es));
+    if (c->prm.precision == SPH_FP64)
+        k_leaf_pos<double><<<blocks_for(nL, 4), 256, 0, c->stream>>>(
+            nL, (const int*)c->l_begin.p, (const int*)c->l_count.p, (const double*)c->l_origin.p, c->P.x, c->P.y,
+            c->P.z, c->P.m, c->P.H, (double4*)c->pos4.p, (double*)c->hf.p);
+    else
+        k_leaf_pos<float><<<blocks_for(nL, 4), 256, 0, c->stream>>>(
+            nL, (const int*)c->l_begin.p, (const int*)c->l_count.p, (const double*)c->l_origin.p, c->P.x, c->P.y,
+            c->P.z, c->P.m, c->P.H, (float4*)c->pos4.p, (float*)c->hf.p);
+    SPH_CHECK_LAUNCH();
+
+    // 7. neighbour-cell lists
+    SPH_TRY(relist(c));
+    SPH_TRY(read_int(c, flags, &fl));
+    if (fl & FLAG_INVALID) return SPH_ERR_INVALID;
+    c->built = true;
+    c->sorted = false;
+    return SPH_OK;
+}
+
+sph_status sort_all(sph_ctx* c)
+{
+    const int64_t n = c->n;
+    const int nL = c->n_leaves;
+    SPH_TRY(buf_ensure(c->skey, (size_t)n * SPH_NDIR * 4));
+    SPH_TRY(buf_ensure(c->sidx, (size_t)n * SPH_NDIR * 2));
+    if (c->prm.precision == SPH_FP64)
+        k_sort_cells<double><<<blocks_for(nL, 4), 256, 0, c->stream>>>(nL, n, (const int*)c->l_begin.p,
+                                                                     (const int*)c->l_count.p, (const double4*)c->pos4.p,
+                                                                     (float*)c->skey.p, (uint16_t*)c->sidx.p,
+                                                                     (int*)c->l_sorted.p);
+    else
+        k_sort_cells<float><<<blocks_for(nL, 4), 256, 0, c->stream>>>(nL, n, (const int*)c->l_begin.p,
+                                                                    (const int*)c->l_count.p, (const float4*)c->pos4.p,
+                                                                    (float*)c->skey.p, (uint16_t*)c->sidx.p,
+                                                                    (int*)c->l_sorted.p);
+    SPH_CHECK_LAUNCH();
+    c->sorted = true;
+    return SPH_OK;
+}

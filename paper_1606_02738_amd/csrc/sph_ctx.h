@@ -1,0 +1,105 @@
+// Host-side context of libsph_hip and the launch wrappers shared by the
+// translation units.  Not part of the C-ABI.
+#pragma once
+
+#include <vector>
+
+#include "sph_internal.h"
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+struct sph_ctx {
+    sph_params prm;
+    std::vector<double> boxes;   // n_domains x 3
+    hipStream_t stream = nullptr;
+
+    // bound particles
+    sph_particles P{};
+    bool bound = false;
+    int64_t n = 0;
+
+    // domains and key layout
+    std::vector<DomainInfo> dom_h;
+    int n_top_total = 0;
+    int D = 0;                   // octree levels encoded in the key
+    int key_bits = 0;
+    double min_s0 = 0;           // smallest top-cell edge over all boxes
+
+    // octree / leaves / lists
+    int n_nodes = 0, n_leaves = 0, depth = 0;
+    int64_t n_list = 0, n_pair_tasks = 0;
+    std::vector<int> level_off;  // node index of the first node of each level
+
+    // stage state
+    bool built = false, sorted = false, dens_done = false, ghost_done = false, force_done = false;
+    bool predicted = false;      // ghost/force use the predicted v, u of a step
+
+    // counters of the last calls
+    sph_stats st{};
+
+    // device buffers
+    DevBuf dom_d, dstat;          // DomainInfo[], per-domain (hmax, hmin) as u64 bits
+    DevBuf keys[2], vals[2];      // radix sort ping-pong
+    DevBuf okeys[2], ovals[2];    // task-order sort ping-pong
+    DevBuf dranges;               // per-box particle ranges [n_domains + 1]
+    const void* keys_sorted = nullptr;  // sorted Morton keys of the last build
+    DevBuf tmp;                   // permutation scratch (8 B per particle)
+    DevBuf nodes, nchild, coff;   // octree
+    DevBuf leafmark, leafscan;    // per particle
+    DevBuf leaf_node;             // leaf -> node
+    DevBuf l_begin, l_count, l_origin, l_lo, l_hi, l_hlist, l_dom, l_off, l_active, l_sorted, l_cnt, l_cost, l_order;
+    DevBuf list;
+    DevBuf pos4, fv4, hf;         // kernel-side particle data (T = float or double)
+    DevBuf skey, sidx;            // per-direction sorted projections
+    DevBuf hlo, hhi, conv;        // Newton brackets and converged flags
+    DevBuf vpx, vpy, vpz, upr;    // predicted v, u of a step
+    DevBuf flags, counters;       // device flags (int[64], see FI_*) and counters (int64)
+    DevBuf scan_tmp;              // scan block sums
+    DevBuf rs_hist;               // radix-sort digit histograms
+    DevBuf sums;                  // per-domain FP64 conservation partials
+    DevBuf dsum_part;
+
+    hipEvent_t ev[8] = {};
+
+    int elem_size() const { return prm.precision == SPH_FP64 ? 8 : 4; }
+};
+
+// buffer management (sph_api.hip)
+sph_status buf_ensure(DevBuf& b, size_t bytes);
+void buf_free(DevBuf& b);
+
+#define SPH_CHECK_HIP(expr)                                  \
+    do {                                                     \
+        hipError_t _e = (expr);                              \
+        if (_e != hipSuccess) return SPH_ERR_HIP;            \
+    } while (0)
+#define SPH_CHECK_LAUNCH() SPH_CHECK_HIP(hipGetLastError())
+#define SPH_TRY(expr)                                        \
+    do {                                                     \
+        sph_status _s = (expr);                              \
+        if (_s != SPH_OK) return _s;                         \
+    } while (0)
+
+// primitives (sph_prims.hip)
+// Exclusive scan of n int32 values (in may equal out); *d_total (device) = sum.
+sph_status scan_exclusive(sph_ctx* c, const int* in, int* out, int n, int* d_total);
+// Stable LSD radix sort of (key, value) pairs on the low `bits` bits between
+// the ping-pong buffers kb[0..1] / vb[0..1] (input in [0]); the sorted data
+// ends in kb[res]/vb[res], res returned through *res_idx.
+sph_status radix_sort(sph_ctx* c, int n, int bits, DevBuf* kb, DevBuf* vb, int* res_idx);
+
+// build stages (sph_build.hip)
+sph_status build_all(sph_ctx* c);
+sph_status sort_all(sph_ctx* c);
+sph_status relist(sph_ctx* c);
+sph_status domain_ranges(sph_ctx* c);
+
+// interaction stages (sph_interact.hip)
+sph_status density_all(sph_ctx* c);
+sph_status ghost_all(sph_ctx* c);
+sph_status force_all(sph_ctx* c);
+sph_status step_all(sph_ctx* c, double dt);
+sph_status domain_sums(sph_ctx* c, double* host_out);

@@ -1,0 +1,948 @@
+// Density, ghost, force and integrator stages on the leaf cells.
+//
+// Work unit: one wave (64 lanes) per leaf cell A.  Lanes hold up to 64 of
+// A's particles (i); when A holds fewer than 64 the wave is split into G
+// groups of CI = 64/G lanes and group g walks every G-th neighbour of the
+// staged tile, so all lanes stay busy.  A's neighbour-cell list gives the
+// cells B; for each, the part of B that can be within range along the pair's
+// sort direction (a window of B's sorted projections) is staged in LDS and
+// streamed through.  Coordinates are cell-relative: each particle is stored
+// relative to its leaf's centre, and the offset between two leaves (with the
+// periodic image) is formed in FP64 once per pair of cells.
+#include <math.h>
+
+#include <algorithm>
+
+#include "sph_ctx.h"
+
+#define WAVES_PER_WG 4
+#define INV_PI_8 2.5464790894703255  // 8/pi: cubic-spline normalisation in 3D
+
+// ---------------------------------------------------------------------------
+// Kernel shape, Sec. 2 (cubic spline with compact support H):
+//   w(q)  = 1 - 6q^2 + 6q^3 (q <= 1/2),  2(1-q)^3 (1/2 < q < 1)
+//   w'(q) = q(18q - 12)     (q <= 1/2), -6(1-q)^2 (1/2 < q < 1)
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline void spline_w_dw(T q, T& w, T& dw)
+{
+    const T t = T(1) - q;
+    if (q <= T(0.5)) {
+        w = T(1) + q * q * (T(6) * q - T(6));
+        dw = q * (T(18) * q - T(12));
+    } else {
+        w = T(2) * t * t * t;
+        dw = T(-6) * t * t;
+    }
+}
+
+template <typename T>
+__device__ inline T spline_dw(T q)
+{
+    const T t = T(1) - q;
+    T v = (q <= T(0.5)) ? q * (T(18) * q - T(12)) : T(-6) * t * t;
+    return (q < T(1)) ? v : T(0);
+}
+
+// Compensated (Kahan) accumulation; COMP = false gives the plain sum.
+template <typename T, bool COMP>
+struct Acc {
+    T s = 0, c = 0;
+    __device__ inline void add(T v)
+    {
+        if (COMP) {
+            const T y = v - c;
+            const T t = s + y;
+            c = (t - s) - y;
+            s = t;
+        } else {
+            s += v;
+        }
+    }
+    __device__ inline double total() const { return COMP ? (double)s - (double)c : (double)s; }
+};
+
+__device__ inline double wave_max(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    return v;
+}
+__device__ inline float wave_minf(float v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off));
+    return v;
+}
+__device__ inline float wave_maxf(float v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+    return v;
+}
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline void shift_vec(int code, const DomainInfo& I, double* s)
+{
+    const int sh = code & 255;
+    s[0] = (sh / 9 - 1) * I.L[0];
+    s[1] = ((sh / 3) % 3 - 1) * I.L[1];
+    s[2] = (sh % 3 - 1) * I.L[2];
+}
+
+// lanes per i-group for a chunk of nc particles: 8, 16, 32 or 64
+__device__ inline int chunk_log2(int nc) { return nc <= 8 ? 3 : (nc <= 16 ? 4 : (nc <= 32 ? 5 : 6)); }
+
+// Window [lo, hi) of B's particles (in the pair's sorted order) whose
+// projection lies in [kmin, kmax).  Returns false if B is not sorted.
+__device__ inline bool sorted_window(const float* skey, int64_t n, int dir, int bB, int nB, int lane, float kmin,
+                                     float kmax, int& lo, int& hi)
+{
+    const float kb = (lane < nB) ? skey[(int64_t)dir * n + bB + lane] : INFINITY;
+    lo = __popcll(__ballot(lane < nB && kb < kmin));
+    hi = __popcll(__ballot(lane < nB && kb < kmax));
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Density sweep + FP64 Newton step (eq. (rho); the smoothing-length
+// constraint rho H^3 = C with its derivative 3 H^2 rho Omega).
+// ---------------------------------------------------------------------------
+struct DensArgs {
+    int n_leaves;
+    int64_t n;
+    const int* l_begin;
+    const int* l_count;
+    const double* l_origin;
+    const double* l_hlist;
+    const int* l_dom;
+    const int* l_off;
+    const ListEntry* list;
+    int* l_active;
+    const int* l_sorted;
+    const void* pos4;
+    const float* skey;
+    const uint16_t* sidx;
+    const DomainInfo* di;
+    const double* m;
+    double* H;
+    double* rho;
+    double* drho;
+    double* hlo;
+    double* hhi;
+    uint8_t* conv;
+    int32_t* nngb;
+    double C_fac;
+    double h_tol;
+    int* flags;
+    unsigned long long* counters;
+    const int* order;   // task order (persistent mode), may be NULL
+    int persistent;
+};
+
+template <typename T, bool COMP>
+__device__ void density_leaf(const DensArgs& a, int A, typename vec4<T>::type* tile, int lane)
+{
+    typedef typename vec4<T>::type V4;
+    const V4* pos4 = (const V4*)a.pos4;
+    const int bA = a.l_begin[A], nA = a.l_count[A];
+    const double oA[3] = {a.l_origin[3 * A], a.l_origin[3 * A + 1], a.l_origin[3 * A + 2]};
+    const DomainInfo& I = a.di[a.l_dom[A]];
+    const double hlim = fmin(fmin(I.L[0], I.L[1]), I.L[2]) / 3.0;
+    const double s0min = fmin(fmin(I.s0[0], I.s0[1]), I.s0[2]);
+    const int e0 = a.l_off[A], e1 = a.l_off[A + 1];
+    bool any_left = false;
+    for (int c0 = 0; c0 < nA; c0 += 64) {
+        const int nc = min(64, nA - c0);
+        const int lg = chunk_log2(nc);
+        const int CI = 1 << lg, G = 64 >> lg;
+        const int ii = lane & (CI - 1), jg = lane >> lg;
+        const bool vi = ii < nc;
+        const int i = bA + c0 + (vi ? ii : 0);
+        const bool act = vi && !a.conv[i];
+        if (__ballot(act) == 0) continue;
+        const V4 pi = pos4[i];
+        const double Hd = a.H[i];
+        const T Hi = (T)Hd, H2 = Hi * Hi, invH = T(1) / Hi;
+        Acc<T, COMP> sw, sd;
+        int cnt = 0;
+        const double hA = wave_max(act ? Hd : 0.0);
+        for (int e = e0; e < e1; e++) {
+            const ListEntry E = a.list[e];
+            if ((double)E.dist > hA * (1.0 + 1e-6)) continue;
+            const int B = E.B, dir = E.code >> 8;
+            const int bB = a.l_begin[B], nB = a.l_count[B];
+            double sv[3];
+            shift_vec(E.code, I, sv);
+            const T dox = (T)(a.l_origin[3 * B] + sv[0] - oA[0]);
+            const T doy = (T)(a.l_origin[3 * B + 1] + sv[1] - oA[1]);
+            const T doz = (T)(a.l_origin[3 * B + 2] + sv[2] - oA[2]);
+            const T xi = pi.x - dox, yi = pi.y - doy, zi = pi.z - doz;  // i in B's frame
+            int lo = 0, hi = nB;
+            const bool srt = a.l_sorted[B] && nB <= 64;
+            if (srt) {
+                double u[3];
+                sph_dir(dir, u);
+                const float ki = (float)((double)xi * u[0] + (double)yi * u[1] + (double)zi * u[2]);
+                float kmin = wave_minf(act ? ki - (float)Hd : INFINITY);
+                float kmax = wave_maxf(act ? ki + (float)Hd : -INFINITY);
+                const float eps = 1e-5f * (fabsf(kmin) + fabsf(kmax)) + 1e-6f * (float)hA;
+                sorted_window(a.skey, a.n, dir, bB, nB, lane, kmin - eps, kmax + eps, lo, hi);
+            }
+            for (int p0 = lo; p0 < hi; p0 += 64) {
+                const int len = min(64, hi - p0);
+                if (lane < len) {
+                    const int t = p0 + lane;
+                    const int jl = srt ? (int)a.sidx[(int64_t)dir * a.n + bB + t] : t;
+                    tile[lane] = pos4[bB + jl];
+                }
+                wave_sync();
+                for (int t = jg; t < len; t += G) {
+                    const V4 pj = tile[t];
+                    const T dx = pj.x - xi, dy = pj.y - yi, dz = pj.z - zi;
+                    const T r2 = dx * dx + dy * dy + dz * dz;
+                    if (act && r2 < H2) {
+                        const T q = sqrt(r2) * invH;
+                        T w, dw;
+                        spline_w_dw(q, w, dw);
+                        sw.add(pj.w * w);
+                        sd.add(pj.w * (T(3) * w + q * dw));
+                        cnt++;
+                    }
+                }
+                wave_sync();
+            }
+        }
+        double Sw = sw.total(), Sd = sd.total();
+        for (int off = CI; off < 64; off <<= 1) {
+            Sw += __shfl_xor(Sw, off);
+            Sd += __shfl_xor(Sd, off);
+            cnt += __shfl_xor(cnt, off);
+        }
+        bool left = false;
+        if (jg == 0 && act) {
+            const double H = Hd;
+            const double rho = INV_PI_8 / (H * H * H) * Sw;
+            const double drho = -INV_PI_8 / (H * H * H * H) * Sd;
+            const double C = a.C_fac * a.m[i];
+            const double f = INV_PI_8 * Sw - C;              // rho H^3 - C
+            const double fp = INV_PI_8 * (3.0 * Sw - Sd) / H; // 3 H^2 rho + H^3 drho/dH
+            a.rho[i] = rho;
+            a.drho[i] = drho;
+            if (a.nngb) a.nngb[i] = cnt;
+            bool done = fabs(f) <= a.h_tol * C;
+            if (!done) {
+                double lo = a.hlo[i], hi = a.hhi[i];
+                if (f < 0.0) lo = H;
+                else hi = H;
+                if (f < 0.0 && H >= hlim) {
+                    atomicOr(a.flags, FLAG_BOX_SMALL);
+                    done = true;
+                } else {
+                    double Hn = H - f / fp;
+                    if (!(Hn > lo && Hn < hi) || !isfinite(Hn)) Hn = isinf(hi) ? 2.0 * H : 0.5 * (lo + hi);
+                    if (Hn > hlim) Hn = hlim;
+                    if (fabs(Hn - H) <= 4.0 * 2.220446049250313e-16 * H) {
+                        done = true;  // stalled at round-off: accept H
+                    } else {
+                        a.H[i] = Hn;
+                        a.hlo[i] = lo;
+                        a.hhi[i] = hi;
+                        if (Hn > a.l_hlist[A]) atomicOr(a.flags, FLAG_RELIST);
+                        if (Hn > s0min) atomicOr(a.flags, FLAG_REBUILD);
+                        left = true;
+                    }
+                }
+            }
+            if (done) {
+                a.conv[i] = 1;
+                atomicAdd(&a.counters[CNT_NDENS], (unsigned long long)cnt);
+            }
+        }
+        const unsigned long long lm = __ballot(left);
+        if (lm) {
+            any_left = true;
+            if (lane == 0) atomicAdd(&a.counters[CNT_UNCONV], (unsigned long long)__popcll(lm));
+        }
+    }
+    if (lane == 0) a.l_active[A] = any_left ? 1 : 0;
+}
+
+template <typename T, bool COMP>
+__global__ __launch_bounds__(256) void k_density(DensArgs a)
+{
+    typedef typename vec4<T>::type V4;
+    __shared__ V4 tiles[WAVES_PER_WG][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (!a.persistent) {
+        const int A = blockIdx.x * WAVES_PER_WG + w;
+        if (A >= a.n_leaves) return;
+        if (!a.l_active[A]) return;
+        density_leaf<T, COMP>(a, A, tiles[w], lane);
+        return;
+    }
+    // persistent: waves pop leaves from a cost-ordered queue
+    for (;;) {
+        int t = 0;
+        if (lane == 0) t = (int)atomicAdd(&a.counters[CNT_QUEUE], 1ull);
+        t = __shfl(t, 0);
+        if (t >= a.n_leaves) break;
+        const int A = a.order ? a.order[t] : t;
+        if (a.l_active[A]) density_leaf<T, COMP>(a, A, tiles[w], lane);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_density_reset(int64_t n, int n_leaves, double* hlo, double* hhi, uint8_t* conv,
+                                                       int* l_active)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        hlo[i] = 0.0;
+        hhi[i] = INFINITY;
+        conv[i] = 0;
+    }
+    if (i < n_leaves) l_active[i] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// Ghost: Omega = 1 + H/(3 rho) drho/dH, P = (gamma-1) rho u, A = P/(Omega rho^2)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_ghost(int64_t n, const double* __restrict__ rho, const double* __restrict__ drho,
+                                               const double* __restrict__ H, const double* __restrict__ u,
+                                               const double* __restrict__ vx, const double* __restrict__ vy,
+                                               const double* __restrict__ vz, double gamma, double* omega, double* P,
+                                               typename vec4<T>::type* fv4, T* hf)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double r = rho[i], h = H[i];
+    const double om = 1.0 + h / (3.0 * r) * drho[i];
+    const double p = (gamma - 1.0) * r * u[i];
+    const double A = p / (om * r * r);
+    if (omega) omega[i] = om;
+    if (P) P[i] = p;
+    typename vec4<T>::type f;
+    f.x = (T)vx[i];
+    f.y = (T)vy[i];
+    f.z = (T)vz[i];
+    f.w = (T)A;
+    fv4[i] = f;
+    hf[i] = (T)h;
+}
+
+// ---------------------------------------------------------------------------
+// Force, eqs. (dvdt) and (dudt), symmetric: every unordered pair once.
+// Pair cells (A,B) with B > A: i-side sums in registers, j-side sums in LDS
+// (lane-rotated so that lanes of a group touch distinct j), flushed with one
+// atomic add per j and quantity.  Self cells: triangular sweep.
+// ---------------------------------------------------------------------------
+struct ForceArgs {
+    int n_leaves;
+    int64_t n;
+    const int* l_begin;
+    const int* l_count;
+    const double* l_origin;
+    const double* l_hlist;
+    const int* l_dom;
+    const int* l_off;
+    const ListEntry* list;
+    const int* l_sorted;
+    const void* pos4;
+    const void* fv4;
+    const void* hf;
+    const float* skey;
+    const uint16_t* sidx;
+    const DomainInfo* di;
+    double* ax;
+    double* ay;
+    double* az;
+    double* dudt;
+    unsigned long long* counters;
+    const int* order;
+    int persistent;
+};
+
+template <typename T>
+struct FTile {
+    typename vec4<T>::type p[64];  // x, y, z (B frame), m
+    typename vec4<T>::type v[64];  // vx, vy, vz, k = A (8/pi) / H^4
+    T h2[64];                      // H^2
+    T ih[64];                      // 1/H
+    T acc[4][64];                  // j-side sums
+    int jl[64];                    // local index in B
+};
+
+template <typename T, bool COMP>
+struct FAcc {
+    Acc<T, COMP> ax, ay, az, du;
+};
+
+// One pair (i, j), d = x_i - x_j.  Returns true if within max(H_i, H_j).
+template <typename T, bool COMP, bool JSIDE>
+__device__ inline bool force_pair(T dx, T dy, T dz, T mi, T h2i, T ihi, T ki, T vxi, T vyi, T vzi,
+                                  const typename vec4<T>::type& pj, const typename vec4<T>::type& fj, T h2j, T ihj,
+                                  FAcc<T, COMP>& ai, T* accj, int o)
+{
+    const T r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 < fmax(h2i, h2j)) || !(r2 > T(0))) return false;
+    const T ir = T(1) / sqrt(r2);
+    const T r = r2 * ir;
+    const T Fi = ki * spline_dw(r * ihi);      // A_i dW/dr(r, H_i)
+    const T Fj = fj.w * spline_dw(r * ihj);    // A_j dW/dr(r, H_j)
+    const T F = (Fi + Fj) * ir;
+    const T dvdr = ((vxi - fj.x) * dx + (vyi - fj.y) * dy + (vzi - fj.z) * dz) * ir;
+    const T mjF = pj.w * F;
+    ai.ax.add(-mjF * dx);
+    ai.ay.add(-mjF * dy);
+    ai.az.add(-mjF * dz);
+    ai.du.add(pj.w * Fi * dvdr);
+    if (JSIDE) {
+        const T miF = mi * F;
+        atomicAdd(&accj[0 * 64 + o], miF * dx);
+        atomicAdd(&accj[1 * 64 + o], miF * dy);
+        atomicAdd(&accj[2 * 64 + o], miF * dz);
+        atomicAdd(&accj[3 * 64 + o], mi * Fj * dvdr);
+    }
+    return true;
+}
+
+template <typename T>
+__device__ inline void stage_force_j(FTile<T>& tl, int slot, int p, const typename vec4<T>::type* pos4,
+                                     const typename vec4<T>::type* fv4, const T* hf, int jl)
+{
+    const T h = hf[p];
+    const T ih = T(1) / h;
+    typename vec4<T>::type f = fv4[p];
+    f.w = f.w * T(INV_PI_8) * ih * ih * ih * ih;
+    tl.p[slot] = pos4[p];
+    tl.v[slot] = f;
+    tl.h2[slot] = h * h;
+    tl.ih[slot] = ih;
+    tl.acc[0][slot] = 0;
+    tl.acc[1][slot] = 0;
+    tl.acc[2][slot] = 0;
+    tl.acc[3][slot] = 0;
+    tl.jl[slot] = jl;
+}
+
+template <typename T, bool COMP>
+__device__ void force_leaf(const ForceArgs& a, int A, FTile<T>& tl, int lane)
+{
+    typedef typename vec4<T>::type V4;
+    const V4* pos4 = (const V4*)a.pos4;
+    const V4* fv4 = (const V4*)a.fv4;
+    const T* hf = (const T*)a.hf;
+    const int bA = a.l_begin[A], nA = a.l_count[A];
+    const double oA[3] = {a.l_origin[3 * A], a.l_origin[3 * A + 1], a.l_origin[3 * A + 2]};
+    const DomainInfo& I = a.di[a.l_dom[A]];
+    const int e0 = a.l_off[A], e1 = a.l_off[A + 1];
+    unsigned long long npairs = 0;
+    for (int c0 = 0; c0 < nA; c0 += 64) {
+        const int nc = min(64, nA - c0);
+        const int lg = chunk_log2(nc);
+        const int CI = 1 << lg, G = 64 >> lg;
+        const int ii = lane & (CI - 1), jg = lane >> lg;
+        const bool vi = ii < nc;
+        const int i = bA + c0 + (vi ? ii : 0);
+        const V4 pi = pos4[i];
+        V4 fi = fv4[i];
+        const T Hi = hf[i];
+        const T h2i = Hi * Hi, ihi = T(1) / Hi;
+        const T ki = fi.w * T(INV_PI_8) * ihi * ihi * ihi * ihi;
+        FAcc<T, COMP> ai;
+        const double hA = wave_max(vi ? (double)Hi : 0.0);
+        for (int e = e0; e < e1; e++) {
+            const ListEntry E = a.list[e];
+            const int B = E.B;
+            if (B < A) continue;
+            const int bB = a.l_begin[B], nB = a.l_count[B];
+            if (B == A) {
+                if (nA <= 64) {
+                    // triangular sweep over the unordered pairs of the cell
+                    if (lane < nA) stage_force_j<T>(tl, lane, bA + lane, pos4, fv4, hf, lane);
+                    wave_sync();
+                    const int steps = nA / 2;  // pair distances 1..floor(n/2)
+                    const bool even = (nA & 1) == 0;
+                    for (int t = jg; t < steps; t += G) {
+                        int b = ii + 1 + t;
+                        if (b >= nA) b -= nA;
+                        const bool ok = vi && !(even && t == steps - 1 && ii >= nA / 2);
+                        if (ok) {
+                            const V4 pj = tl.p[b];
+                            const T dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+                            if (force_pair<T, COMP, true>(dx, dy, dz, pi.w, h2i, ihi, ki, fi.x, fi.y, fi.z, pj, tl.v[b],
+                                                          tl.h2[b], tl.ih[b], ai, &tl.acc[0][0], b))
+                                npairs++;
+                        }
+                    }
+                    wave_sync();
+                    if (jg == 0 && vi) {
+                        ai.ax.add(tl.acc[0][ii]);
+                        ai.ay.add(tl.acc[1][ii]);
+                        ai.az.add(tl.acc[2][ii]);
+                        ai.du.add(tl.acc[3][ii]);
+                    }
+                    wave_sync();
+                } else {
+                    // large cell: gather over all j != i of the cell (i side only)
+                    for (int p0 = 0; p0 < nA; p0 += 64) {
+                        const int len = min(64, nA - p0);
+                        if (lane < len) stage_force_j<T>(tl, lane, bA + p0 + lane, pos4, fv4, hf, p0 + lane);
+                        wave_sync();
+                        for (int t = jg; t < len; t += G) {
+                            if (!vi || p0 + t == c0 + ii) continue;
+                            const V4 pj = tl.p[t];
+                            const T dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+                            if (force_pair<T, COMP, false>(dx, dy, dz, pi.w, h2i, ihi, ki, fi.x, fi.y, fi.z, pj,
+                                                           tl.v[t], tl.h2[t], tl.ih[t], ai, nullptr, t))
+                                if (p0 + t > c0 + ii) npairs++;
+                        }
+                        wave_sync();
+                    }
+                }
+                continue;
+            }
+            const double R = fmax(hA, a.l_hlist[B]);
+            if ((double)E.dist > R * (1.0 + 1e-6)) continue;
+            double sv[3];
+            shift_vec(E.code, I, sv);
+            const T dox = (T)(a.l_origin[3 * B] + sv[0] - oA[0]);
+            const T doy = (T)(a.l_origin[3 * B + 1] + sv[1] - oA[1]);
+            const T doz = (T)(a.l_origin[3 * B + 2] + sv[2] - oA[2]);
+            const T xi = pi.x - dox, yi = pi.y - doy, zi = pi.z - doz;
+            const int dir = E.code >> 8;
+            int lo = 0, hi = nB;
+            const bool srt = a.l_sorted[B] && nB <= 64;
+            if (srt) {
+                double u[3];
+                sph_dir(dir, u);
+                const float ki_ = (float)((double)xi * u[0] + (double)yi * u[1] + (double)zi * u[2]);
+                const float Rf = (float)R;
+                float kmin = wave_minf(vi ? ki_ - Rf : INFINITY);
+                float kmax = wave_maxf(vi ? ki_ + Rf : -INFINITY);
+                const float eps = 1e-5f * (fabsf(kmin) + fabsf(kmax)) + 1e-6f * Rf;
+                sorted_window(a.skey, a.n, dir, bB, nB, lane, kmin - eps, kmax + eps, lo, hi);
+            }
+            for (int p0 = lo; p0 < hi; p0 += 64) {
+                const int len = min(64, hi - p0);
+                if (lane < len) {
+                    const int t = p0 + lane;
+                    const int jl = srt ? (int)a.sidx[(int64_t)dir * a.n + bB + t] : t;
+                    stage_force_j<T>(tl, lane, bB + jl, pos4, fv4, hf, jl);
+                }
+                wave_sync();
+                // group jg owns slots jg, jg+G, ...; lanes of a group rotate over them
+                const int Lg = (jg < len) ? (len - jg + G - 1) / G : 0;
+                const int Lmax = (len + G - 1) / G;
+                const int s0 = (Lg > 0) ? ii % Lg : 0;
+                for (int t = 0; t < Lmax; t++) {
+                    if (vi && t < Lg) {
+                        int s = s0 + t;
+                        if (s >= Lg) s -= Lg;
+                        const int o = jg + G * s;
+                        const V4 pj = tl.p[o];
+                        const T dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
+                        if (force_pair<T, COMP, true>(dx, dy, dz, pi.w, h2i, ihi, ki, fi.x, fi.y, fi.z, pj, tl.v[o],
+                                                      tl.h2[o], tl.ih[o], ai, &tl.acc[0][0], o))
+                            npairs++;
+                    }
+                }
+                wave_sync();
+                if (lane < len) {
+                    const int p = bB + tl.jl[lane];
+                    const T gx = tl.acc[0][lane], gy = tl.acc[1][lane], gz = tl.acc[2][lane], gu = tl.acc[3][lane];
+                    if (gx != T(0) || gy != T(0) || gz != T(0) || gu != T(0)) {
+                        atomicAdd(&a.ax[p], (double)gx);
+                        atomicAdd(&a.ay[p], (double)gy);
+                        atomicAdd(&a.az[p], (double)gz);
+                        atomicAdd(&a.dudt[p], (double)gu);
+                    }
+                }
+                wave_sync();
+            }
+        }
+        double sx = ai.ax.total(), sy = ai.ay.total(), sz = ai.az.total(), su = ai.du.total();
+        for (int off = CI; off < 64; off <<= 1) {
+            sx += __shfl_xor(sx, off);
+            sy += __shfl_xor(sy, off);
+            sz += __shfl_xor(sz, off);
+            su += __shfl_xor(su, off);
+        }
+        if (jg == 0 && vi) {
+            atomicAdd(&a.ax[i], sx);
+            atomicAdd(&a.ay[i], sy);
+            atomicAdd(&a.az[i], sz);
+            atomicAdd(&a.dudt[i], su);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) npairs += __shfl_xor(npairs, off);
+    if (lane == 0 && npairs) atomicAdd(&a.counters[CNT_NFORCE], npairs);
+}
+
+template <typename T, bool COMP>
+__global__ __launch_bounds__(256) void k_force(ForceArgs a)
+{
+    __shared__ FTile<T> tiles[WAVES_PER_WG];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (!a.persistent) {
+        const int A = blockIdx.x * WAVES_PER_WG + w;
+        if (A >= a.n_leaves) return;
+        force_leaf<T, COMP>(a, A, tiles[w], lane);
+        return;
+    }
+    for (;;) {
+        int t = 0;
+        if (lane == 0) t = (int)atomicAdd(&a.counters[CNT_QUEUE2], 1ull);
+        t = __shfl(t, 0);
+        if (t >= a.n_leaves) break;
+        force_leaf<T, COMP>(a, a.order ? a.order[t] : t, tiles[w], lane);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Integrator (kick-drift-kick) and FP64 conservation sums.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_kick_drift(int64_t n, double* x, double* y, double* z, double* vx, double* vy,
+                                                    double* vz, double* u, const double* __restrict__ ax,
+                                                    const double* __restrict__ ay, const double* __restrict__ az,
+                                                    const double* __restrict__ dudt, const int32_t* __restrict__ dom,
+                                                    const DomainInfo* __restrict__ di, double dt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double h = 0.5 * dt;
+    const double v[3] = {vx[i] + ax[i] * h, vy[i] + ay[i] * h, vz[i] + az[i] * h};
+    vx[i] = v[0];
+    vy[i] = v[1];
+    vz[i] = v[2];
+    u[i] += dudt[i] * h;
+    const DomainInfo& I = di[dom ? dom[i] : 0];
+    double* c[3] = {x, y, z};
+    for (int a = 0; a < 3; a++) {
+        double q = c[a][i] + v[a] * dt;
+        q -= I.L[a] * floor(q / I.L[a]);
+        if (q >= I.L[a]) q -= I.L[a];
+        if (q < 0.0) q = 0.0;
+        c[a][i] = q;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_predict(int64_t n, const double* __restrict__ vx, const double* __restrict__ vy,
+                                                 const double* __restrict__ vz, const double* __restrict__ u,
+                                                 const double* __restrict__ ax, const double* __restrict__ ay,
+                                                 const double* __restrict__ az, const double* __restrict__ dudt,
+                                                 double dt, double* vpx, double* vpy, double* vpz, double* upr)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double h = 0.5 * dt;
+    vpx[i] = vx[i] + ax[i] * h;
+    vpy[i] = vy[i] + ay[i] * h;
+    vpz[i] = vz[i] + az[i] * h;
+    upr[i] = u[i] + dudt[i] * h;
+}
+
+__global__ __launch_bounds__(256) void k_kick(int64_t n, double* vx, double* vy, double* vz, double* u,
+                                              const double* __restrict__ ax, const double* __restrict__ ay,
+                                              const double* __restrict__ az, const double* __restrict__ dudt, double dt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double h = 0.5 * dt;
+    vx[i] += ax[i] * h;
+    vy[i] += ay[i] * h;
+    vz[i] += az[i] * h;
+    u[i] += dudt[i] * h;
+}
+
+#define SUM_CHUNKS 64
+// partial[(d * SUM_CHUNKS + chunk) * 5 + k]
+__global__ __launch_bounds__(256) void k_sums_partial(const int* __restrict__ ranges, const double* __restrict__ m,
+                                                      const double* __restrict__ vx, const double* __restrict__ vy,
+                                                      const double* __restrict__ vz, const double* __restrict__ u,
+                                                      double* partial)
+{
+    __shared__ double red[5][256];
+    const int d = blockIdx.y, ch = blockIdx.x, tid = threadIdx.x;
+    const int b = ranges[d], e = ranges[d + 1];
+    double s[5] = {0, 0, 0, 0, 0};
+    for (int64_t i = b + (int64_t)ch * 256 + tid; i < e; i += (int64_t)SUM_CHUNKS * 256) {
+        const double mm = m[i], v0 = vx[i], v1 = vy[i], v2 = vz[i];
+        s[0] += mm;
+        s[1] += mm * v0;
+        s[2] += mm * v1;
+        s[3] += mm * v2;
+        s[4] += mm * (0.5 * (v0 * v0 + v1 * v1 + v2 * v2) + u[i]);
+    }
+    for (int k = 0; k < 5; k++) red[k][tid] = s[k];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (tid < st)
+            for (int k = 0; k < 5; k++) red[k][tid] += red[k][tid + st];
+        __syncthreads();
+    }
+    if (tid < 5) partial[((int64_t)d * SUM_CHUNKS + ch) * 5 + tid] = red[tid][0];
+}
+
+__global__ void k_sums_final(int ndom, const double* __restrict__ partial, double* out)
+{
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= ndom) return;
+    for (int k = 0; k < 5; k++) {
+        double s = 0.0;
+        for (int ch = 0; ch < SUM_CHUNKS; ch++) s += partial[((int64_t)d * SUM_CHUNKS + ch) * 5 + k];
+        out[5 * d + k] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host orchestration
+// ---------------------------------------------------------------------------
+static inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
+
+static int resident_wgs(sph_ctx* c)
+{
+    if (c->prm.persistent_wgs > 0) return c->prm.persistent_wgs;
+    return 256 * 8;  // 256 CUs x 8 workgroups of 4 waves
+}
+
+static sph_status launch_density(sph_ctx* c)
+{
+    DensArgs a;
+    a.n_leaves = c->n_leaves;
+    a.n = c->n;
+    a.l_begin = (const int*)c->l_begin.p;
+    a.l_count = (const int*)c->l_count.p;
+    a.l_origin = (const double*)c->l_origin.p;
+    a.l_hlist = (const double*)c->l_hlist.p;
+    a.l_dom = (const int*)c->l_dom.p;
+    a.l_off = (const int*)c->l_off.p;
+    a.list = (const ListEntry*)c->list.p;
+    a.l_active = (int*)c->l_active.p;
+    a.l_sorted = (const int*)c->l_sorted.p;
+    a.pos4 = c->pos4.p;
+    a.skey = (const float*)c->skey.p;
+    a.sidx = (const uint16_t*)c->sidx.p;
+    a.di = (const DomainInfo*)c->dom_d.p;
+    a.m = c->P.m;
+    a.H = c->P.H;
+    a.rho = c->P.rho;
+    a.drho = c->P.drho_dH;
+    a.hlo = (double*)c->hlo.p;
+    a.hhi = (double*)c->hhi.p;
+    a.conv = (uint8_t*)c->conv.p;
+    a.nngb = c->P.nngb;
+    a.C_fac = pow(c->prm.kernel_gamma * c->prm.eta, 3.0);
+    a.h_tol = c->prm.precision == SPH_FP64 ? c->prm.h_tol : std::max(c->prm.h_tol, 2e-6);
+    a.flags = (int*)c->flags.p;
+    a.counters = (unsigned long long*)c->counters.p;
+    a.persistent = c->prm.exec_mode == SPH_EXEC_PERSISTENT;
+    a.order = a.persistent ? (const int*)c->l_order.p : nullptr;
+    const int nb = a.persistent ? std::min(resident_wgs(c), blocks_for(c->n_leaves, WAVES_PER_WG))
+                                : blocks_for(c->n_leaves, WAVES_PER_WG);
+    if (nb <= 0) return SPH_OK;
+    if (c->prm.precision == SPH_FP64)
+        k_density<double, false><<<nb, 256, 0, c->stream>>>(a);
+    else if (c->prm.precision == SPH_FP32C)
+        k_density<float, true><<<nb, 256, 0, c->stream>>>(a);
+    else
+        k_density<float, false><<<nb, 256, 0, c->stream>>>(a);
+    SPH_CHECK_LAUNCH();
+    return SPH_OK;
+}
+
+sph_status density_all(sph_ctx* c)
+{
+    if (!c->sorted) return SPH_ERR_STATE;
+    int* flags = (int*)c->flags.p;
+    unsigned long long* cnt = (unsigned long long*)c->counters.p;
+    SPH_CHECK_HIP(hipEventRecord(c->ev[0], c->stream));
+    SPH_TRY(buf_ensure(c->hlo, (size_t)c->n * 8));
+    SPH_TRY(buf_ensure(c->hhi, (size_t)c->n * 8));
+    SPH_TRY(buf_ensure(c->conv, (size_t)c->n));
+    k_density_reset<<<blocks_for(std::max<int64_t>(c->n, c->n_leaves), 256), 256, 0, c->stream>>>(
+        c->n, c->n_leaves, (double*)c->hlo.p, (double*)c->hhi.p, (uint8_t*)c->conv.p, (int*)c->l_active.p);
+    SPH_CHECK_LAUNCH();
+    SPH_CHECK_HIP(hipMemsetAsync(cnt, 0, CNT_N * 8, c->stream));
+    c->st.relists = 0;
+    int sweeps = 0;
+    unsigned long long unconv = 0;
+    int fl = 0;
+    sph_status status = SPH_OK;
+    for (sweeps = 1; sweeps <= c->prm.max_h_iter; sweeps++) {
+        SPH_CHECK_HIP(hipMemsetAsync(flags, 0, sizeof(int), c->stream));
+        SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_UNCONV], 0, 8, c->stream));
+        SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_QUEUE], 0, 8, c->stream));
+        SPH_TRY(launch_density(c));
+        unsigned long long hc[CNT_N];
+        SPH_CHECK_HIP(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, c->stream));
+        SPH_CHECK_HIP(hipMemcpyAsync(&fl, flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
+        unconv = hc[CNT_UNCONV];
+        if (fl & FLAG_BOX_SMALL) status = SPH_ERR_BOX_TOO_SMALL;
+        if (unconv == 0) break;
+        if (fl & FLAG_REBUILD) {
+            // a smoothing length outgrew the top grid: rebuild the cells and
+            // continue from the current H (brackets restart)
+            SPH_TRY(build_all(c));
+            SPH_TRY(sort_all(c));
+            k_density_reset<<<blocks_for(std::max<int64_t>(c->n, c->n_leaves), 256), 256, 0, c->stream>>>(
+                c->n, c->n_leaves, (double*)c->hlo.p, (double*)c->hhi.p, (uint8_t*)c->conv.p, (int*)c->l_active.p);
+            SPH_CHECK_LAUNCH();
+            SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_NDENS], 0, 8, c->stream));
+            c->st.rebuilds++;
+        } else if (fl & FLAG_RELIST) {
+            SPH_TRY(relist(c));
+            c->st.relists++;
+        }
+    }
+    SPH_CHECK_HIP(hipEventRecord(c->ev[1], c->stream));
+    unsigned long long nd = 0;
+    SPH_CHECK_HIP(hipMemcpyAsync(&nd, &cnt[CNT_NDENS], 8, hipMemcpyDeviceToHost, c->stream));
+    SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
+    c->st.sweeps = std::min(sweeps, c->prm.max_h_iter);
+    c->st.n_unconverged = (int)unconv;
+    c->st.n_dens = (int64_t)nd;
+    c->dens_done = true;
+    c->ghost_done = false;
+    c->force_done = false;
+    if (status != SPH_OK) return status;
+    return unconv ? SPH_ERR_NOT_CONVERGED : SPH_OK;
+}
+
+sph_status ghost_all(sph_ctx* c)
+{
+    if (!c->dens_done) return SPH_ERR_STATE;
+    const bool pr = c->predicted;
+    const double* u = pr ? (const double*)c->upr.p : c->P.u;
+    const double* vx = pr ? (const double*)c->vpx.p : c->P.vx;
+    const double* vy = pr ? (const double*)c->vpy.p : c->P.vy;
+    const double* vz = pr ? (const double*)c->vpz.p : c->P.vz;
+    SPH_CHECK_HIP(hipEventRecord(c->ev[2], c->stream));
+    if (c->prm.precision == SPH_FP64)
+        k_ghost<double><<<blocks_for(c->n, 256), 256, 0, c->stream>>>(c->n, c->P.rho, c->P.drho_dH, c->P.H, u, vx, vy,
+                                                                     vz, c->prm.gamma, c->P.omega, c->P.P,
+                                                                     (double4*)c->fv4.p, (double*)c->hf.p);
+    else
+        k_ghost<float><<<blocks_for(c->n, 256), 256, 0, c->stream>>>(c->n, c->P.rho, c->P.drho_dH, c->P.H, u, vx, vy,
+                                                                    vz, c->prm.gamma, c->P.omega, c->P.P,
+                                                                    (float4*)c->fv4.p, (float*)c->hf.p);
+    SPH_CHECK_LAUNCH();
+    SPH_CHECK_HIP(hipEventRecord(c->ev[3], c->stream));
+    c->ghost_done = true;
+    return SPH_OK;
+}
+
+sph_status force_all(sph_ctx* c)
+{
+    if (!c->ghost_done) return SPH_ERR_STATE;
+    const size_t nb8 = (size_t)c->n * 8;
+    unsigned long long* cnt = (unsigned long long*)c->counters.p;
+    SPH_CHECK_HIP(hipEventRecord(c->ev[4], c->stream));
+    SPH_CHECK_HIP(hipMemsetAsync(c->P.ax, 0, nb8, c->stream));
+    SPH_CHECK_HIP(hipMemsetAsync(c->P.ay, 0, nb8, c->stream));
+    SPH_CHECK_HIP(hipMemsetAsync(c->P.az, 0, nb8, c->stream));
+    SPH_CHECK_HIP(hipMemsetAsync(c->P.dudt, 0, nb8, c->stream));
+    SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_NFORCE], 0, 8, c->stream));
+    SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_QUEUE2], 0, 8, c->stream));
+    ForceArgs a;
+    a.n_leaves = c->n_leaves;
+    a.n = c->n;
+    a.l_begin = (const int*)c->l_begin.p;
+    a.l_count = (const int*)c->l_count.p;
+    a.l_origin = (const double*)c->l_origin.p;
+    a.l_hlist = (const double*)c->l_hlist.p;
+    a.l_dom = (const int*)c->l_dom.p;
+    a.l_off = (const int*)c->l_off.p;
+    a.list = (const ListEntry*)c->list.p;
+    a.l_sorted = (const int*)c->l_sorted.p;
+    a.pos4 = c->pos4.p;
+    a.fv4 = c->fv4.p;
+    a.hf = c->hf.p;
+    a.skey = (const float*)c->skey.p;
+    a.sidx = (const uint16_t*)c->sidx.p;
+    a.di = (const DomainInfo*)c->dom_d.p;
+    a.ax = c->P.ax;
+    a.ay = c->P.ay;
+    a.az = c->P.az;
+    a.dudt = c->P.dudt;
+    a.counters = cnt;
+    a.persistent = c->prm.exec_mode == SPH_EXEC_PERSISTENT;
+    a.order = a.persistent ? (const int*)c->l_order.p : nullptr;
+    const int nb = a.persistent ? std::min(resident_wgs(c), blocks_for(c->n_leaves, WAVES_PER_WG))
+                                : blocks_for(c->n_leaves, WAVES_PER_WG);
+    if (nb > 0) {
+        if (c->prm.precision == SPH_FP64)
+            k_force<double, false><<<nb, 256, 0, c->stream>>>(a);
+        else if (c->prm.precision == SPH_FP32C)
+            k_force<float, true><<<nb, 256, 0, c->stream>>>(a);
+        else
+            k_force<float, false><<<nb, 256, 0, c->stream>>>(a);
+        SPH_CHECK_LAUNCH();
+    }
+    SPH_CHECK_HIP(hipEventRecord(c->ev[5], c->stream));
+    unsigned long long nf = 0;
+    SPH_CHECK_HIP(hipMemcpyAsync(&nf, &cnt[CNT_NFORCE], 8, hipMemcpyDeviceToHost, c->stream));
+    SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
+    c->st.n_force = (int64_t)nf;
+    c->force_done = true;
+    return SPH_OK;
+}
+
+sph_status domain_sums(sph_ctx* c, double* host_out)
+{
+    const int nd = c->prm.n_domains;
+    SPH_TRY(buf_ensure(c->dsum_part, (size_t)nd * SUM_CHUNKS * 5 * 8 + (size_t)nd * 5 * 8));
+    const int* ranges = (const int*)c->dranges.p;
+    double* part = (double*)c->dsum_part.p;
+    double* out = part + (size_t)nd * SUM_CHUNKS * 5;
+    dim3 g(SUM_CHUNKS, nd);
+    k_sums_partial<<<g, 256, 0, c->stream>>>(ranges, c->P.m, c->P.vx, c->P.vy, c->P.vz, c->P.u, part);
+    SPH_CHECK_LAUNCH();
+    k_sums_final<<<blocks_for(nd, 64), 64, 0, c->stream>>>(nd, part, out);
+    SPH_CHECK_LAUNCH();
+    SPH_CHECK_HIP(hipMemcpyAsync(host_out, out, (size_t)nd * 5 * 8, hipMemcpyDeviceToHost, c->stream));
+    SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
+    return SPH_OK;
+}
+
+sph_status step_all(sph_ctx* c, double dt)
+{
+    if (!c->force_done) return SPH_ERR_STATE;
+    const int nb = blocks_for(c->n, 256);
+    k_kick_drift<<<nb, 256, 0, c->stream>>>(c->n, c->P.x, c->P.y, c->P.z, c->P.vx, c->P.vy, c->P.vz, c->P.u, c->P.ax,
+                                            c->P.ay, c->P.az, c->P.dudt, c->P.domain, (const DomainInfo*)c->dom_d.p,
+                                            dt);
+    SPH_CHECK_LAUNCH();
+    SPH_TRY(build_all(c));
+    SPH_TRY(sort_all(c));
+    const size_t nb8 = (size_t)c->n * 8;
+    SPH_TRY(buf_ensure(c->vpx, nb8));
+    SPH_TRY(buf_ensure(c->vpy, nb8));
+    SPH_TRY(buf_ensure(c->vpz, nb8));
+    SPH_TRY(buf_ensure(c->upr, nb8));
+    k_predict<<<nb, 256, 0, c->stream>>>(c->n, c->P.vx, c->P.vy, c->P.vz, c->P.u, c->P.ax, c->P.ay, c->P.az, c->P.dudt,
+                                         dt, (double*)c->vpx.p, (double*)c->vpy.p, (double*)c->vpz.p,
+                                         (double*)c->upr.p);
+    SPH_CHECK_LAUNCH();
+    sph_status s = density_all(c);
+    if (s != SPH_OK) return s;
+    c->predicted = true;
+    s = ghost_all(c);
+    if (s == SPH_OK) s = force_all(c);
+    c->predicted = false;
+    if (s != SPH_OK) return s;
+    k_kick<<<nb, 256, 0, c->stream>>>(c->n, c->P.vx, c->P.vy, c->P.vz, c->P.u, c->P.ax, c->P.ay, c->P.az, c->P.dudt, dt);
+    SPH_CHECK_LAUNCH();
+    std::vector<double> sums((size_t)c->prm.n_domains * 5);
+    SPH_TRY(domain_sums(c, sums.data()));
+    for (int k = 0; k < 5; k++) {
+        double t = 0.0;
+        for (int d = 0; d < c->prm.n_domains; d++) t += sums[5 * d + k];
+        c->st.conserved[k] = t;
+    }
+    return SPH_OK;
+}

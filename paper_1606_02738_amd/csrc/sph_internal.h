@@ -1,0 +1,103 @@
+// Internal data layout of libsph_hip (gfx950).  Not part of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sph.h"
+
+#define SPH_WAVE 64
+#define SPH_MAX_LEAF 64          // particles per leaf cell (one wave of lanes)
+#define SPH_NDIR 13              // axis directions between neighbouring cells
+#define SPH_MAX_DEPTH 16         // octree levels below the top grid
+
+// One periodic box ("domain") and its top-level cell grid.
+struct DomainInfo {
+    double L[3];      // box edges
+    double s0[3];     // top-cell edges (>= largest H of the box)
+    int n_top[3];     // top cells per dimension (>= 3)
+    int top_offset;   // global index of the box's first top cell
+};
+
+// Octree cell.  Children of a cell are contiguous in the node array.
+struct Node {
+    uint64_t key_lo;  // first Morton key of the cell
+    int begin, count; // particle range (Morton order)
+    int first_child;  // -1 for a leaf
+    int n_child;
+    int level, domain;
+    int leaf;         // leaf id or -1
+    int top;          // global top-cell index
+    double lo[3], hi[3];   // tight bounding box of the particles
+    double hmax;           // largest H in the cell (subtree)
+    double c_lo[3], c_sz[3];  // geometric cell corner and edge lengths
+};
+
+// Neighbour-cell list entry of leaf A: leaf B, periodic image and the
+// sort direction to use for the pair.
+struct ListEntry {
+    int B;
+    int code;         // shift index (0..26) | dir << 8
+    float dist;       // box-to-box distance between A and the image of B
+    float pad;
+};
+
+__host__ __device__ inline int shift_index(int sx, int sy, int sz) { return (sx + 1) * 9 + (sy + 1) * 3 + (sz + 1); }
+
+// The 13 directions between a cell and its 26 neighbours (one per +/- pair).
+__host__ __device__ inline void sph_dir(int k, double* d)
+{
+    const int t[13][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, -1, 0}, {1, 0, 1}, {1, 0, -1},
+                          {0, 1, 1}, {0, 1, -1}, {1, 1, 1}, {1, 1, -1}, {1, -1, 1}, {1, -1, -1}};
+    double n = sqrt((double)(t[k][0] * t[k][0] + t[k][1] * t[k][1] + t[k][2] * t[k][2]));
+    d[0] = t[k][0] / n; d[1] = t[k][1] / n; d[2] = t[k][2] / n;
+}
+
+// Device-side error / event flags (bit mask in ctx->d_flags).
+enum {
+    FLAG_INVALID = 1,      // NaN / non-positive / out-of-box input
+    FLAG_RELIST = 2,       // some H grew beyond the radius the lists were built for
+    FLAG_REBUILD = 4,      // some H grew beyond the top-cell edge
+    FLAG_BOX_SMALL = 8,    // some H reached the box limit with f < 0
+};
+
+// Slots of the int[64] flags buffer.
+enum { FI_FLAGS = 0, FI_SCRATCH = 8, FI_NCHILD = 9, FI_NLEAVES = 10, FI_NLIST = 11, FI_NFLAGS = 64 };
+
+// Counters written by kernels (device, int64).
+enum { CNT_UNCONV = 0, CNT_NDENS = 1, CNT_NFORCE = 2, CNT_QUEUE = 3, CNT_QUEUE2 = 4, CNT_N = 8 };
+
+// Leaf arrays (device SoA).
+struct LeafArrays {
+    int* begin;
+    int* count;
+    double* origin;   // 3 per leaf: reference point of the cell-relative coordinates
+    double* lo;       // 3 per leaf
+    double* hi;       // 3 per leaf
+    double* hlist;    // radius the neighbour lists were built for
+    int* dom;
+    int* list_off;    // n_leaves + 1
+    int* active;      // leaf has unconverged particles
+    int* sorted;      // 1 if the per-direction sort is valid
+};
+
+// Kernel-side view of the per-box constants and physics parameters.
+struct PhysParams {
+    double gamma;
+    double C_fac;     // (kernel_gamma * eta)^3
+    double h_tol;
+};
+
+// Device helpers shared by the kernels.
+template <typename T> struct vec4;
+template <> struct vec4<float> { typedef float4 type; };
+template <> struct vec4<double> { typedef double4 type; };
+
+__device__ inline uint64_t double_as_u64(double v) { return (uint64_t)__double_as_longlong(v); }
+__device__ inline double u64_as_double(uint64_t v) { return __longlong_as_double((long long)v); }
+
+// Positive doubles order like their bit patterns: atomic max via integer max.
+__device__ inline void atomic_max_pos_double(double* addr, double v)
+{
+    atomicMax((unsigned long long*)addr, (unsigned long long)double_as_u64(v));
+}

@@ -1,0 +1,218 @@
+"""ctypes binding of libsph_hip (the C-ABI in include/sph.h).
+
+Argument marshalling only: every stage runs in the library's HIP kernels.
+Particle arrays are torch tensors on the GPU (float64 unless stated); torch
+provides device memory and the stream, nothing else.  If the library is not
+built this module raises at import of :func:`lib` -- there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsph_hip.so")
+
+SPH_FP64, SPH_FP32C, SPH_FP32 = 0, 1, 2
+SPH_EXEC_GRID, SPH_EXEC_PERSISTENT = 0, 1
+PRECISIONS = {"fp64": SPH_FP64, "fp32c": SPH_FP32C, "fp32": SPH_FP32}
+EXEC_MODES = {"grid": SPH_EXEC_GRID, "persistent": SPH_EXEC_PERSISTENT}
+
+STATUS = {0: "SPH_OK", -1: "SPH_ERR_INVALID", -2: "SPH_ERR_HIP", -3: "SPH_ERR_NOT_CONVERGED",
+          -4: "SPH_ERR_H_EXCEEDS_CELL", -5: "SPH_ERR_BOX_TOO_SMALL", -6: "SPH_ERR_ALLOC",
+          -7: "SPH_ERR_STATE"}
+
+FLOAT_FIELDS = ("x", "y", "z", "vx", "vy", "vz", "u", "m", "H", "rho", "drho_dH", "omega", "P",
+                "ax", "ay", "az", "dudt")
+
+
+class SPHError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__("%s: %s (%d)" % (where, STATUS.get(status, "?"), status))
+
+
+class Params(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("eta", C.c_double), ("kernel_gamma", C.c_double),
+                ("h_tol", C.c_double), ("max_h_iter", C.c_int), ("n_split", C.c_int),
+                ("precision", C.c_int), ("exec_mode", C.c_int), ("n_domains", C.c_int),
+                ("persistent_wgs", C.c_int), ("waves_per_wg", C.c_int), ("pad", C.c_int),
+                ("boxes", C.POINTER(C.c_double))]
+
+
+class Particles(C.Structure):
+    _fields_ = [("n", C.c_int64)] + [(f, C.c_void_p) for f in FLOAT_FIELDS] + \
+               [("id", C.c_void_p), ("domain", C.c_void_p), ("nngb", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_leaves", C.c_int64), ("n_nodes", C.c_int64),
+                ("n_list", C.c_int64), ("n_pair_tasks", C.c_int64), ("n_dens", C.c_int64),
+                ("n_force", C.c_int64), ("sweeps", C.c_int32), ("n_unconverged", C.c_int32),
+                ("relists", C.c_int32), ("rebuilds", C.c_int32), ("depth", C.c_int32),
+                ("key_bits", C.c_int32), ("conserved", C.c_double * 5),
+                ("t_density_ms", C.c_double), ("t_ghost_ms", C.c_double),
+                ("t_force_ms", C.c_double), ("t_build_ms", C.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["conserved"] = list(self.conserved)
+        return d
+
+
+_lib = None
+EXPORTS = ("sph_create", "sph_destroy", "sph_build_cells", "sph_sort_cells", "sph_density",
+           "sph_ghost", "sph_force", "sph_step", "sph_get_stats", "sph_domain_sums",
+           "sph_status_str", "sph_version")
+
+
+def lib():
+    """Load libsph_hip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libsph_hip.so is not built (run paper_1606_02738_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.sph_create.argtypes = [C.POINTER(Params), vp, C.POINTER(vp)]
+        L.sph_destroy.argtypes = [vp]
+        L.sph_build_cells.argtypes = [vp, C.POINTER(Particles)]
+        for f in ("sph_sort_cells", "sph_density", "sph_ghost", "sph_force"):
+            getattr(L, f).argtypes = [vp]
+        L.sph_step.argtypes = [vp, C.c_double]
+        L.sph_get_stats.argtypes = [vp, C.POINTER(Stats)]
+        L.sph_domain_sums.argtypes = [vp, C.POINTER(C.c_double)]
+        L.sph_status_str.restype = C.c_char_p
+        L.sph_status_str.argtypes = [C.c_int]
+        L.sph_version.restype = C.c_char_p
+        for f in EXPORTS:
+            if f not in ("sph_status_str", "sph_version"):
+                getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st, where):
+    if st != 0:
+        raise SPHError(st, where)
+
+
+def to_device(d, device="cuda"):
+    """Copy a generator dict (numpy) to GPU tensors with every field the
+    library binds (outputs zero-initialised)."""
+    import torch
+    n = d["x"].size
+    t = {}
+    for k in FLOAT_FIELDS:
+        if k in d:
+            t[k] = torch.from_numpy(np.ascontiguousarray(d[k], dtype=np.float64)).to(device)
+        else:
+            t[k] = torch.zeros(n, dtype=torch.float64, device=device)
+    t["id"] = torch.from_numpy(np.ascontiguousarray(d.get("id", np.arange(n)), dtype=np.int64)).to(device)
+    dom = d.get("domain")
+    t["domain"] = torch.from_numpy(np.ascontiguousarray(
+        dom if dom is not None else np.zeros(n), dtype=np.int32)).to(device)
+    t["nngb"] = torch.zeros(n, dtype=torch.int32, device=device)
+    return t
+
+
+def to_host(t, order_by_id=True):
+    """Tensors -> numpy, optionally back in the original particle order."""
+    out = {k: v.detach().cpu().numpy() for k, v in t.items()}
+    if order_by_id:
+        inv = np.argsort(out["id"], kind="stable")
+        out = {k: v[inv] for k, v in out.items()}
+    return out
+
+
+class SPH:
+    """One context of the library bound to one particle set."""
+
+    def __init__(self, boxes, precision="fp32c", exec_mode="grid", gamma=5.0 / 3.0, eta=1.2348,
+                 kernel_gamma=math.sqrt(10.0 / 3.0), h_tol=None, max_h_iter=40, n_split=64,
+                 persistent_wgs=0, stream=None):
+        import torch
+        self._torch = torch
+        b = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(-1, 3))
+        self.n_domains = b.shape[0]
+        self._boxes = b
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        if h_tol is None:
+            h_tol = 1e-10 if prec == SPH_FP64 else 1e-6
+        p = Params()
+        p.gamma, p.eta, p.kernel_gamma, p.h_tol = gamma, eta, kernel_gamma, h_tol
+        p.max_h_iter, p.n_split, p.precision = max_h_iter, n_split, prec
+        p.exec_mode = EXEC_MODES[exec_mode] if isinstance(exec_mode, str) else int(exec_mode)
+        p.n_domains, p.persistent_wgs, p.waves_per_wg, p.pad = self.n_domains, persistent_wgs, 0, 0
+        p.boxes = b.ctypes.data_as(C.POINTER(C.c_double))
+        self.params = p
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = s
+        h = C.c_void_p()
+        _check(lib().sph_create(C.byref(p), C.c_void_p(s.cuda_stream), C.byref(h)), "sph_create")
+        self.h = h
+        self.t = None
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().sph_destroy(self.h)
+            self.h = C.c_void_p()
+
+    __del__ = close
+
+    def bind(self, t):
+        """Attach device tensors (dict from :func:`to_device`)."""
+        for k in FLOAT_FIELDS:
+            v = t[k]
+            assert v.is_cuda and v.dtype == self._torch.float64 and v.is_contiguous(), k
+        self.t = t
+        P = Particles()
+        P.n = t["x"].numel()
+        for k in FLOAT_FIELDS:
+            setattr(P, k, t[k].data_ptr())
+        P.id = t["id"].data_ptr() if "id" in t else None
+        P.domain = t["domain"].data_ptr() if self.n_domains > 1 else None
+        P.nngb = t["nngb"].data_ptr() if "nngb" in t else None
+        self._P = P
+        return self
+
+    def build_cells(self):
+        _check(lib().sph_build_cells(self.h, C.byref(self._P)), "sph_build_cells")
+
+    def sort_cells(self):
+        _check(lib().sph_sort_cells(self.h), "sph_sort_cells")
+
+    def density(self):
+        _check(lib().sph_density(self.h), "sph_density")
+
+    def ghost(self):
+        _check(lib().sph_ghost(self.h), "sph_ghost")
+
+    def force(self):
+        _check(lib().sph_force(self.h), "sph_force")
+
+    def step(self, dt):
+        _check(lib().sph_step(self.h, float(dt)), "sph_step")
+
+    def stats(self):
+        s = Stats()
+        _check(lib().sph_get_stats(self.h, C.byref(s)), "sph_get_stats")
+        return s.as_dict()
+
+    def domain_sums(self):
+        out = np.zeros(5 * self.n_domains)
+        _check(lib().sph_domain_sums(self.h, out.ctypes.data_as(C.POINTER(C.c_double))),
+               "sph_domain_sums")
+        return out.reshape(self.n_domains, 5)
+
+    def run(self):
+        """build_cells -> sort_cells -> density -> ghost -> force."""
+        self.build_cells()
+        self.sort_cells()
+        self.density()
+        self.ghost()
+        self.force()
+        return self

@@ -1,0 +1,74 @@
+"""Host-side checks of the C-ABI library: it loads, exports every function
+that include/sph.h declares, and rejects bad arguments before touching the
+GPU.  No compute calls (no GPU needed)."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1606_02738_amd import sph as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "sph.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"(?:sph_status|const char\s*\*)\s+(sph_\w+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(S.LIB_PATH):
+        from paper_1606_02738_amd import build
+        build.build()
+    return S.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 12, names
+    for f in names:
+        assert hasattr(L, f), f
+    assert set(S.EXPORTS) <= set(names)
+
+
+def test_status_strings_and_version(L):
+    assert L.sph_status_str(0) == b"ok"
+    for code in (-1, -2, -3, -4, -5, -6, -7):
+        assert L.sph_status_str(code) != b"unknown status"
+    assert b"gfx950" in L.sph_version()
+
+
+def _params(**kw):
+    p = S.Params()
+    box = np.ones(3)
+    p.gamma, p.eta, p.kernel_gamma, p.h_tol = 5 / 3, 1.2348, math.sqrt(10 / 3), 1e-6
+    p.max_h_iter, p.n_split, p.precision, p.exec_mode = 20, 64, 1, 0
+    p.n_domains, p.persistent_wgs, p.waves_per_wg, p.pad = 1, 0, 0, 0
+    for k, v in kw.items():
+        setattr(p, k, v)
+    p.boxes = box.ctypes.data_as(C.POINTER(C.c_double))
+    return p, box
+
+
+@pytest.mark.parametrize("bad", [dict(gamma=1.0), dict(eta=0.0), dict(h_tol=0.0), dict(max_h_iter=0),
+                                 dict(n_split=0), dict(n_split=65), dict(precision=7),
+                                 dict(exec_mode=3), dict(n_domains=0)])
+def test_create_rejects_bad_params(L, bad):
+    p, box = _params(**bad)
+    h = C.c_void_p()
+    assert L.sph_create(C.byref(p), None, C.byref(h)) == -1
+    assert not h.value
+
+
+def test_null_arguments(L):
+    assert L.sph_create(None, None, None) == -1
+    assert L.sph_destroy(None) == 0
+    for f in ("sph_sort_cells", "sph_density", "sph_ghost", "sph_force"):
+        assert getattr(L, f)(None) == -1
+    assert L.sph_step(None, 0.1) == -1
+    assert L.sph_build_cells(None, None) == -1

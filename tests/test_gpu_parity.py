@@ -1,0 +1,137 @@
+"""HIP path vs the FP64 oracle, element by element, through the C-ABI.
+
+Sizes: the 32^3 jittered lattice of the plain-method workload (many tiles,
+ragged leaf occupancy), reduced-size versions of the shock-tube, clustered
+and ensemble workloads, a ragged random subset, and the error paths."""
+import numpy as np
+import pytest
+import torch  # noqa: F401  (first import on a fresh box is slow: keep it out of the timed tests)
+
+import gen
+import oracle
+from gpu_helpers import TOL_FP32, TOL_FP64, assert_close, gpu_run, log, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _dev():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1606_02738_amd import sph as S
+    S.lib()
+    oracle.build()
+
+
+@pytest.mark.parametrize("vs", [0.0, 0.1])
+def test_lattice32_fp64(vs):
+    log("case lattice32 fp64 vsigma=%g" % vs)
+    d = gen.lattice(32, vsigma=vs, seed=2739)
+    g, st = gpu_run(d, precision="fp64")
+    o = oracle_run(d)
+    assert st["n_unconverged"] == 0
+    assert_close(g, o, TOL_FP64, counts_exact=True, stats=st)
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp32"])
+def test_lattice32_fp32(prec):
+    log("case lattice32 %s" % prec)
+    d = gen.lattice(32, vsigma=0.1, seed=2739)
+    g, st = gpu_run(d, precision=prec)
+    o = oracle_run(d)
+    assert_close(g, o, TOL_FP32, counts_exact=False)
+
+
+def test_exact_lattice_fp64_counts_and_zero_force():
+    log("case exact lattice 16^3 fp64")
+    d = gen.lattice(16, jitter=0.0)
+    g, st = gpu_run(d, precision="fp64")
+    assert np.all(g["nngb"] == 57)
+    o = oracle_run(d)
+    assert_close(g, o, TOL_FP64, stats=st)
+
+
+@pytest.mark.parametrize("prec,mode", [("fp64", "grid"), ("fp32c", "grid"), ("fp32c", "persistent")])
+def test_clustered_small(prec, mode):
+    log("case clustered 32^3 %s %s" % (prec, mode))
+    d = gen.clustered(32, n_halos=20, seed=2741)
+    g, st = gpu_run(d, precision=prec, exec_mode=mode)
+    o = oracle_run(d)
+    log("stats: leaves=%d depth=%d sweeps=%d relists=%d" % (st["n_leaves"], st["depth"], st["sweeps"],
+                                                           st["relists"]))
+    assert st["n_unconverged"] == 0
+    if prec == "fp64":
+        assert_close(g, o, TOL_FP64, stats=st)
+    else:
+        assert_close(g, o, TOL_FP32, counts_exact=False)
+
+
+@pytest.mark.parametrize("n_split", [8, 32])
+def test_small_leaves(n_split):
+    log("case lattice16 n_split=%d" % n_split)
+    d = gen.lattice(16, vsigma=0.1, seed=7)
+    g, st = gpu_run(d, precision="fp64", n_split=n_split)
+    o = oracle_run(d)
+    assert_close(g, o, TOL_FP64, stats=st)
+
+
+def test_sod_small_fp32c():
+    log("case sod 20/10 fp32c")
+    d = gen.sod(20)
+    g, st = gpu_run(d, precision="fp32c")
+    o = oracle_run(d)
+    assert_close(g, o, TOL_FP32, counts_exact=False)
+
+
+def test_ragged_subset_fp64():
+    log("case ragged subset fp64")
+    d = gen.lattice(16, jitter=0.3, vsigma=0.2, seed=3)
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(d["x"].size, 1500, replace=False))
+    s = gen.subset(d, idx)
+    s["id"] = np.arange(idx.size, dtype=np.int64)
+    s["H"] = s["H"] * 1.3
+    g, st = gpu_run(s, precision="fp64")
+    o = oracle_run(s)
+    assert_close(g, o, TOL_FP64, stats=st)
+
+
+def test_ensemble_small_fp32c():
+    log("case ensemble 4 boxes fp32c")
+    d = gen.ensemble(4, (8, 14), seed=11)
+    g, st = gpu_run(d, precision="fp32c")
+    o = oracle_run(d)
+    assert_close(g, o, TOL_FP32, counts_exact=False)
+
+
+def test_errors_and_state():
+    import torch
+    from paper_1606_02738_amd import sph as S
+    log("case error paths")
+    d = gen.lattice(8, seed=1)
+    d["x"][5] = np.nan
+    sim = S.SPH(d["box"], precision="fp32c")
+    sim.bind(S.to_device(d))
+    with pytest.raises(S.SPHError) as ei:
+        sim.build_cells()
+    assert ei.value.status == -1
+    with pytest.raises(S.SPHError) as ei:
+        sim.density()
+    assert ei.value.status == -7
+    sim.close()
+    d = gen.lattice(8, seed=1)
+    d["y"][3] = 1.0  # outside [0, L)
+    sim = S.SPH(d["box"], precision="fp32c")
+    sim.bind(S.to_device(d))
+    with pytest.raises(S.SPHError) as ei:
+        sim.build_cells()
+    assert ei.value.status == -1
+    sim.close()
+    d = gen.lattice(6, seed=1)  # H = 0.375 > L/3
+    sim = S.SPH(d["box"], precision="fp32c")
+    sim.bind(S.to_device(d))
+    with pytest.raises(S.SPHError) as ei:
+        sim.build_cells()
+    assert ei.value.status == -5
+    sim.close()
+    torch.cuda.synchronize()
