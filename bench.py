@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Benchmark of the SPH neighbour-interaction hot path on one MI355X.
+
+Workload: the clustered cosmology-like periodic unit box, 256^3 = 16,777,216
+equal-mass particles (lognormal density field with sigma_ln = 1.5 plus 500
+NFW halos, concentrations 5-15, log-uniform masses over 3 decades),
+synthetic and seeded.  One step = one kick-drift-kick step through the
+C-ABI: cell rebuild (Morton keys, radix sort, octree, neighbour-cell lists),
+per-direction sort, density sweeps with the FP64 smoothing-length test
+(warm-started), ghost, symmetric force, kicks and FP64 conservation sums.
+
+Metric: SPH neighbour interactions per second, counting N_dens = sum_i
+#{j : r_ij < H_i} (self included) plus 2 N_force with N_force the unordered
+pairs within max(H_i, H_j), divided by the wall time of whole steps.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic FP32/FP64 operations per evaluated interaction (an FMA counts
+# as 2): density pair (distance, kernel value and H-derivative, two
+# accumulations) and symmetric force pair (distance, both kernel gradients,
+# both sides' acceleration and du/dt).  Compensated sums add 4 per
+# accumulation.  Only pairs inside the range are counted.
+FLOPS_DENS = {"fp32c": 31, "fp32": 23, "fp64": 23}
+FLOPS_FORCE = {"fp32c": 64, "fp32": 52, "fp64": 52}
+# MI355X vector ALU peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x
+# 2 flop (FMA) x 2.4 GHz; FP64 vector runs at the same rate.
+PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(n_side, seed):
+    """The FP64 oracle (k-d tree, OpenMP over the host's threads) on the same
+    clustered recipe at n_side^3 particles: density solve from the same kind
+    of initial guess, ghost and force."""
+    import gen
+    import oracle
+    oracle.build()
+    d = gen.clustered(n_side, seed=seed, n_halos=max(1, int(round(500 * (n_side / 256) ** 3))))
+    t0 = time.perf_counter()
+    o = oracle.full(d, tree=True)
+    dt = time.perf_counter() - t0
+    inter = o["n_dens"] + 2 * o["n_force"]
+    return {"value": inter / dt, "unit": "interactions/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "clustered recipe at %d^3 = %d particles (%.3g of the workload), full density "
+                      "solve + ghost + force, %.1f s" % (n_side, n_side ** 3, (n_side / 256) ** 3, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n-side", type=int, default=256)
+    ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp32", "fp64"])
+    ap.add_argument("--exec", dest="exec_mode", default="grid", choices=["grid", "persistent"])
+    ap.add_argument("--n-split", type=int, default=64)
+    ap.add_argument("--cpu-n-side", type=int, default=128)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=2741)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus %d)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_1606_02738_amd import sph as S
+
+    assert torch.cuda.is_available(), "needs a GPU"
+    S.lib()
+    log("generating clustered %d^3 ..." % args.n_side)
+    t0 = time.perf_counter()
+    d = gen.clustered(args.n_side, seed=args.seed,
+                      n_halos=max(1, int(round(500 * (args.n_side / 256) ** 3))))
+    log("generated in %.1f s" % (time.perf_counter() - t0))
+    n = d["x"].size
+    sim = S.SPH(d["box"], precision=args.precision, exec_mode=args.exec_mode, n_split=args.n_split)
+    t = S.to_device(d)
+    del d
+    sim.bind(t)
+    log("initial convergence (cold start) ...")
+    t0 = time.perf_counter()
+    sim.run()
+    torch.cuda.synchronize()
+    st0 = sim.stats()
+    log("cold start: %.2f s, sweeps=%d leaves=%d depth=%d" % (time.perf_counter() - t0, st0["sweeps"],
+                                                              st0["n_leaves"], st0["depth"]))
+    H = t["H"]
+    Hs = H[::max(1, n // 2_000_000)].float()
+    q = torch.quantile(Hs, torch.tensor([0.001, 0.999], device=Hs.device)).cpu().numpy()
+    h_span = float(q[1] / q[0])
+    cs = math.sqrt(5.0 / 3.0 * (2.0 / 3.0) * float(t["u"].max()))
+    dt = 0.25 * float(H.min()) / math.sqrt(10.0 / 3.0) / cs
+
+    for k in range(args.warmup):
+        sim.step(dt)
+        log("warmup step %d done" % k)
+    torch.cuda.synchronize()
+    per = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        sim.step(dt)
+        per.append(sim.stats())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log("timed %d steps in %.3f s" % (args.steps, wall))
+
+    inter = sum(s["n_dens"] + 2 * s["n_force"] for s in per)
+    t_dgf = sum(s["t_density_ms"] + s["t_ghost_ms"] + s["t_force_ms"] for s in per) / 1e3
+    dens_ms = sum(s["t_density_kernels_ms"] for s in per)
+    dens_launch = sum(s["n_density_launches"] for s in per)
+    dens_evals = sum(s["n_dens_evals"] for s in per)
+    force_ms = sum(s["t_force_kernel_ms"] for s in per)
+    force_pairs = sum(s["n_force"] for s in per)
+    prec = args.precision
+    dens_flops = dens_evals * FLOPS_DENS[prec]
+    force_flops = force_pairs * FLOPS_FORCE[prec]
+    if dens_ms >= force_ms:
+        kname, kflops, kms, klaunch = "k_density", dens_flops, dens_ms, dens_launch
+    else:
+        kname, kflops, kms, klaunch = "k_force", force_flops, force_ms, args.steps
+    achieved = kflops / (kms / 1e3) / 1e12
+    roof = {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
+            "launches": klaunch, "avg_launch_ms": kms / max(1, klaunch),
+            "flop_per_launch": kflops / max(1, klaunch)}
+    other = {"k_density": {"ms_total": dens_ms, "launches": dens_launch,
+                           "tflops": dens_flops / max(dens_ms, 1e-9) / 1e9},
+             "k_force": {"ms_total": force_ms, "launches": args.steps,
+                         "tflops": force_flops / max(force_ms, 1e-9) / 1e9}}
+
+    out = {
+        "metric": "SPH neighbour interactions/s (density+force) + step time, 256^3 clustered, vs oracle",
+        "value": inter / wall,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "clustered %d^3 periodic unit box: lognormal sigma_ln=1.5 + NFW halos, "
+                               "h span %.0fx (0.1-99.9%%)" % (args.n_side, h_span),
+                   "n_particles": n, "precision": prec, "exec": args.exec_mode, "n_split": args.n_split,
+                   "dt": dt},
+        "interactions_per_step": inter / args.steps,
+        "n_dens_per_step": sum(s["n_dens"] for s in per) / args.steps,
+        "n_force_per_step": force_pairs / args.steps,
+        "interactions_per_s_density_ghost_force": inter / t_dgf,
+        "mean_sweeps": sum(s["sweeps"] for s in per) / args.steps,
+        "phase_ms_per_step": {"density": sum(s["t_density_ms"] for s in per) / args.steps,
+                              "ghost": sum(s["t_ghost_ms"] for s in per) / args.steps,
+                              "force": sum(s["t_force_ms"] for s in per) / args.steps},
+        "kernels": other,
+        "roofline": roof,
+    }
+    sim.close()
+    del t
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n_side, args.seed)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

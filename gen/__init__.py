@@ -110,7 +110,7 @@ def _gaussian_field(n_grid, rng, slope, smooth):
     amp[0, 0, 0] = 0.0
     fk *= amp
     del k2, amp
-    f = np.fft.irfftn(fk, s=(n_grid, n_grid, n_grid))
+    f = np.fft.irfftn(fk, s=(n_grid, n_grid, n_grid), axes=(0, 1, 2))
     f -= f.mean()
     f /= f.std()
     return f
@@ -235,7 +235,7 @@ def perturbed_lattice(n_side, rng, amp=0.3, smooth=0.1, jitter=0.1):
     k2 = KX ** 2 + KY ** 2 + KZ ** 2
     k2[0, 0, 0] = 1.0
     # displacement psi with div(psi) = -delta
-    psi = [np.fft.irfftn(1j * K * fk / k2, s=delta.shape).ravel() for K in (KX, KY, KZ)]
+    psi = [np.fft.irfftn(1j * K * fk / k2, s=delta.shape, axes=(0, 1, 2)).ravel() for K in (KX, KY, KZ)]
     g = (np.arange(n_side) + 0.5) * dx
     X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
     pos = []
@@ -281,7 +281,7 @@ def make_config(k, seed=None, small=False):
     if k in (3, 4):
         return clustered(32 if small else 256, seed=s, n_halos=20 if small else 500)
     if k == 5:
-        return ensemble(4 if small else 64, (8, 14) if small else (16, 96), seed=s)
+        return ensemble(4 if small else 64, (12, 16) if small else (16, 96), seed=s)
     raise ValueError(k)
 
 

@@ -110,6 +110,11 @@ typedef struct {
     double t_ghost_ms;
     double t_force_ms;
     double t_build_ms;       /* last build_cells + sort_cells */
+    double t_density_kernels_ms; /* summed duration of the density-sweep kernels of the last density call */
+    double t_force_kernel_ms;    /* duration of the force kernel of the last force call */
+    int64_t n_dens_evals;    /* interactions r_ij < H_i evaluated over all sweeps of the last density call */
+    int32_t n_density_launches; /* density-sweep kernel launches of the last density call */
+    int32_t pad;
 } sph_stats;
 
 typedef struct sph_ctx sph_ctx;

@@ -77,6 +77,8 @@ sph_status sph_create(const sph_params* params, void* hip_stream, sph_ctx** out)
     if (s == SPH_OK) s = buf_ensure(c->dstat, (size_t)p.n_domains * 16);
     for (int k = 0; k < 8 && s == SPH_OK; k++)
         if (hipEventCreate(&c->ev[k]) != hipSuccess) s = SPH_ERR_HIP;
+    for (int k = 0; k < 4 && s == SPH_OK; k++)
+        if (hipEventCreate(&c->kev[k]) != hipSuccess) s = SPH_ERR_HIP;
     if (s == SPH_OK && hipMemsetAsync(c->flags.p, 0, FI_NFLAGS * sizeof(int), c->stream) != hipSuccess) s = SPH_ERR_HIP;
     if (s == SPH_OK && hipMemsetAsync(c->counters.p, 0, CNT_N * 8, c->stream) != hipSuccess) s = SPH_ERR_HIP;
     if (s != SPH_OK) {
@@ -101,6 +103,8 @@ sph_status sph_destroy(sph_ctx* c)
     for (DevBuf* b : all) buf_free(*b);
     for (int k = 0; k < 8; k++)
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+    for (int k = 0; k < 4; k++)
+        if (c->kev[k]) (void)hipEventDestroy(c->kev[k]);
     delete c;
     return SPH_OK;
 }

@@ -293,7 +293,7 @@ __global__ __launch_bounds__(256) void k_leaf_pos(int n_leaves, const int* __res
                                                   const double* __restrict__ z, const double* __restrict__ m,
                                                   const double* __restrict__ H, typename vec4<T>::type* pos4, T* hf)
 {
-    const int A = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int A = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6));
     if (A >= n_leaves) return;
     const int lane = threadIdx.x & 63;
     const int b = l_begin[A], c = l_count[A];
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
 __global__ __launch_bounds__(256) void k_node_hmax(Node* nodes, int level_start, int n_level, const double* __restrict__ H,
                                                    double* l_hlist)
 {
-    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int k = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (k >= n_level) return;
     const int lane = threadIdx.x & 63;
     Node& nd = nodes[level_start + k];
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(256) void k_sort_cells(int n_leaves, int64_t n, con
                                                     const typename vec4<T>::type* __restrict__ pos4,
                                                     float* __restrict__ skey, uint16_t* __restrict__ sidx, int* l_sorted)
 {
-    const int A = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int A = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (A >= n_leaves) return;
     const int lane = threadIdx.x & 63;
     const int b = l_begin[A], c = l_count[A];
@@ -662,7 +662,14 @@ sph_status build_all(sph_ctx* c)
         DomainInfo& I = c->dom_h[d];
         if (dstat_h[2 * d] == 0ull) { hmax = 0.0; hmin = INFINITY; }  // empty box
         for (int a = 0; a < 3; a++) {
-            int nt = (hmax > 0.0) ? (int)floor(I.L[a] / (hmax * (1.0 + 1e-12))) : 3;
+            // largest cell count with edge L/nt >= hmax
+            int nt = 3;
+            if (hmax > 0.0) {
+                const double q = floor(I.L[a] / hmax);
+                nt = q > 1e6 ? 1000000 : (int)q;
+                while (nt > 0 && I.L[a] / nt < hmax) nt--;
+                while (I.L[a] / (nt + 1) >= hmax && nt < 1000000) nt++;
+            }
             if (nt < 3) return SPH_ERR_BOX_TOO_SMALL;
             nt = std::min(nt, 128);
             I.n_top[a] = nt;

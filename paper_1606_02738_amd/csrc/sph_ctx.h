@@ -63,6 +63,7 @@ struct sph_ctx {
     DevBuf dsum_part;
 
     hipEvent_t ev[8] = {};
+    hipEvent_t kev[4] = {};     // per-launch kernel timing
 
     int elem_size() const { return prm.precision == SPH_FP64 ? 8 : 4; }
 };

@@ -77,6 +77,20 @@ __device__ inline float wave_maxf(float v)
     for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
     return v;
 }
+// Wave-uniform pop from a device task counter.  Every lane takes part in the
+// atomic (lane 0 adds 1, the others 0) and the result is read from the first
+// lane into a scalar register, so loops that exit on it have a uniform exit
+// condition.  (A pop made by lane 0 alone inside `if (lane == 0)` lets the
+// compiler treat the loop exit as divergent and run the other lanes on
+// without lane 0.)
+__device__ inline int wave_pop(unsigned long long* counter, int lane)
+{
+    const unsigned long long v = atomicAdd(counter, (unsigned long long)(lane == 0 ? 1 : 0));
+    return __builtin_amdgcn_readfirstlane((int)v);
+}
+
+__device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 __device__ inline void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -221,6 +235,12 @@ __device__ void density_leaf(const DensArgs& a, int A, typename vec4<T>::type* t
             Sd += __shfl_xor(Sd, off);
             cnt += __shfl_xor(cnt, off);
         }
+        {
+            // interactions evaluated by this sweep (lanes of group 0 hold the totals)
+            unsigned long long ev = (jg == 0 && act) ? (unsigned long long)cnt : 0ull;
+            for (int off = 32; off > 0; off >>= 1) ev += __shfl_xor(ev, off);
+            if (lane == 0 && ev) atomicAdd(&a.counters[CNT_DEVAL], ev);
+        }
         bool left = false;
         if (jg == 0 && act) {
             const double H = Hd;
@@ -243,6 +263,9 @@ __device__ void density_leaf(const DensArgs& a, int A, typename vec4<T>::type* t
                 } else {
                     double Hn = H - f / fp;
                     if (!(Hn > lo && Hn < hi) || !isfinite(Hn)) Hn = isinf(hi) ? 2.0 * H : 0.5 * (lo + hi);
+                    // at most doubling per sweep: a far-off step would only force
+                    // needless list and grid rebuilds before the bracket closes
+                    if (Hn > 2.0 * H) Hn = 2.0 * H;
                     if (Hn > hlim) Hn = hlim;
                     if (fabs(Hn - H) <= 4.0 * 2.220446049250313e-16 * H) {
                         done = true;  // stalled at round-off: accept H
@@ -277,19 +300,19 @@ __global__ __launch_bounds__(256) void k_density(DensArgs a)
     __shared__ V4 tiles[WAVES_PER_WG][64];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (!a.persistent) {
-        const int A = blockIdx.x * WAVES_PER_WG + w;
+        const int A = uniform(blockIdx.x * WAVES_PER_WG + w);
         if (A >= a.n_leaves) return;
         if (!a.l_active[A]) return;
         density_leaf<T, COMP>(a, A, tiles[w], lane);
         return;
     }
-    // persistent: waves pop leaves from a cost-ordered queue
-    for (;;) {
-        int t = 0;
-        if (lane == 0) t = (int)atomicAdd(&a.counters[CNT_QUEUE], 1ull);
-        t = __shfl(t, 0);
+    // persistent: waves pop leaves from a cost-ordered queue; a wave pops at
+    // most n_leaves times
+    for (int it = 0; it <= a.n_leaves; it++) {
+        const int t = wave_pop(&a.counters[CNT_QUEUE], lane);
         if (t >= a.n_leaves) break;
-        const int A = a.order ? a.order[t] : t;
+        const int A = uniform(a.order ? a.order[t] : t);
+        if (A < 0 || A >= a.n_leaves) break;
         if (a.l_active[A]) density_leaf<T, COMP>(a, A, tiles[w], lane);
     }
 }
@@ -588,17 +611,17 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a)
     __shared__ FTile<T> tiles[WAVES_PER_WG];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (!a.persistent) {
-        const int A = blockIdx.x * WAVES_PER_WG + w;
+        const int A = uniform(blockIdx.x * WAVES_PER_WG + w);
         if (A >= a.n_leaves) return;
         force_leaf<T, COMP>(a, A, tiles[w], lane);
         return;
     }
-    for (;;) {
-        int t = 0;
-        if (lane == 0) t = (int)atomicAdd(&a.counters[CNT_QUEUE2], 1ull);
-        t = __shfl(t, 0);
+    for (int it = 0; it <= a.n_leaves; it++) {
+        const int t = wave_pop(&a.counters[CNT_QUEUE2], lane);
         if (t >= a.n_leaves) break;
-        force_leaf<T, COMP>(a, a.order ? a.order[t] : t, tiles[w], lane);
+        const int A = uniform(a.order ? a.order[t] : t);
+        if (A < 0 || A >= a.n_leaves) break;
+        force_leaf<T, COMP>(a, A, tiles[w], lane);
     }
 }
 
@@ -768,6 +791,9 @@ sph_status density_all(sph_ctx* c)
     SPH_CHECK_LAUNCH();
     SPH_CHECK_HIP(hipMemsetAsync(cnt, 0, CNT_N * 8, c->stream));
     c->st.relists = 0;
+    c->st.t_density_kernels_ms = 0.0;
+    c->st.n_density_launches = 0;
+    c->st.n_dens_evals = 0;
     int sweeps = 0;
     unsigned long long unconv = 0;
     int fl = 0;
@@ -776,11 +802,20 @@ sph_status density_all(sph_ctx* c)
         SPH_CHECK_HIP(hipMemsetAsync(flags, 0, sizeof(int), c->stream));
         SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_UNCONV], 0, 8, c->stream));
         SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_QUEUE], 0, 8, c->stream));
+        SPH_CHECK_HIP(hipEventRecord(c->kev[0], c->stream));
         SPH_TRY(launch_density(c));
+        SPH_CHECK_HIP(hipEventRecord(c->kev[1], c->stream));
         unsigned long long hc[CNT_N];
         SPH_CHECK_HIP(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, c->stream));
         SPH_CHECK_HIP(hipMemcpyAsync(&fl, flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
+        {
+            float ms = 0.f;
+            SPH_CHECK_HIP(hipEventElapsedTime(&ms, c->kev[0], c->kev[1]));
+            c->st.t_density_kernels_ms += ms;
+            c->st.n_density_launches++;
+            c->st.n_dens_evals = (int64_t)hc[CNT_DEVAL];
+        }
         unconv = hc[CNT_UNCONV];
         if (fl & FLAG_BOX_SMALL) status = SPH_ERR_BOX_TOO_SMALL;
         if (unconv == 0) break;
@@ -874,6 +909,7 @@ sph_status force_all(sph_ctx* c)
     a.order = a.persistent ? (const int*)c->l_order.p : nullptr;
     const int nb = a.persistent ? std::min(resident_wgs(c), blocks_for(c->n_leaves, WAVES_PER_WG))
                                 : blocks_for(c->n_leaves, WAVES_PER_WG);
+    SPH_CHECK_HIP(hipEventRecord(c->kev[2], c->stream));
     if (nb > 0) {
         if (c->prm.precision == SPH_FP64)
             k_force<double, false><<<nb, 256, 0, c->stream>>>(a);
@@ -883,10 +919,16 @@ sph_status force_all(sph_ctx* c)
             k_force<float, false><<<nb, 256, 0, c->stream>>>(a);
         SPH_CHECK_LAUNCH();
     }
+    SPH_CHECK_HIP(hipEventRecord(c->kev[3], c->stream));
     SPH_CHECK_HIP(hipEventRecord(c->ev[5], c->stream));
     unsigned long long nf = 0;
     SPH_CHECK_HIP(hipMemcpyAsync(&nf, &cnt[CNT_NFORCE], 8, hipMemcpyDeviceToHost, c->stream));
     SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
+    {
+        float ms = 0.f;
+        SPH_CHECK_HIP(hipEventElapsedTime(&ms, c->kev[2], c->kev[3]));
+        c->st.t_force_kernel_ms = ms;
+    }
     c->st.n_force = (int64_t)nf;
     c->force_done = true;
     return SPH_OK;

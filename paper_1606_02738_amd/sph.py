@@ -55,7 +55,9 @@ class Stats(C.Structure):
                 ("relists", C.c_int32), ("rebuilds", C.c_int32), ("depth", C.c_int32),
                 ("key_bits", C.c_int32), ("conserved", C.c_double * 5),
                 ("t_density_ms", C.c_double), ("t_ghost_ms", C.c_double),
-                ("t_force_ms", C.c_double), ("t_build_ms", C.c_double)]
+                ("t_force_ms", C.c_double), ("t_build_ms", C.c_double),
+                ("t_density_kernels_ms", C.c_double), ("t_force_kernel_ms", C.c_double),
+                ("n_dens_evals", C.c_int64), ("n_density_launches", C.c_int32), ("pad", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

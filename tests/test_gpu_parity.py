@@ -51,7 +51,9 @@ def test_exact_lattice_fp64_counts_and_zero_force():
     assert_close(g, o, TOL_FP64, stats=st)
 
 
-@pytest.mark.parametrize("prec,mode", [("fp64", "grid"), ("fp32c", "grid"), ("fp32c", "persistent")])
+@pytest.mark.parametrize("prec,mode", [
+    ("fp64", "grid"), ("fp32c", "grid"),
+    ("fp32c", "persistent"), ("fp64", "persistent")])
 def test_clustered_small(prec, mode):
     log("case clustered 32^3 %s %s" % (prec, mode))
     d = gen.clustered(32, n_halos=20, seed=2741)
@@ -98,7 +100,7 @@ def test_ragged_subset_fp64():
 
 def test_ensemble_small_fp32c():
     log("case ensemble 4 boxes fp32c")
-    d = gen.ensemble(4, (8, 14), seed=11)
+    d = gen.ensemble(4, (12, 16), seed=11)
     g, st = gpu_run(d, precision="fp32c")
     o = oracle_run(d)
     assert_close(g, o, TOL_FP32, counts_exact=False)
