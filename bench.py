@@ -68,6 +68,7 @@ def main():
     ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp32", "fp64"])
     ap.add_argument("--exec", dest="exec_mode", default="grid", choices=["grid", "persistent"])
     ap.add_argument("--n-split", type=int, default=64)
+    ap.add_argument("--prune", default="box", choices=["box", "sorted"])
     ap.add_argument("--cpu-n-side", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=2741)
@@ -91,7 +92,8 @@ def main():
                       n_halos=max(1, int(round(500 * (args.n_side / 256) ** 3))))
     log("generated in %.1f s" % (time.perf_counter() - t0))
     n = d["x"].size
-    sim = S.SPH(d["box"], precision=args.precision, exec_mode=args.exec_mode, n_split=args.n_split)
+    sim = S.SPH(d["box"], precision=args.precision, exec_mode=args.exec_mode, n_split=args.n_split,
+                prune=args.prune)
     t = S.to_device(d)
     del d
     sim.bind(t)
@@ -162,6 +164,7 @@ def main():
         "config": {"workload": "clustered %d^3 periodic unit box: lognormal sigma_ln=1.5 + NFW halos, "
                                "h span %.0fx (0.1-99.9%%)" % (args.n_side, h_span),
                    "n_particles": n, "precision": prec, "exec": args.exec_mode, "n_split": args.n_split,
+                   "prune": args.prune,
                    "dt": dt},
         "interactions_per_step": inter / args.steps,
         "n_dens_per_step": sum(s["n_dens"] for s in per) / args.steps,

@@ -54,6 +54,7 @@ typedef enum {
 
 enum { SPH_FP64 = 0, SPH_FP32C = 1, SPH_FP32 = 2 };      /* sph_params.precision */
 enum { SPH_EXEC_GRID = 0, SPH_EXEC_PERSISTENT = 1 };     /* sph_params.exec_mode */
+enum { SPH_PRUNE_BOX = 0, SPH_PRUNE_SORTED = 1 };        /* sph_params.prune */
 
 typedef struct {
     double gamma;        /* adiabatic index, 5/3 */
@@ -69,8 +70,11 @@ typedef struct {
                             cost-ordered device task queue */
     int n_domains;       /* number of independent periodic boxes (>= 1) */
     int persistent_wgs;  /* resident workgroups for the persistent mode (0: auto) */
-    int waves_per_wg;    /* waves per workgroup in the interaction kernels (1..4, 0: 4) */
-    int pad;
+    int waves_per_wg;    /* reserved, 0 */
+    int prune;           /* pair-candidate selection: SPH_PRUNE_BOX (neighbour-cell
+                            particles within range of the bounding box of the cell's
+                            particles) or SPH_PRUNE_SORTED (window of the sort stage's
+                            per-direction order) */
     const double* boxes; /* HOST pointer, n_domains x 3 box edge lengths; copied */
 } sph_params;
 

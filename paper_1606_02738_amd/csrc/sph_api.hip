@@ -62,6 +62,7 @@ sph_status sph_create(const sph_params* params, void* hip_stream, sph_ctx** out)
     if (p.max_h_iter < 1 || p.n_split < 1 || p.n_split > SPH_MAX_LEAF) return SPH_ERR_INVALID;
     if (p.precision < SPH_FP64 || p.precision > SPH_FP32) return SPH_ERR_INVALID;
     if (p.exec_mode < SPH_EXEC_GRID || p.exec_mode > SPH_EXEC_PERSISTENT) return SPH_ERR_INVALID;
+    if (p.prune < SPH_PRUNE_BOX || p.prune > SPH_PRUNE_SORTED) return SPH_ERR_INVALID;
     for (int k = 0; k < 3 * p.n_domains; k++)
         if (!(p.boxes[k] > 0.0) || !isfinite(p.boxes[k])) return SPH_ERR_INVALID;
     sph_ctx* c = new (std::nothrow) sph_ctx();
@@ -182,7 +183,11 @@ sph_status sph_get_stats(sph_ctx* c, sph_stats* out)
     c->st.n_leaves = c->n_leaves;
     c->st.n_nodes = c->n_nodes;
     c->st.n_list = c->n_list;
-    c->st.n_pair_tasks = c->n_pair_tasks;
+    {
+        unsigned long long np = 0;
+        SPH_CHECK_HIP(hipMemcpy(&np, (unsigned long long*)c->counters.p + CNT_NPAIR, 8, hipMemcpyDeviceToHost));
+        c->st.n_pair_tasks = (int64_t)np;
+    }
     c->st.depth = c->depth;
     c->st.key_bits = c->key_bits;
     c->st.t_density_ms = c->dens_done ? elapsed(c->ev[0], c->ev[1]) : -1.0;

@@ -15,52 +15,58 @@
 // Validation: finite inputs, positive m and H, positions inside [0,L) of the
 // particle's box; per-box largest and smallest H.
 // ---------------------------------------------------------------------------
+__device__ inline void flush_hrange(unsigned long long* dstat, int d, double hmx, double hmn)
+{
+    atomicMax(&dstat[2 * d], (unsigned long long)__double_as_longlong(hmx));
+    atomicMin(&dstat[2 * d + 1], (unsigned long long)__double_as_longlong(hmn));
+}
+
+// Grid-stride: each thread keeps the H range of its current box and flushes
+// it when the box changes; at the end a wave whose lanes share one box
+// reduces across lanes first (one atomic pair per wave).
 __global__ __launch_bounds__(256) void k_validate(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
                                                   const double* __restrict__ z, const double* __restrict__ H,
                                                   const double* __restrict__ m, const int32_t* __restrict__ dom,
                                                   int ndom, const DomainInfo* __restrict__ di,
                                                   unsigned long long* dstat, int* flags)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool ok = i < n;
-    int d = 0;
-    double h = 0.0;
-    if (ok) {
-        d = dom ? dom[i] : 0;
+    int dcur = -1;
+    double hmx = 0.0, hmn = INFINITY;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int d = dom ? dom[i] : 0;
         if (d < 0 || d >= ndom) {
-            atomicOr(flags, FLAG_INVALID);
-            ok = false;
+            bad = true;
+            continue;
         }
-    }
-    if (ok) {
         const double* L = di[d].L;
-        const double px = x[i], py = y[i], pz = z[i];
-        h = H[i];
-        const double mm = m[i];
-        bool good = isfinite(px) && isfinite(py) && isfinite(pz) && px >= 0.0 && px < L[0] && py >= 0.0 &&
-                    py < L[1] && pz >= 0.0 && pz < L[2] && isfinite(h) && h > 0.0 && isfinite(mm) && mm > 0.0;
+        const double px = x[i], py = y[i], pz = z[i], h = H[i], mm = m[i];
+        const bool good = isfinite(px) && isfinite(py) && isfinite(pz) && px >= 0.0 && px < L[0] && py >= 0.0 &&
+                          py < L[1] && pz >= 0.0 && pz < L[2] && isfinite(h) && h > 0.0 && isfinite(mm) && mm > 0.0;
         if (!good) {
-            atomicOr(flags, FLAG_INVALID);
-            ok = false;
+            bad = true;
+            continue;
         }
+        if (d != dcur) {
+            if (dcur >= 0) flush_hrange(dstat, dcur, hmx, hmn);
+            dcur = d;
+            hmx = 0.0;
+            hmn = INFINITY;
+        }
+        hmx = fmax(hmx, h);
+        hmn = fmin(hmn, h);
     }
-    // wave-level reduction when the whole wave is one box
-    const int d0 = __shfl(d, 0);
-    const unsigned long long act = __ballot(ok);
-    const unsigned long long same = __ballot(ok && d == d0);
-    if (act != 0 && same == act && __shfl(ok ? 1 : 0, 0)) {
-        double hmx = ok ? h : 0.0, hmn = ok ? h : INFINITY;
+    if (bad) atomicOr(flags, FLAG_INVALID);
+    const int d0 = __shfl(dcur, 0);
+    const bool uni = __ballot(dcur != d0) == 0ull;
+    if (uni && d0 >= 0) {
         for (int off = 32; off > 0; off >>= 1) {
             hmx = fmax(hmx, __shfl_xor(hmx, off));
             hmn = fmin(hmn, __shfl_xor(hmn, off));
         }
-        if ((threadIdx.x & 63) == 0) {
-            atomicMax(&dstat[2 * d0], (unsigned long long)__double_as_longlong(hmx));
-            atomicMin(&dstat[2 * d0 + 1], (unsigned long long)__double_as_longlong(hmn));
-        }
-    } else if (ok) {
-        atomicMax(&dstat[2 * d], (unsigned long long)__double_as_longlong(h));
-        atomicMin(&dstat[2 * d + 1], (unsigned long long)__double_as_longlong(h));
+        if ((threadIdx.x & 63) == 0) flush_hrange(dstat, d0, hmx, hmn);
+    } else if (dcur >= 0) {
+        flush_hrange(dstat, dcur, hmx, hmn);
     }
 }
 
@@ -150,22 +156,68 @@ __global__ __launch_bounds__(256) void k_top_nodes(int n_top_total, int ndom, co
         nd.hi[a] = -INFINITY;
     }
     nd.hmax = 0.0;
+    nd.hmin = INFINITY;
+    nd.merged = 0;
+    nd.pad = 0;
     nodes[t] = nd;
+}
+
+// Children of a split cell: octants holding more than n_split particles
+// become cells of their own (split again at the next level); runs of
+// consecutive smaller octants (in Morton order) are merged into one leaf
+// while the run holds at most n_split particles, so leaves stay near the
+// size of one wave.  Merging is allowed only when the parent already meets
+// the extent / smallest-H bound, so a merged leaf never needs a split.
+// Writes (first octant, particle begin, count) per child; returns the number
+// of children.
+__device__ inline int child_groups(const int* bnd, int n_split, bool allow_merge, int* gq, int* gb, int* gc)
+{
+    int n = 0, open = -1;
+    for (int q = 0; q < 8; q++) {
+        const int c = bnd[q + 1] - bnd[q];
+        if (c == 0) continue;
+        if (c > n_split || !allow_merge) {
+            open = -1;
+            gq[n] = q; gb[n] = bnd[q]; gc[n] = c;
+            n++;
+            continue;
+        }
+        if (open >= 0 && gc[open] + c <= n_split) {
+            gc[open] += c;
+            continue;
+        }
+        gq[n] = q; gb[n] = bnd[q]; gc[n] = c;
+        open = n;
+        n++;
+    }
+    return n;
 }
 
 // Statistics of one cell (bounding box, largest H) and its number of
 // non-empty children if it is to be split.  One workgroup per cell.
+// Whether a cell with these statistics must be split for precision: its
+// extent exceeds h_ratio times its smallest H (FP32 cell-relative
+// coordinates keep an absolute error of ~1e-7 of the cell extent).
+__device__ inline bool extent_too_large(const Node& nd, double h_ratio)
+{
+    if (!(h_ratio > 0.0) || nd.count < 2) return false;
+    const double ext = fmax(fmax(nd.hi[0] - nd.lo[0], nd.hi[1] - nd.lo[1]), nd.hi[2] - nd.lo[2]);
+    return ext > h_ratio * nd.hmin;
+}
+
+// Statistics of one cell (bounding box, largest and smallest H) and its
+// number of children if it is to be split.  One workgroup per cell.
 __global__ __launch_bounds__(256) void k_node_stats(Node* nodes, int level_start, const uint64_t* __restrict__ keys,
                                                     const double* __restrict__ x, const double* __restrict__ y,
                                                     const double* __restrict__ z, const double* __restrict__ H, int D,
-                                                    int n_split, int* nchild)
+                                                    int n_split, double h_ratio, int* nchild)
 {
-    __shared__ double red[7][256];
+    __shared__ double red[8][256];
     __shared__ int bnd[9];
     const int k = blockIdx.x;
     Node* nd = &nodes[level_start + k];
     const int b = nd->begin, c = nd->count, tid = threadIdx.x;
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, hm = 0.0;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, hm = 0.0, hn = INFINITY;
     for (int p = b + tid; p < b + c; p += 256) {
         const double q[3] = {x[p], y[p], z[p]};
         for (int a = 0; a < 3; a++) {
@@ -173,12 +225,14 @@ __global__ __launch_bounds__(256) void k_node_stats(Node* nodes, int level_start
             hi[a] = fmax(hi[a], q[a]);
         }
         hm = fmax(hm, H[p]);
+        hn = fmin(hn, H[p]);
     }
     for (int a = 0; a < 3; a++) {
         red[a][tid] = lo[a];
         red[3 + a][tid] = hi[a];
     }
     red[6][tid] = hm;
+    red[7][tid] = hn;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
         if (tid < s) {
@@ -187,24 +241,32 @@ __global__ __launch_bounds__(256) void k_node_stats(Node* nodes, int level_start
                 red[3 + a][tid] = fmax(red[3 + a][tid], red[3 + a][tid + s]);
             }
             red[6][tid] = fmax(red[6][tid], red[6][tid + s]);
+            red[7][tid] = fmin(red[7][tid], red[7][tid + s]);
         }
         __syncthreads();
     }
-    const bool split = c > n_split && nd->level < D;
-    if (split && tid < 9) {
-        const uint64_t step = 1ull << (3 * (D - nd->level - 1));
-        bnd[tid] = (tid == 0) ? b : (tid == 8 ? b + c : lower_bound_u64(keys, b, b + c, nd->key_lo + step * tid));
-    }
-    __syncthreads();
     if (tid == 0) {
         for (int a = 0; a < 3; a++) {
             nd->lo[a] = red[a][0];
             nd->hi[a] = red[3 + a][0];
         }
         nd->hmax = red[6][0];
+        nd->hmin = red[7][0];
+    }
+    __syncthreads();
+    const bool wide = extent_too_large(*nd, h_ratio);
+    const bool split = !nd->merged && nd->level < D && (c > n_split || wide);
+    if (split && tid < 9) {
+        const uint64_t step = 1ull << (3 * (D - nd->level - 1));
+        bnd[tid] = (tid == 0) ? b : (tid == 8 ? b + c : lower_bound_u64(keys, b, b + c, nd->key_lo + step * tid));
+    }
+    __syncthreads();
+    if (tid == 0) {
         int nc = 0;
-        if (split)
-            for (int q = 0; q < 8; q++) nc += (bnd[q + 1] > bnd[q]) ? 1 : 0;
+        if (split) {
+            int gq[8], gb[8], gc[8];
+            nc = child_groups(bnd, n_split, !wide, gq, gb, gc);
+        }
         nchild[k] = nc;
         nd->n_child = nc;
         nd->first_child = -1;
@@ -212,7 +274,8 @@ __global__ __launch_bounds__(256) void k_node_stats(Node* nodes, int level_start
 }
 
 __global__ __launch_bounds__(64) void k_emit_children(Node* nodes, int level_start, int n_level, const int* __restrict__ coff,
-                                                      int child_base, const uint64_t* __restrict__ keys, int D)
+                                                      int child_base, const uint64_t* __restrict__ keys, int D, int n_split,
+                                                      double h_ratio)
 {
     const int k = blockIdx.x;
     if (k >= n_level) return;
@@ -225,14 +288,16 @@ __global__ __launch_bounds__(64) void k_emit_children(Node* nodes, int level_sta
     if (tid < 9) bnd[tid] = (tid == 0) ? b : (tid == 8 ? b + c : lower_bound_u64(keys, b, b + c, nd->key_lo + step * tid));
     __syncthreads();
     if (tid == 0) {
-        int out = child_base + coff[k];
+        int gq[8], gb[8], gc[8];
+        const int ng = child_groups(bnd, n_split, !extent_too_large(*nd, h_ratio), gq, gb, gc);
+        const int out = child_base + coff[k];
         nd->first_child = out;
-        for (int q = 0; q < 8; q++) {
-            if (bnd[q + 1] <= bnd[q]) continue;
+        for (int g = 0; g < ng; g++) {
+            const int q = gq[g];
             Node ch;
             ch.key_lo = nd->key_lo + step * q;
-            ch.begin = bnd[q];
-            ch.count = bnd[q + 1] - bnd[q];
+            ch.begin = gb[g];
+            ch.count = gc[g];
             ch.first_child = -1;
             ch.n_child = 0;
             ch.level = nd->level + 1;
@@ -247,7 +312,10 @@ __global__ __launch_bounds__(64) void k_emit_children(Node* nodes, int level_sta
                 ch.hi[a] = -INFINITY;
             }
             ch.hmax = 0.0;
-            nodes[out++] = ch;
+            ch.hmin = INFINITY;
+            ch.merged = (q + 1 < 8 && gb[g] + gc[g] > bnd[q + 1]) ? 1 : 0;
+            ch.pad = 0;
+            nodes[out + g] = ch;
         }
     }
 }
@@ -281,7 +349,7 @@ __global__ __launch_bounds__(256) void k_leaf_fill(Node* nodes, int n_nodes, con
         l_hi[3 * id + a] = nd.hi[a];
         l_origin[3 * id + a] = 0.5 * (nd.lo[a] + nd.hi[a]);
     }
-    l_hlist[id] = nd.hmax;
+    l_hlist[id] = nd.hmax * (1.0 + SPH_LIST_SKIN);
     l_dom[id] = nd.domain;
 }
 
@@ -310,12 +378,14 @@ __global__ __launch_bounds__(256) void k_leaf_pos(int n_leaves, const int* __res
 }
 
 // ---------------------------------------------------------------------------
-// Neighbour-cell lists.  For leaf A, every leaf B (with periodic image) whose
-// bounding box lies closer to A's than max(h_A, h_B) -- the largest H of the
-// two cells -- may hold interacting pairs (ranges r < H_i of eq. (rho) and
-// r < max(H_i, H_j) of eq. (dvdt)).  Found by descending the octree from the
-// 27 top cells around A's top cell, pruning cells by box distance against
-// max(h_A, largest H in the subtree).
+// Neighbour-cell lists (gather form).  Leaf A's list holds every leaf B (with
+// periodic image) whose bounding box lies closer to A's than h_A, the radius
+// A's list is built for (largest H in A plus a skin): these are the cells the
+// density sum of eq. (rho) over r < H_i needs.  The symmetric force range
+// r < max(H_i, H_j) of eq. (dvdt) is covered by the union of A's and B's
+// lists; each unordered pair of cells is evaluated once by a fixed owner
+// (see force_owner).  Found by descending the octree from the 27 top cells
+// around A's top cell, pruning cells whose box lies h_A or farther away.
 // ---------------------------------------------------------------------------
 #define WALK_STACK 160
 
@@ -333,6 +403,15 @@ __device__ inline double box_dist(const double* alo, const double* ahi, const do
     return sqrt(d2);
 }
 
+// Distance between leaf boxes A and B + s, evaluated with the lower-indexed
+// leaf as reference so that it is bitwise the same from both sides.
+__device__ inline double leaf_dist(int A, const Node& NA, int B, const Node& NB, const double* s)
+{
+    if (A <= B) return box_dist(NA.lo, NA.hi, NB.lo, NB.hi, s);
+    const double ms[3] = {-s[0], -s[1], -s[2]};
+    return box_dist(NB.lo, NB.hi, NA.lo, NA.hi, ms);
+}
+
 template <bool FILL>
 __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restrict__ leaf_node, const Node* __restrict__ nodes,
                                               const DomainInfo* __restrict__ di, const double* __restrict__ l_hlist,
@@ -346,6 +425,7 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
     const int loc = NA.top - I.top_offset;
     const int tc[3] = {loc / (I.n_top[2] * I.n_top[1]), (loc / I.n_top[2]) % I.n_top[1], loc % I.n_top[2]};
     const double hA = l_hlist[A];
+    const double prune = hA * (1.0 + 1e-12);
     const double ca[3] = {0.5 * (NA.lo[0] + NA.hi[0]), 0.5 * (NA.lo[1] + NA.hi[1]), 0.5 * (NA.lo[2] + NA.hi[2])};
     int cnt = 0;
     int out = FILL ? l_off[A] : 0;
@@ -370,10 +450,9 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
         while (sp > 0) {
             const Node& nd = nodes[stack[--sp]];
             if (nd.count == 0) continue;
-            const double d = box_dist(NA.lo, NA.hi, nd.lo, nd.hi, sv);
-            const double R = fmax(hA, nd.hmax) * (1.0 + 1e-12);
-            if (d >= R) continue;
             if (nd.n_child == 0) {
+                const double d = leaf_dist(A, NA, nd.leaf, nd, sv);
+                if (!(d < hA)) continue;
                 if (FILL) {
                     if (out < out_end && out < list_cap) {
                         // sort direction: the one of 13 most aligned with the centre offset
@@ -390,8 +469,7 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
                         ListEntry e;
                         e.B = nd.leaf;
                         e.code = code_shift | (best << 8);
-                        e.dist = (float)d;
-                        e.pad = 0.f;
+                        e.dist = d;
                         list[out] = e;
                     } else {
                         atomicOr(flags, FLAG_INVALID);
@@ -400,6 +478,7 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
                 }
                 cnt++;
             } else {
+                if (box_dist(NA.lo, NA.hi, nd.lo, nd.hi, sv) > prune) continue;
                 if (sp + nd.n_child > WALK_STACK) {
                     atomicOr(flags, FLAG_INVALID);
                     continue;
@@ -429,7 +508,7 @@ __global__ __launch_bounds__(256) void k_node_hmax(Node* nodes, int level_start,
     for (int off = 32; off > 0; off >>= 1) hm = fmax(hm, __shfl_xor(hm, off));
     if (lane == 0) {
         nd.hmax = hm;
-        if (nd.leaf >= 0) l_hlist[nd.leaf] = hm;
+        if (nd.leaf >= 0) l_hlist[nd.leaf] = hm * (1.0 + SPH_LIST_SKIN);
     }
 }
 
@@ -526,12 +605,19 @@ static sph_status permute_all(sph_ctx* c, const uint32_t* perm)
 // in which the persistent kernels drain the leaves.
 __global__ __launch_bounds__(256) void k_leaf_cost(int n_leaves, const int* __restrict__ l_count,
                                                    const int* __restrict__ l_off, const ListEntry* __restrict__ list,
-                                                   uint64_t* keys, uint32_t* vals)
+                                                   const double* __restrict__ l_hlist, uint64_t* keys, uint32_t* vals,
+                                                   unsigned long long* n_owned)
 {
     const int A = blockIdx.x * blockDim.x + threadIdx.x;
     if (A >= n_leaves) return;
     long long s = 0;
-    for (int e = l_off[A]; e < l_off[A + 1]; e++) s += l_count[list[e].B];
+    unsigned long long own = 0;
+    for (int e = l_off[A]; e < l_off[A + 1]; e++) {
+        const ListEntry E = list[e];
+        s += l_count[E.B];
+        if (E.B != A && (E.B > A || !(E.dist < l_hlist[E.B]))) own++;
+    }
+    if (own) atomicAdd(n_owned, own);
     long long cost = (long long)l_count[A] * s;
     const long long cmax = (1ll << 40) - 1;
     if (cost > cmax) cost = cmax;
@@ -546,9 +632,11 @@ static sph_status task_order(sph_ctx* c)
         SPH_TRY(buf_ensure(c->okeys[q], (size_t)(nL + 1) * 8));
         SPH_TRY(buf_ensure(c->ovals[q], (size_t)(nL + 1) * 4));
     }
+    unsigned long long* npair = (unsigned long long*)c->counters.p + CNT_NPAIR;
+    SPH_CHECK_HIP(hipMemsetAsync(npair, 0, 8, c->stream));
     k_leaf_cost<<<blocks_for(nL, 256), 256, 0, c->stream>>>(nL, (const int*)c->l_count.p, (const int*)c->l_off.p,
-                                                          (const ListEntry*)c->list.p, (uint64_t*)c->okeys[0].p,
-                                                          (uint32_t*)c->ovals[0].p);
+                                                          (const ListEntry*)c->list.p, (const double*)c->l_hlist.p,
+                                                          (uint64_t*)c->okeys[0].p, (uint32_t*)c->ovals[0].p, npair);
     SPH_CHECK_LAUNCH();
     int res = 0;
     SPH_TRY(radix_sort(c, nL, 40, c->okeys, c->ovals, &res));
@@ -615,7 +703,6 @@ sph_status relist(sph_ctx* c)
                                                             total, flags);
     SPH_CHECK_LAUNCH();
     c->n_list = total;
-    c->n_pair_tasks = (total - nL) / 2;
     return task_order(c);
 }
 
@@ -642,7 +729,7 @@ sph_status build_all(sph_ctx* c)
     }
     SPH_CHECK_HIP(hipMemcpyAsync(c->dom_d.p, c->dom_h.data(), nd * sizeof(DomainInfo), hipMemcpyHostToDevice, c->stream));
     SPH_CHECK_HIP(hipMemcpyAsync(c->dstat.p, dstat_h.data(), 2 * nd * 8, hipMemcpyHostToDevice, c->stream));
-    k_validate<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->P.x, c->P.y, c->P.z, c->P.H, c->P.m, c->P.domain, nd,
+    k_validate<<<std::min(blocks_for(n, 256), 2048), 256, 0, c->stream>>>(n, c->P.x, c->P.y, c->P.z, c->P.H, c->P.m, c->P.domain, nd,
                                                         (const DomainInfo*)c->dom_d.p,
                                                         (unsigned long long*)c->dstat.p, flags);
     SPH_CHECK_LAUNCH();
@@ -715,6 +802,9 @@ sph_status build_all(sph_ctx* c)
     k_top_nodes<<<blocks_for(top, 256), 256, 0, c->stream>>>(top, nd, (const DomainInfo*)c->dom_d.p, keys, (int)n, D,
                                                            (Node*)c->nodes.p);
     SPH_CHECK_LAUNCH();
+    // FP32 cell-relative coordinates: keep every leaf's extent within
+    // SPH_FP32_EXTENT_RATIO of its smallest smoothing length
+    const double h_ratio = c->prm.precision == SPH_FP64 ? 0.0 : SPH_FP32_EXTENT_RATIO;
     c->level_off.clear();
     c->level_off.push_back(0);
     int level_start = 0, n_level = top, n_nodes = top;
@@ -723,7 +813,7 @@ sph_status build_all(sph_ctx* c)
         SPH_TRY(buf_ensure(c->nchild, (size_t)(n_level + 1) * sizeof(int)));
         int* nchild = (int*)c->nchild.p;
         k_node_stats<<<n_level, 256, 0, c->stream>>>((Node*)c->nodes.p, level_start, keys, c->P.x, c->P.y, c->P.z,
-                                                     c->P.H, D, c->prm.n_split, nchild);
+                                                     c->P.H, D, c->prm.n_split, h_ratio, nchild);
         SPH_CHECK_LAUNCH();
         SPH_TRY(scan_exclusive(c, nchild, nchild, n_level, flags + FI_NCHILD));
         int total = 0;
@@ -741,7 +831,8 @@ sph_status build_all(sph_ctx* c)
             c->nodes = nb2;
             cap = ncap;
         }
-        k_emit_children<<<n_level, 64, 0, c->stream>>>((Node*)c->nodes.p, level_start, n_level, nchild, n_nodes, keys, D);
+        k_emit_children<<<n_level, 64, 0, c->stream>>>((Node*)c->nodes.p, level_start, n_level, nchild, n_nodes, keys, D,
+                                                       c->prm.n_split, h_ratio);
         SPH_CHECK_LAUNCH();
         level_start = n_nodes;
         n_level = total;

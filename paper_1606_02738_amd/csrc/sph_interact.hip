@@ -121,6 +121,57 @@ __device__ inline bool sorted_window(const float* skey, int64_t n, int dir, int 
 }
 
 // ---------------------------------------------------------------------------
+// Pair-candidate selection.  For a neighbour cell B the particles that can
+// interact with the wave's i particles are chosen either
+//  - PRUNE_BOX: B's particles whose distance to the bounding box of the
+//    wave's i particles is below the interaction range (3D test, one load of
+//    B's cell per pair of cells, the next cell prefetched into registers), or
+//  - PRUNE_SORTED: the window of B's particles sorted along the pair
+//    direction whose projections lie within the range of the i projections
+//    (the sort stage's per-direction order).
+// ---------------------------------------------------------------------------
+enum { PRUNE_BOX = 0, PRUNE_SORTED = 1 };
+
+template <typename T> __device__ inline T wave_min_t(T v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+    return v;
+}
+template <typename T> __device__ inline T wave_max_t(T v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    return v;
+}
+
+// Squared distance from p to the box [lo, hi].
+template <typename T>
+__device__ inline T box_d2(T px, T py, T pz, T lx, T ly, T lz, T hx, T hy, T hz)
+{
+    const T gx = fmax(fmax(lx - px, px - hx), T(0));
+    const T gy = fmax(fmax(ly - py, py - hy), T(0));
+    const T gz = fmax(fmax(lz - pz, pz - hz), T(0));
+    return gx * gx + gy * gy + gz * gz;
+}
+
+// lane position among the set lanes of mask below it
+__device__ inline int mask_rank(unsigned long long mask, int lane)
+{
+    const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    return __popcll(mask & lt);
+}
+
+// Neighbour-entry batch of one wave, in LDS.
+template <typename T>
+struct EBatch {
+    int b[64];     // first particle of B
+    int n[64];     // particles of B
+    int B[64];     // leaf index of B
+    int dir[64];   // sort direction of the pair
+    T ox[64], oy[64], oz[64];  // origin(B) + periodic shift - origin(A)
+    T R[64];       // interaction range of the pair (force)
+};
+
+// ---------------------------------------------------------------------------
 // Density sweep + FP64 Newton step (eq. (rho); the smoothing-length
 // constraint rho H^3 = C with its derivative 3 H^2 rho Omega).
 // ---------------------------------------------------------------------------
@@ -156,8 +207,46 @@ struct DensArgs {
     int persistent;
 };
 
-template <typename T, bool COMP>
-__device__ void density_leaf(const DensArgs& a, int A, typename vec4<T>::type* tile, int lane)
+template <typename T>
+struct DTile {
+    typename vec4<T>::type p[64];  // selected particles of B (B frame), w = m
+    EBatch<T> e;
+};
+
+// Load the entries [eb, eb + nbt) of A's list, keep those that pass
+// keep(E), compact them into the batch; returns their number.
+template <typename T, typename Keep>
+__device__ inline int load_batch(const ListEntry* list, int eb, int nbt, int lane, const int* l_begin, const int* l_count,
+                                 const double* l_origin, const double* oA, const DomainInfo& I, Keep keep, EBatch<T>& E,
+                                 const double* l_hlist, int A)
+{
+    bool ok = false;
+    ListEntry en;
+    if (lane < nbt) {
+        en = list[eb + lane];
+        ok = keep(en);
+    }
+    const unsigned long long mask = __ballot(ok);
+    if (ok) {
+        const int s = mask_rank(mask, lane);
+        const int B = en.B;
+        double sv[3];
+        shift_vec(en.code, I, sv);
+        E.b[s] = l_begin[B];
+        E.n[s] = l_count[B];
+        E.B[s] = B;
+        E.dir[s] = en.code >> 8;
+        E.ox[s] = (T)(l_origin[3 * B] + sv[0] - oA[0]);
+        E.oy[s] = (T)(l_origin[3 * B + 1] + sv[1] - oA[1]);
+        E.oz[s] = (T)(l_origin[3 * B + 2] + sv[2] - oA[2]);
+        E.R[s] = (T)(l_hlist ? l_hlist[B] : 0.0);
+    }
+    wave_sync();
+    return __popcll(mask);
+}
+
+template <typename T, bool COMP, int PRUNE>
+__device__ void density_leaf(const DensArgs& a, int A, DTile<T>& L, int lane)
 {
     typedef typename vec4<T>::type V4;
     const V4* pos4 = (const V4*)a.pos4;
@@ -183,51 +272,97 @@ __device__ void density_leaf(const DensArgs& a, int A, typename vec4<T>::type* t
         Acc<T, COMP> sw, sd;
         int cnt = 0;
         const double hA = wave_max(act ? Hd : 0.0);
-        for (int e = e0; e < e1; e++) {
-            const ListEntry E = a.list[e];
-            if ((double)E.dist > hA * (1.0 + 1e-6)) continue;
-            const int B = E.B, dir = E.code >> 8;
-            const int bB = a.l_begin[B], nB = a.l_count[B];
-            double sv[3];
-            shift_vec(E.code, I, sv);
-            const T dox = (T)(a.l_origin[3 * B] + sv[0] - oA[0]);
-            const T doy = (T)(a.l_origin[3 * B + 1] + sv[1] - oA[1]);
-            const T doz = (T)(a.l_origin[3 * B + 2] + sv[2] - oA[2]);
-            const T xi = pi.x - dox, yi = pi.y - doy, zi = pi.z - doz;  // i in B's frame
-            int lo = 0, hi = nB;
-            const bool srt = a.l_sorted[B] && nB <= 64;
-            if (srt) {
-                double u[3];
-                sph_dir(dir, u);
-                const float ki = (float)((double)xi * u[0] + (double)yi * u[1] + (double)zi * u[2]);
-                float kmin = wave_minf(act ? ki - (float)Hd : INFINITY);
-                float kmax = wave_maxf(act ? ki + (float)Hd : -INFINITY);
-                const float eps = 1e-5f * (fabsf(kmin) + fabsf(kmax)) + 1e-6f * (float)hA;
-                sorted_window(a.skey, a.n, dir, bB, nB, lane, kmin - eps, kmax + eps, lo, hi);
+        // bounding box of the active i (A frame) and the squared pruning radius
+        const T big = T(1e30);
+        const T bxl = wave_min_t<T>(act ? pi.x : big), bxh = wave_max_t<T>(act ? pi.x : -big);
+        const T byl = wave_min_t<T>(act ? pi.y : big), byh = wave_max_t<T>(act ? pi.y : -big);
+        const T bzl = wave_min_t<T>(act ? pi.z : big), bzh = wave_max_t<T>(act ? pi.z : -big);
+        const T hAm = (T)(hA * (1.0 + 1e-5));
+        const T hA2 = hAm * hAm;
+        for (int eb = e0; eb < e1; eb += 64) {
+            const int nbt = min(64, e1 - eb);
+            const int nv = load_batch<T>(a.list, eb, nbt, lane, a.l_begin, a.l_count, a.l_origin, oA, I,
+                                         [&](const ListEntry& E) { return E.dist < hA; }, L.e, nullptr, A);
+            V4 pf;  // prefetched first cell of the next pair
+            if (PRUNE == PRUNE_BOX && nv > 0) {
+                const int n0 = L.e.n[0];
+                if (lane < n0) pf = pos4[L.e.b[0] + lane];
             }
-            for (int p0 = lo; p0 < hi; p0 += 64) {
-                const int len = min(64, hi - p0);
-                if (lane < len) {
-                    const int t = p0 + lane;
-                    const int jl = srt ? (int)a.sidx[(int64_t)dir * a.n + bB + t] : t;
-                    tile[lane] = pos4[bB + jl];
-                }
-                wave_sync();
-                for (int t = jg; t < len; t += G) {
-                    const V4 pj = tile[t];
-                    const T dx = pj.x - xi, dy = pj.y - yi, dz = pj.z - zi;
-                    const T r2 = dx * dx + dy * dy + dz * dz;
-                    if (act && r2 < H2) {
-                        const T q = sqrt(r2) * invH;
-                        T w, dw;
-                        spline_w_dw(q, w, dw);
-                        sw.add(pj.w * w);
-                        sd.add(pj.w * (T(3) * w + q * dw));
-                        cnt++;
+            for (int k = 0; k < nv; k++) {
+                const int bB = L.e.b[k], nB = L.e.n[k];
+                const T dox = L.e.ox[k], doy = L.e.oy[k], doz = L.e.oz[k];
+                const T xi = pi.x - dox, yi = pi.y - doy, zi = pi.z - doz;  // i in B's frame
+                int len = 0;
+                if (PRUNE == PRUNE_BOX && nB <= 64) {
+                    const V4 pj = pf;
+                    if (k + 1 < nv) {
+                        const int n1 = L.e.n[k + 1];
+                        if (lane < n1) pf = pos4[L.e.b[k + 1] + lane];
+                    }
+                    const bool in = lane < nB && box_d2<T>(pj.x, pj.y, pj.z, bxl - dox, byl - doy, bzl - doz,
+                                                            bxh - dox, byh - doy, bzh - doz) < hA2;
+                    const unsigned long long mk = __ballot(in);
+                    if (in) L.p[mask_rank(mk, lane)] = pj;
+                    len = __popcll(mk);
+                    wave_sync();
+                    for (int t = jg; t < len; t += G) {
+                        const V4 q4 = L.p[t];
+                        const T dx = q4.x - xi, dy = q4.y - yi, dz = q4.z - zi;
+                        const T r2 = dx * dx + dy * dy + dz * dz;
+                        if (act && r2 < H2) {
+                            const T q = sqrt(r2) * invH;
+                            T w, dw;
+                            spline_w_dw(q, w, dw);
+                            sw.add(q4.w * w);
+                            sd.add(q4.w * (T(3) * w + q * dw));
+                            cnt++;
+                        }
+                    }
+                    wave_sync();
+                } else {
+                    // sorted-axis window (or a cell too large for one tile)
+                    int lo = 0, hi = nB;
+                    const int dir = L.e.dir[k];
+                    const bool srt = PRUNE == PRUNE_SORTED && a.l_sorted[L.e.B[k]] && nB <= 64;
+                    if (srt) {
+                        double u[3];
+                        sph_dir(dir, u);
+                        const float ki = (float)((double)xi * u[0] + (double)yi * u[1] + (double)zi * u[2]);
+                        float kmin = wave_minf(act ? ki - (float)Hd : INFINITY);
+                        float kmax = wave_maxf(act ? ki + (float)Hd : -INFINITY);
+                        const float eps = 1e-5f * (fabsf(kmin) + fabsf(kmax)) + 1e-6f * (float)hA;
+                        sorted_window(a.skey, a.n, dir, bB, nB, lane, kmin - eps, kmax + eps, lo, hi);
+                    }
+                    for (int p0 = lo; p0 < hi; p0 += 64) {
+                        len = min(64, hi - p0);
+                        if (lane < len) {
+                            const int t = p0 + lane;
+                            const int jl = srt ? (int)a.sidx[(int64_t)dir * a.n + bB + t] : t;
+                            L.p[lane] = pos4[bB + jl];
+                        }
+                        wave_sync();
+                        for (int t = jg; t < len; t += G) {
+                            const V4 q4 = L.p[t];
+                            const T dx = q4.x - xi, dy = q4.y - yi, dz = q4.z - zi;
+                            const T r2 = dx * dx + dy * dy + dz * dz;
+                            if (act && r2 < H2) {
+                                const T q = sqrt(r2) * invH;
+                                T w, dw;
+                                spline_w_dw(q, w, dw);
+                                sw.add(q4.w * w);
+                                sd.add(q4.w * (T(3) * w + q * dw));
+                                cnt++;
+                            }
+                        }
+                        wave_sync();
+                    }
+                    if (PRUNE == PRUNE_BOX && k + 1 < nv) {
+                        const int n1 = L.e.n[k + 1];
+                        if (lane < n1) pf = pos4[L.e.b[k + 1] + lane];
                     }
                 }
-                wave_sync();
             }
+            wave_sync();
         }
         double Sw = sw.total(), Sd = sd.total();
         for (int off = CI; off < 64; off <<= 1) {
@@ -293,17 +428,16 @@ __device__ void density_leaf(const DensArgs& a, int A, typename vec4<T>::type* t
     if (lane == 0) a.l_active[A] = any_left ? 1 : 0;
 }
 
-template <typename T, bool COMP>
+template <typename T, bool COMP, int PRUNE>
 __global__ __launch_bounds__(256) void k_density(DensArgs a)
 {
-    typedef typename vec4<T>::type V4;
-    __shared__ V4 tiles[WAVES_PER_WG][64];
+    __shared__ DTile<T> tiles[WAVES_PER_WG];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (!a.persistent) {
         const int A = uniform(blockIdx.x * WAVES_PER_WG + w);
         if (A >= a.n_leaves) return;
         if (!a.l_active[A]) return;
-        density_leaf<T, COMP>(a, A, tiles[w], lane);
+        density_leaf<T, COMP, PRUNE>(a, A, tiles[w], lane);
         return;
     }
     // persistent: waves pop leaves from a cost-ordered queue; a wave pops at
@@ -313,7 +447,7 @@ __global__ __launch_bounds__(256) void k_density(DensArgs a)
         if (t >= a.n_leaves) break;
         const int A = uniform(a.order ? a.order[t] : t);
         if (A < 0 || A >= a.n_leaves) break;
-        if (a.l_active[A]) density_leaf<T, COMP>(a, A, tiles[w], lane);
+        if (a.l_active[A]) density_leaf<T, COMP, PRUNE>(a, A, tiles[w], lane);
     }
 }
 
@@ -358,9 +492,11 @@ __global__ __launch_bounds__(256) void k_ghost(int64_t n, const double* __restri
 
 // ---------------------------------------------------------------------------
 // Force, eqs. (dvdt) and (dudt), symmetric: every unordered pair once.
-// Pair cells (A,B) with B > A: i-side sums in registers, j-side sums in LDS
-// (lane-rotated so that lanes of a group touch distinct j), flushed with one
-// atomic add per j and quantity.  Self cells: triangular sweep.
+// Pair cells (A,B): i-side sums in registers, j-side sums in LDS (lanes of a
+// group rotate over distinct j), flushed with one atomic add per j and
+// quantity.  The cell's own pairs: triangular sweep.  Each unordered pair of
+// cells is evaluated by one owner: the lower index if the pair is in both
+// cells' lists, else the cell whose list holds it.
 // ---------------------------------------------------------------------------
 struct ForceArgs {
     int n_leaves;
@@ -396,6 +532,7 @@ struct FTile {
     T ih[64];                      // 1/H
     T acc[4][64];                  // j-side sums
     int jl[64];                    // local index in B
+    EBatch<T> e;
 };
 
 template <typename T, bool COMP>
@@ -433,14 +570,12 @@ __device__ inline bool force_pair(T dx, T dy, T dz, T mi, T h2i, T ihi, T ki, T 
 }
 
 template <typename T>
-__device__ inline void stage_force_j(FTile<T>& tl, int slot, int p, const typename vec4<T>::type* pos4,
-                                     const typename vec4<T>::type* fv4, const T* hf, int jl)
+__device__ inline void stage_force_j(FTile<T>& tl, int slot, const typename vec4<T>::type& p, typename vec4<T>::type f,
+                                     T h, int jl)
 {
-    const T h = hf[p];
     const T ih = T(1) / h;
-    typename vec4<T>::type f = fv4[p];
     f.w = f.w * T(INV_PI_8) * ih * ih * ih * ih;
-    tl.p[slot] = pos4[p];
+    tl.p[slot] = p;
     tl.v[slot] = f;
     tl.h2[slot] = h * h;
     tl.ih[slot] = ih;
@@ -451,7 +586,7 @@ __device__ inline void stage_force_j(FTile<T>& tl, int slot, int p, const typena
     tl.jl[slot] = jl;
 }
 
-template <typename T, bool COMP>
+template <typename T, bool COMP, int PRUNE>
 __device__ void force_leaf(const ForceArgs& a, int A, FTile<T>& tl, int lane)
 {
     typedef typename vec4<T>::type V4;
@@ -471,121 +606,178 @@ __device__ void force_leaf(const ForceArgs& a, int A, FTile<T>& tl, int lane)
         const bool vi = ii < nc;
         const int i = bA + c0 + (vi ? ii : 0);
         const V4 pi = pos4[i];
-        V4 fi = fv4[i];
+        const V4 fi = fv4[i];
         const T Hi = hf[i];
         const T h2i = Hi * Hi, ihi = T(1) / Hi;
         const T ki = fi.w * T(INV_PI_8) * ihi * ihi * ihi * ihi;
         FAcc<T, COMP> ai;
         const double hA = wave_max(vi ? (double)Hi : 0.0);
-        for (int e = e0; e < e1; e++) {
-            const ListEntry E = a.list[e];
-            const int B = E.B;
-            if (B < A) continue;
-            const int bB = a.l_begin[B], nB = a.l_count[B];
-            if (B == A) {
-                if (nA <= 64) {
-                    // triangular sweep over the unordered pairs of the cell
-                    if (lane < nA) stage_force_j<T>(tl, lane, bA + lane, pos4, fv4, hf, lane);
+        const T big = T(1e30);
+        const T bxl = wave_min_t<T>(vi ? pi.x : big), bxh = wave_max_t<T>(vi ? pi.x : -big);
+        const T byl = wave_min_t<T>(vi ? pi.y : big), byh = wave_max_t<T>(vi ? pi.y : -big);
+        const T bzl = wave_min_t<T>(vi ? pi.z : big), bzh = wave_max_t<T>(vi ? pi.z : -big);
+
+        // the cell's own pairs
+        if (nA <= 64) {
+            // triangular sweep over the unordered pairs of the cell
+            if (lane < nA) stage_force_j<T>(tl, lane, pos4[bA + lane], fv4[bA + lane], hf[bA + lane], lane);
+            wave_sync();
+            const int steps = nA / 2;  // pair distances 1..floor(n/2)
+            const bool even = (nA & 1) == 0;
+            for (int t = jg; t < steps; t += G) {
+                int b = ii + 1 + t;
+                if (b >= nA) b -= nA;
+                const bool ok = vi && !(even && t == steps - 1 && ii >= nA / 2);
+                if (ok) {
+                    const V4 pj = tl.p[b];
+                    const T dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+                    if (force_pair<T, COMP, true>(dx, dy, dz, pi.w, h2i, ihi, ki, fi.x, fi.y, fi.z, pj, tl.v[b],
+                                                  tl.h2[b], tl.ih[b], ai, &tl.acc[0][0], b))
+                        npairs++;
+                }
+            }
+            wave_sync();
+            if (jg == 0 && vi) {
+                ai.ax.add(tl.acc[0][ii]);
+                ai.ay.add(tl.acc[1][ii]);
+                ai.az.add(tl.acc[2][ii]);
+                ai.du.add(tl.acc[3][ii]);
+            }
+            wave_sync();
+        } else {
+            // large cell: gather over all j != i of the cell (i side only)
+            for (int p0 = 0; p0 < nA; p0 += 64) {
+                const int len = min(64, nA - p0);
+                if (lane < len) {
+                    const int p = bA + p0 + lane;
+                    stage_force_j<T>(tl, lane, pos4[p], fv4[p], hf[p], p0 + lane);
+                }
+                wave_sync();
+                for (int t = jg; t < len; t += G) {
+                    if (!vi || p0 + t == c0 + ii) continue;
+                    const V4 pj = tl.p[t];
+                    const T dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+                    if (force_pair<T, COMP, false>(dx, dy, dz, pi.w, h2i, ihi, ki, fi.x, fi.y, fi.z, pj, tl.v[t],
+                                                   tl.h2[t], tl.ih[t], ai, nullptr, t))
+                        if (p0 + t > c0 + ii) npairs++;
+                }
+                wave_sync();
+            }
+        }
+
+        // pairs with other cells
+        for (int eb = e0; eb < e1; eb += 64) {
+            const int nbt = min(64, e1 - eb);
+            const double* hl = a.l_hlist;
+            const int nv = load_batch<T>(a.list, eb, nbt, lane, a.l_begin, a.l_count, a.l_origin, oA, I,
+                                         [&](const ListEntry& E) {
+                                             const int B = E.B;
+                                             if (B == A) return false;
+                                             if (B < A && E.dist < hl[B]) return false;  // owned by B
+                                             return E.dist < fmax(hA, hl[B]);
+                                         },
+                                         tl.e, hl, A);
+            V4 pf, ff;
+            T hh = T(1);
+            if (PRUNE == PRUNE_BOX && nv > 0) {
+                const int n0 = tl.e.n[0];
+                if (lane < n0) {
+                    const int p = tl.e.b[0] + lane;
+                    pf = pos4[p];
+                    ff = fv4[p];
+                    hh = hf[p];
+                }
+            }
+            for (int k = 0; k < nv; k++) {
+                const int bB = tl.e.b[k], nB = tl.e.n[k];
+                const T dox = tl.e.ox[k], doy = tl.e.oy[k], doz = tl.e.oz[k];
+                const T xi = pi.x - dox, yi = pi.y - doy, zi = pi.z - doz;
+                const T R = fmax((T)hA, tl.e.R[k]);
+                int passes_lo = 0, passes_hi = nB;
+                bool direct = PRUNE == PRUNE_BOX && nB <= 64;
+                const int dir = tl.e.dir[k];
+                const bool srt = !direct && PRUNE == PRUNE_SORTED && a.l_sorted[tl.e.B[k]] && nB <= 64;
+                if (srt) {
+                    double u[3];
+                    sph_dir(dir, u);
+                    const float ki_ = (float)((double)xi * u[0] + (double)yi * u[1] + (double)zi * u[2]);
+                    const float Rf = (float)R;
+                    float kmin = wave_minf(vi ? ki_ - Rf : INFINITY);
+                    float kmax = wave_maxf(vi ? ki_ + Rf : -INFINITY);
+                    const float eps = 1e-5f * (fabsf(kmin) + fabsf(kmax)) + 1e-6f * Rf;
+                    sorted_window(a.skey, a.n, dir, bB, nB, lane, kmin - eps, kmax + eps, passes_lo, passes_hi);
+                }
+                for (int p0 = passes_lo; p0 < passes_hi; p0 += 64) {
+                    int len;
+                    if (direct) {
+                        const V4 pj = pf, fj = ff;
+                        const T hj = hh;
+                        if (k + 1 < nv) {
+                            const int n1 = tl.e.n[k + 1];
+                            if (lane < n1) {
+                                const int p = tl.e.b[k + 1] + lane;
+                                pf = pos4[p];
+                                ff = fv4[p];
+                                hh = hf[p];
+                            }
+                        }
+                        const T Rj = fmax((T)hA, hj) * T(1.00001);
+                        const bool in = lane < nB && box_d2<T>(pj.x, pj.y, pj.z, bxl - dox, byl - doy, bzl - doz,
+                                                                bxh - dox, byh - doy, bzh - doz) < Rj * Rj;
+                        const unsigned long long mk = __ballot(in);
+                        if (in) stage_force_j<T>(tl, mask_rank(mk, lane), pj, fj, hj, lane);
+                        len = __popcll(mk);
+                    } else {
+                        len = min(64, passes_hi - p0);
+                        if (lane < len) {
+                            const int t = p0 + lane;
+                            const int jl = srt ? (int)a.sidx[(int64_t)dir * a.n + bB + t] : t;
+                            const int p = bB + jl;
+                            stage_force_j<T>(tl, lane, pos4[p], fv4[p], hf[p], jl);
+                        }
+                    }
                     wave_sync();
-                    const int steps = nA / 2;  // pair distances 1..floor(n/2)
-                    const bool even = (nA & 1) == 0;
-                    for (int t = jg; t < steps; t += G) {
-                        int b = ii + 1 + t;
-                        if (b >= nA) b -= nA;
-                        const bool ok = vi && !(even && t == steps - 1 && ii >= nA / 2);
-                        if (ok) {
-                            const V4 pj = tl.p[b];
-                            const T dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-                            if (force_pair<T, COMP, true>(dx, dy, dz, pi.w, h2i, ihi, ki, fi.x, fi.y, fi.z, pj, tl.v[b],
-                                                          tl.h2[b], tl.ih[b], ai, &tl.acc[0][0], b))
+                    // group jg owns slots jg, jg+G, ...; lanes of a group rotate over them
+                    const int Lg = (jg < len) ? (len - jg + G - 1) / G : 0;
+                    const int Lmax = (len + G - 1) / G;
+                    const int s0 = (Lg > 0) ? ii % Lg : 0;
+                    for (int t = 0; t < Lmax; t++) {
+                        if (vi && t < Lg) {
+                            int s = s0 + t;
+                            if (s >= Lg) s -= Lg;
+                            const int o = jg + G * s;
+                            const V4 pj = tl.p[o];
+                            const T dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
+                            if (force_pair<T, COMP, true>(dx, dy, dz, pi.w, h2i, ihi, ki, fi.x, fi.y, fi.z, pj, tl.v[o],
+                                                          tl.h2[o], tl.ih[o], ai, &tl.acc[0][0], o))
                                 npairs++;
                         }
                     }
                     wave_sync();
-                    if (jg == 0 && vi) {
-                        ai.ax.add(tl.acc[0][ii]);
-                        ai.ay.add(tl.acc[1][ii]);
-                        ai.az.add(tl.acc[2][ii]);
-                        ai.du.add(tl.acc[3][ii]);
+                    if (lane < len) {
+                        const int p = bB + tl.jl[lane];
+                        const T gx = tl.acc[0][lane], gy = tl.acc[1][lane], gz = tl.acc[2][lane], gu = tl.acc[3][lane];
+                        if (gx != T(0) || gy != T(0) || gz != T(0) || gu != T(0)) {
+                            atomicAdd(&a.ax[p], (double)gx);
+                            atomicAdd(&a.ay[p], (double)gy);
+                            atomicAdd(&a.az[p], (double)gz);
+                            atomicAdd(&a.dudt[p], (double)gu);
+                        }
                     }
                     wave_sync();
-                } else {
-                    // large cell: gather over all j != i of the cell (i side only)
-                    for (int p0 = 0; p0 < nA; p0 += 64) {
-                        const int len = min(64, nA - p0);
-                        if (lane < len) stage_force_j<T>(tl, lane, bA + p0 + lane, pos4, fv4, hf, p0 + lane);
-                        wave_sync();
-                        for (int t = jg; t < len; t += G) {
-                            if (!vi || p0 + t == c0 + ii) continue;
-                            const V4 pj = tl.p[t];
-                            const T dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-                            if (force_pair<T, COMP, false>(dx, dy, dz, pi.w, h2i, ihi, ki, fi.x, fi.y, fi.z, pj,
-                                                           tl.v[t], tl.h2[t], tl.ih[t], ai, nullptr, t))
-                                if (p0 + t > c0 + ii) npairs++;
-                        }
-                        wave_sync();
+                    if (direct) break;
+                }
+                if (!direct && PRUNE == PRUNE_BOX && k + 1 < nv) {
+                    const int n1 = tl.e.n[k + 1];
+                    if (lane < n1) {
+                        const int p = tl.e.b[k + 1] + lane;
+                        pf = pos4[p];
+                        ff = fv4[p];
+                        hh = hf[p];
                     }
                 }
-                continue;
             }
-            const double R = fmax(hA, a.l_hlist[B]);
-            if ((double)E.dist > R * (1.0 + 1e-6)) continue;
-            double sv[3];
-            shift_vec(E.code, I, sv);
-            const T dox = (T)(a.l_origin[3 * B] + sv[0] - oA[0]);
-            const T doy = (T)(a.l_origin[3 * B + 1] + sv[1] - oA[1]);
-            const T doz = (T)(a.l_origin[3 * B + 2] + sv[2] - oA[2]);
-            const T xi = pi.x - dox, yi = pi.y - doy, zi = pi.z - doz;
-            const int dir = E.code >> 8;
-            int lo = 0, hi = nB;
-            const bool srt = a.l_sorted[B] && nB <= 64;
-            if (srt) {
-                double u[3];
-                sph_dir(dir, u);
-                const float ki_ = (float)((double)xi * u[0] + (double)yi * u[1] + (double)zi * u[2]);
-                const float Rf = (float)R;
-                float kmin = wave_minf(vi ? ki_ - Rf : INFINITY);
-                float kmax = wave_maxf(vi ? ki_ + Rf : -INFINITY);
-                const float eps = 1e-5f * (fabsf(kmin) + fabsf(kmax)) + 1e-6f * Rf;
-                sorted_window(a.skey, a.n, dir, bB, nB, lane, kmin - eps, kmax + eps, lo, hi);
-            }
-            for (int p0 = lo; p0 < hi; p0 += 64) {
-                const int len = min(64, hi - p0);
-                if (lane < len) {
-                    const int t = p0 + lane;
-                    const int jl = srt ? (int)a.sidx[(int64_t)dir * a.n + bB + t] : t;
-                    stage_force_j<T>(tl, lane, bB + jl, pos4, fv4, hf, jl);
-                }
-                wave_sync();
-                // group jg owns slots jg, jg+G, ...; lanes of a group rotate over them
-                const int Lg = (jg < len) ? (len - jg + G - 1) / G : 0;
-                const int Lmax = (len + G - 1) / G;
-                const int s0 = (Lg > 0) ? ii % Lg : 0;
-                for (int t = 0; t < Lmax; t++) {
-                    if (vi && t < Lg) {
-                        int s = s0 + t;
-                        if (s >= Lg) s -= Lg;
-                        const int o = jg + G * s;
-                        const V4 pj = tl.p[o];
-                        const T dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
-                        if (force_pair<T, COMP, true>(dx, dy, dz, pi.w, h2i, ihi, ki, fi.x, fi.y, fi.z, pj, tl.v[o],
-                                                      tl.h2[o], tl.ih[o], ai, &tl.acc[0][0], o))
-                            npairs++;
-                    }
-                }
-                wave_sync();
-                if (lane < len) {
-                    const int p = bB + tl.jl[lane];
-                    const T gx = tl.acc[0][lane], gy = tl.acc[1][lane], gz = tl.acc[2][lane], gu = tl.acc[3][lane];
-                    if (gx != T(0) || gy != T(0) || gz != T(0) || gu != T(0)) {
-                        atomicAdd(&a.ax[p], (double)gx);
-                        atomicAdd(&a.ay[p], (double)gy);
-                        atomicAdd(&a.az[p], (double)gz);
-                        atomicAdd(&a.dudt[p], (double)gu);
-                    }
-                }
-                wave_sync();
-            }
+            wave_sync();
         }
         double sx = ai.ax.total(), sy = ai.ay.total(), sz = ai.az.total(), su = ai.du.total();
         for (int off = CI; off < 64; off <<= 1) {
@@ -605,7 +797,7 @@ __device__ void force_leaf(const ForceArgs& a, int A, FTile<T>& tl, int lane)
     if (lane == 0 && npairs) atomicAdd(&a.counters[CNT_NFORCE], npairs);
 }
 
-template <typename T, bool COMP>
+template <typename T, bool COMP, int PRUNE>
 __global__ __launch_bounds__(256) void k_force(ForceArgs a)
 {
     __shared__ FTile<T> tiles[WAVES_PER_WG];
@@ -613,7 +805,7 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a)
     if (!a.persistent) {
         const int A = uniform(blockIdx.x * WAVES_PER_WG + w);
         if (A >= a.n_leaves) return;
-        force_leaf<T, COMP>(a, A, tiles[w], lane);
+        force_leaf<T, COMP, PRUNE>(a, A, tiles[w], lane);
         return;
     }
     for (int it = 0; it <= a.n_leaves; it++) {
@@ -621,7 +813,7 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a)
         if (t >= a.n_leaves) break;
         const int A = uniform(a.order ? a.order[t] : t);
         if (A < 0 || A >= a.n_leaves) break;
-        force_leaf<T, COMP>(a, A, tiles[w], lane);
+        force_leaf<T, COMP, PRUNE>(a, A, tiles[w], lane);
     }
 }
 
@@ -767,12 +959,17 @@ static sph_status launch_density(sph_ctx* c)
     const int nb = a.persistent ? std::min(resident_wgs(c), blocks_for(c->n_leaves, WAVES_PER_WG))
                                 : blocks_for(c->n_leaves, WAVES_PER_WG);
     if (nb <= 0) return SPH_OK;
-    if (c->prm.precision == SPH_FP64)
-        k_density<double, false><<<nb, 256, 0, c->stream>>>(a);
-    else if (c->prm.precision == SPH_FP32C)
-        k_density<float, true><<<nb, 256, 0, c->stream>>>(a);
-    else
-        k_density<float, false><<<nb, 256, 0, c->stream>>>(a);
+    const bool srt = c->prm.prune == SPH_PRUNE_SORTED;
+    if (c->prm.precision == SPH_FP64) {
+        if (srt) k_density<double, false, PRUNE_SORTED><<<nb, 256, 0, c->stream>>>(a);
+        else k_density<double, false, PRUNE_BOX><<<nb, 256, 0, c->stream>>>(a);
+    } else if (c->prm.precision == SPH_FP32C) {
+        if (srt) k_density<float, true, PRUNE_SORTED><<<nb, 256, 0, c->stream>>>(a);
+        else k_density<float, true, PRUNE_BOX><<<nb, 256, 0, c->stream>>>(a);
+    } else {
+        if (srt) k_density<float, false, PRUNE_SORTED><<<nb, 256, 0, c->stream>>>(a);
+        else k_density<float, false, PRUNE_BOX><<<nb, 256, 0, c->stream>>>(a);
+    }
     SPH_CHECK_LAUNCH();
     return SPH_OK;
 }
@@ -789,7 +986,7 @@ sph_status density_all(sph_ctx* c)
     k_density_reset<<<blocks_for(std::max<int64_t>(c->n, c->n_leaves), 256), 256, 0, c->stream>>>(
         c->n, c->n_leaves, (double*)c->hlo.p, (double*)c->hhi.p, (uint8_t*)c->conv.p, (int*)c->l_active.p);
     SPH_CHECK_LAUNCH();
-    SPH_CHECK_HIP(hipMemsetAsync(cnt, 0, CNT_N * 8, c->stream));
+    SPH_CHECK_HIP(hipMemsetAsync(cnt, 0, CNT_NPAIR * 8, c->stream));
     c->st.relists = 0;
     c->st.t_density_kernels_ms = 0.0;
     c->st.n_density_launches = 0;
@@ -911,12 +1108,17 @@ sph_status force_all(sph_ctx* c)
                                 : blocks_for(c->n_leaves, WAVES_PER_WG);
     SPH_CHECK_HIP(hipEventRecord(c->kev[2], c->stream));
     if (nb > 0) {
-        if (c->prm.precision == SPH_FP64)
-            k_force<double, false><<<nb, 256, 0, c->stream>>>(a);
-        else if (c->prm.precision == SPH_FP32C)
-            k_force<float, true><<<nb, 256, 0, c->stream>>>(a);
-        else
-            k_force<float, false><<<nb, 256, 0, c->stream>>>(a);
+        const bool srt = c->prm.prune == SPH_PRUNE_SORTED;
+        if (c->prm.precision == SPH_FP64) {
+            if (srt) k_force<double, false, PRUNE_SORTED><<<nb, 256, 0, c->stream>>>(a);
+            else k_force<double, false, PRUNE_BOX><<<nb, 256, 0, c->stream>>>(a);
+        } else if (c->prm.precision == SPH_FP32C) {
+            if (srt) k_force<float, true, PRUNE_SORTED><<<nb, 256, 0, c->stream>>>(a);
+            else k_force<float, true, PRUNE_BOX><<<nb, 256, 0, c->stream>>>(a);
+        } else {
+            if (srt) k_force<float, false, PRUNE_SORTED><<<nb, 256, 0, c->stream>>>(a);
+            else k_force<float, false, PRUNE_BOX><<<nb, 256, 0, c->stream>>>(a);
+        }
         SPH_CHECK_LAUNCH();
     }
     SPH_CHECK_HIP(hipEventRecord(c->kev[3], c->stream));

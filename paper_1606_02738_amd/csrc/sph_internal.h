@@ -30,17 +30,29 @@ struct Node {
     int top;          // global top-cell index
     double lo[3], hi[3];   // tight bounding box of the particles
     double hmax;           // largest H in the cell (subtree)
+    double hmin;           // smallest H in the cell
     double c_lo[3], c_sz[3];  // geometric cell corner and edge lengths
+    int merged;            // 1: run of sibling octants merged into one leaf
+    int pad;
 };
 
 // Neighbour-cell list entry of leaf A: leaf B, periodic image and the
-// sort direction to use for the pair.
+// sort direction to use for the pair.  A's list holds every leaf B whose
+// bounding box (image) lies closer than h_A (the radius the list was built
+// for), i.e. the cells the density gather of A needs.
 struct ListEntry {
     int B;
     int code;         // shift index (0..26) | dir << 8
-    float dist;       // box-to-box distance between A and the image of B
-    float pad;
+    double dist;      // box-to-box distance, computed in a canonical order so
+                      // that the entries (A,B) and (B,A) hold the same bits
 };
+
+// Relative margin added to a cell's largest H when its list is built, so
+// that small growth of H during the iteration needs no new list.
+#define SPH_LIST_SKIN 0.05
+
+// Largest leaf extent / smallest H of the leaf in the FP32 modes.
+#define SPH_FP32_EXTENT_RATIO 16.0
 
 __host__ __device__ inline int shift_index(int sx, int sy, int sz) { return (sx + 1) * 9 + (sy + 1) * 3 + (sz + 1); }
 
@@ -65,7 +77,7 @@ enum {
 enum { FI_FLAGS = 0, FI_SCRATCH = 8, FI_NCHILD = 9, FI_NLEAVES = 10, FI_NLIST = 11, FI_NFLAGS = 64 };
 
 // Counters written by kernels (device, int64).
-enum { CNT_UNCONV = 0, CNT_NDENS = 1, CNT_NFORCE = 2, CNT_QUEUE = 3, CNT_QUEUE2 = 4, CNT_DEVAL = 5, CNT_N = 8 };
+enum { CNT_UNCONV = 0, CNT_NDENS = 1, CNT_NFORCE = 2, CNT_QUEUE = 3, CNT_QUEUE2 = 4, CNT_DEVAL = 5, CNT_NPAIR = 6, CNT_N = 8 };
 
 // Leaf arrays (device SoA).
 struct LeafArrays {

@@ -20,6 +20,8 @@ SPH_FP64, SPH_FP32C, SPH_FP32 = 0, 1, 2
 SPH_EXEC_GRID, SPH_EXEC_PERSISTENT = 0, 1
 PRECISIONS = {"fp64": SPH_FP64, "fp32c": SPH_FP32C, "fp32": SPH_FP32}
 EXEC_MODES = {"grid": SPH_EXEC_GRID, "persistent": SPH_EXEC_PERSISTENT}
+SPH_PRUNE_BOX, SPH_PRUNE_SORTED = 0, 1
+PRUNE_MODES = {"box": SPH_PRUNE_BOX, "sorted": SPH_PRUNE_SORTED}
 
 STATUS = {0: "SPH_OK", -1: "SPH_ERR_INVALID", -2: "SPH_ERR_HIP", -3: "SPH_ERR_NOT_CONVERGED",
           -4: "SPH_ERR_H_EXCEEDS_CELL", -5: "SPH_ERR_BOX_TOO_SMALL", -6: "SPH_ERR_ALLOC",
@@ -39,7 +41,7 @@ class Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("eta", C.c_double), ("kernel_gamma", C.c_double),
                 ("h_tol", C.c_double), ("max_h_iter", C.c_int), ("n_split", C.c_int),
                 ("precision", C.c_int), ("exec_mode", C.c_int), ("n_domains", C.c_int),
-                ("persistent_wgs", C.c_int), ("waves_per_wg", C.c_int), ("pad", C.c_int),
+                ("persistent_wgs", C.c_int), ("waves_per_wg", C.c_int), ("prune", C.c_int),
                 ("boxes", C.POINTER(C.c_double))]
 
 
@@ -135,7 +137,7 @@ class SPH:
 
     def __init__(self, boxes, precision="fp32c", exec_mode="grid", gamma=5.0 / 3.0, eta=1.2348,
                  kernel_gamma=math.sqrt(10.0 / 3.0), h_tol=None, max_h_iter=40, n_split=64,
-                 persistent_wgs=0, stream=None):
+                 persistent_wgs=0, prune="box", stream=None):
         import torch
         self._torch = torch
         b = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(-1, 3))
@@ -148,7 +150,8 @@ class SPH:
         p.gamma, p.eta, p.kernel_gamma, p.h_tol = gamma, eta, kernel_gamma, h_tol
         p.max_h_iter, p.n_split, p.precision = max_h_iter, n_split, prec
         p.exec_mode = EXEC_MODES[exec_mode] if isinstance(exec_mode, str) else int(exec_mode)
-        p.n_domains, p.persistent_wgs, p.waves_per_wg, p.pad = self.n_domains, persistent_wgs, 0, 0
+        p.n_domains, p.persistent_wgs, p.waves_per_wg = self.n_domains, persistent_wgs, 0
+        p.prune = PRUNE_MODES[prune] if isinstance(prune, str) else int(prune)
         p.boxes = b.ctypes.data_as(C.POINTER(C.c_double))
         self.params = p
         s = stream if stream is not None else torch.cuda.current_stream()

@@ -51,13 +51,13 @@ def test_exact_lattice_fp64_counts_and_zero_force():
     assert_close(g, o, TOL_FP64, stats=st)
 
 
-@pytest.mark.parametrize("prec,mode", [
-    ("fp64", "grid"), ("fp32c", "grid"),
-    ("fp32c", "persistent"), ("fp64", "persistent")])
-def test_clustered_small(prec, mode):
-    log("case clustered 32^3 %s %s" % (prec, mode))
+@pytest.mark.parametrize("prec,mode,prune", [
+    ("fp64", "grid", "box"), ("fp32c", "grid", "box"), ("fp64", "grid", "sorted"), ("fp32c", "grid", "sorted"),
+    ("fp32c", "persistent", "box"), ("fp64", "persistent", "sorted")])
+def test_clustered_small(prec, mode, prune):
+    log("case clustered 32^3 %s %s %s" % (prec, mode, prune))
     d = gen.clustered(32, n_halos=20, seed=2741)
-    g, st = gpu_run(d, precision=prec, exec_mode=mode)
+    g, st = gpu_run(d, precision=prec, exec_mode=mode, prune=prune)
     o = oracle_run(d)
     log("stats: leaves=%d depth=%d sweeps=%d relists=%d" % (st["n_leaves"], st["depth"], st["sweeps"],
                                                            st["relists"]))
@@ -137,3 +137,32 @@ def test_errors_and_state():
     assert ei.value.status == -5
     sim.close()
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec,prune", [("fp64", "box"), ("fp64", "sorted"), ("fp32c", "box")])
+def test_unsplittable_cell(prec, prune):
+    """150 particles inside a cube of edge 1e-7: the deepest cell level
+    cannot split them, so one leaf holds more than a wave (multi-chunk paths
+    of density, force and sort)."""
+    log("case unsplittable cell %s %s" % (prec, prune))
+    d = gen.lattice(16, vsigma=0.1, seed=21)
+    rng = np.random.default_rng(4)
+    k = 150
+    c = rng.uniform(-5e-8, 5e-8, (k, 3)) + 0.5
+    for a, key in enumerate(("x", "y", "z")):
+        d[key] = np.concatenate([d[key], c[:, a]])
+    for key in ("vx", "vy", "vz"):
+        d[key] = np.concatenate([d[key], rng.normal(0, 0.1, k)])
+    d["u"] = np.concatenate([d["u"], np.ones(k)])
+    d["m"] = np.concatenate([d["m"], np.full(k, d["m"][0])])
+    d["H"] = np.concatenate([d["H"], np.full(k, 1e-6)])
+    n = d["x"].size
+    d["id"] = np.arange(n, dtype=np.int64)
+    d["domain"] = np.zeros(n, dtype=np.int32)
+    g, st = gpu_run(d, precision=prec, prune=prune)
+    assert st["n_unconverged"] == 0
+    o = oracle_run(d)
+    if prec == "fp64":
+        assert_close(g, o, TOL_FP64, stats=st)
+    else:
+        assert_close(g, o, TOL_FP32, counts_exact=False)
