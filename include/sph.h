@@ -91,8 +91,9 @@ typedef struct {
     double *dudt;            /* du/dt (out, force) */
     int64_t *id;             /* optional: carried through the permutation (may be NULL) */
     int32_t *domain;         /* box index of each particle; NULL when n_domains == 1 */
-    int32_t *nngb;           /* optional: #{j : r_ij < H_i}, self included, at the
-                                converged H (out, density; may be NULL) */
+    int32_t *nngb;           /* optional: #{j : r_ij < H_i}, self included (out; may be
+                                NULL).  Written by the density stage at the last H it
+                                evaluated and rewritten by the force stage at the final H */
 } sph_particles;
 
 typedef struct {
@@ -101,7 +102,9 @@ typedef struct {
     int64_t n_nodes;         /* cells of all levels */
     int64_t n_list;          /* neighbour-cell entries (ordered pairs incl. self) */
     int64_t n_pair_tasks;    /* unordered pair tasks (B > A) */
-    int64_t n_dens;          /* sum_i #{j : r_ij < H_i}, self included, last density call */
+    int64_t n_dens;          /* sum_i #{j : r_ij < H_i}, self included, at the final H
+                                (from the last force call; after density alone, at the
+                                last H the density stage evaluated) */
     int64_t n_force;         /* #{unordered i != j : r_ij < max(H_i,H_j)}, last force call */
     int32_t sweeps;          /* density sweeps of the last density call */
     int32_t n_unconverged;   /* particles left unconverged by the last density call */
@@ -142,7 +145,9 @@ sph_status sph_build_cells(sph_ctx* ctx, const sph_particles* p);
 /* Sort stage (Sec. 3.1 "sorted" cells): for every leaf cell and each of the
  * 13 axis directions between neighbouring cells, the particles' projections
  * sorted ascending; used to skip pair candidates whose projections differ by
- * at least the interaction range.  Requires sph_build_cells. */
+ * at least the interaction range (prune = SPH_PRUNE_SORTED).  With
+ * SPH_PRUNE_BOX the interaction kernels do not read this order and the call
+ * only records the stage.  Requires sph_build_cells. */
 sph_status sph_sort_cells(sph_ctx* ctx);
 
 /* Density stage, eq. (rho): sweeps over self and pair interactions computing

@@ -330,7 +330,7 @@ __global__ __launch_bounds__(256) void k_mark_leaves(const Node* __restrict__ no
 
 __global__ __launch_bounds__(256) void k_leaf_fill(Node* nodes, int n_nodes, const int* __restrict__ leafscan,
                                                    int* leaf_node, int* l_begin, int* l_count, double* l_origin,
-                                                   double* l_lo, double* l_hi, double* l_hlist, int* l_dom)
+                                                   double* l_lo, double* l_hi, double* l_hlist, int* l_dom, int* l_top)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_nodes) return;
@@ -351,6 +351,7 @@ __global__ __launch_bounds__(256) void k_leaf_fill(Node* nodes, int n_nodes, con
     }
     l_hlist[id] = nd.hmax * (1.0 + SPH_LIST_SKIN);
     l_dom[id] = nd.domain;
+    l_top[id] = nd.top;
 }
 
 // Cell-relative coordinates (and masses) of every particle in its leaf.
@@ -403,30 +404,65 @@ __device__ inline double box_dist(const double* alo, const double* ahi, const do
     return sqrt(d2);
 }
 
-// Distance between leaf boxes A and B + s, evaluated with the lower-indexed
-// leaf as reference so that it is bitwise the same from both sides.
-__device__ inline double leaf_dist(int A, const Node& NA, int B, const Node& NB, const double* s)
+__constant__ float c_dirs[SPH_NDIR][3] = {
+    {1.f, 0.f, 0.f}, {0.f, 1.f, 0.f}, {0.f, 0.f, 1.f},
+    {0.70710678f, 0.70710678f, 0.f}, {0.70710678f, -0.70710678f, 0.f},
+    {0.70710678f, 0.f, 0.70710678f}, {0.70710678f, 0.f, -0.70710678f},
+    {0.f, 0.70710678f, 0.70710678f}, {0.f, 0.70710678f, -0.70710678f},
+    {0.57735027f, 0.57735027f, 0.57735027f}, {0.57735027f, 0.57735027f, -0.57735027f},
+    {0.57735027f, -0.57735027f, 0.57735027f}, {0.57735027f, -0.57735027f, -0.57735027f}};
+
+__global__ __launch_bounds__(256) void k_wnodes(const Node* __restrict__ nodes, int n_nodes, WNode* __restrict__ w)
 {
-    if (A <= B) return box_dist(NA.lo, NA.hi, NB.lo, NB.hi, s);
-    const double ms[3] = {-s[0], -s[1], -s[2]};
-    return box_dist(NB.lo, NB.hi, NA.lo, NA.hi, ms);
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_nodes) return;
+    const Node& nd = nodes[k];
+    WNode o;
+    for (int a = 0; a < 3; a++) {
+        o.lo[a] = __double2float_rd(nd.lo[a]);
+        o.hi[a] = __double2float_ru(nd.hi[a]);
+    }
+    o.first_child = nd.first_child;
+    o.n_child = nd.n_child;
+    o.count = nd.count;
+    o.leaf = nd.leaf;
+    w[k] = o;
+}
+
+__device__ inline float box_dist_f(const float* alo, const float* ahi, const float* blo, const float* bhi,
+                                   const float* s)
+{
+    float d2 = 0.f;
+    for (int a = 0; a < 3; a++) {
+        const float lo = blo[a] + s[a], hi = bhi[a] + s[a];
+        float g = 0.f;
+        if (lo > ahi[a]) g = lo - ahi[a];
+        else if (alo[a] > hi) g = alo[a] - hi;
+        d2 += g * g;
+    }
+    return sqrtf(d2);
 }
 
 template <bool FILL>
-__global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restrict__ leaf_node, const Node* __restrict__ nodes,
+__global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restrict__ leaf_node, const WNode* __restrict__ wn,
+                                              const double* __restrict__ l_lo, const double* __restrict__ l_hi,
+                                              const int* __restrict__ l_dom, const int* __restrict__ l_top,
                                               const DomainInfo* __restrict__ di, const double* __restrict__ l_hlist,
                                               int* counts, const int* __restrict__ l_off, ListEntry* __restrict__ list,
-                                              int list_cap, int* flags)
+                                              int list_cap, int with_dir, int* flags)
 {
     const int A = blockIdx.x * blockDim.x + threadIdx.x;
     if (A >= n_leaves) return;
-    const Node& NA = nodes[leaf_node[A]];
-    const DomainInfo& I = di[NA.domain];
-    const int loc = NA.top - I.top_offset;
+    const DomainInfo& I = di[l_dom[A]];
+    const int loc = l_top[A] - I.top_offset;
     const int tc[3] = {loc / (I.n_top[2] * I.n_top[1]), (loc / I.n_top[2]) % I.n_top[1], loc % I.n_top[2]};
     const double hA = l_hlist[A];
-    const double prune = hA * (1.0 + 1e-12);
-    const double ca[3] = {0.5 * (NA.lo[0] + NA.hi[0]), 0.5 * (NA.lo[1] + NA.hi[1]), 0.5 * (NA.lo[2] + NA.hi[2])};
+    // conservative float pruning radius: the float boxes are rounded outward;
+    // the absolute term covers the rounding of box + periodic shift in float
+    const float prune = (float)(hA * (1.0 + 1e-5) + 1e-6 * fmax(fmax(I.L[0], I.L[1]), I.L[2]));
+    const WNode& WA = wn[leaf_node[A]];
+    const double alo[3] = {l_lo[3 * A], l_lo[3 * A + 1], l_lo[3 * A + 2]};
+    const double ahi[3] = {l_hi[3 * A], l_hi[3 * A + 1], l_hi[3 * A + 2]};
     int cnt = 0;
     int out = FILL ? l_off[A] : 0;
     const int out_end = FILL ? l_off[A + 1] : 0;
@@ -437,37 +473,51 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
         const int o[3] = {sx, sy, sz};
         int nc[3], ps[3];
         double sv[3];
+        float svf[3];
         for (int a = 0; a < 3; a++) {
             nc[a] = tc[a] + o[a];
             ps[a] = 0;
             if (nc[a] < 0) { nc[a] += I.n_top[a]; ps[a] = -1; }
             else if (nc[a] >= I.n_top[a]) { nc[a] -= I.n_top[a]; ps[a] = 1; }
             sv[a] = ps[a] * I.L[a];
+            svf[a] = (float)sv[a];
         }
         const int code_shift = shift_index(ps[0], ps[1], ps[2]);
         int sp = 0;
         stack[sp++] = I.top_offset + (nc[0] * I.n_top[1] + nc[1]) * I.n_top[2] + nc[2];
         while (sp > 0) {
-            const Node& nd = nodes[stack[--sp]];
+            const WNode nd = wn[stack[--sp]];
             if (nd.count == 0) continue;
+            if (box_dist_f(WA.lo, WA.hi, nd.lo, nd.hi, svf) > prune) continue;
             if (nd.n_child == 0) {
-                const double d = leaf_dist(A, NA, nd.leaf, nd, sv);
+                // exact distance between the leaf boxes, in the canonical order
+                const int B = nd.leaf;
+                const double blo[3] = {l_lo[3 * B], l_lo[3 * B + 1], l_lo[3 * B + 2]};
+                const double bhi[3] = {l_hi[3 * B], l_hi[3 * B + 1], l_hi[3 * B + 2]};
+                double d;
+                if (A <= B) {
+                    d = box_dist(alo, ahi, blo, bhi, sv);
+                } else {
+                    const double ms[3] = {-sv[0], -sv[1], -sv[2]};
+                    d = box_dist(blo, bhi, alo, ahi, ms);
+                }
                 if (!(d < hA)) continue;
                 if (FILL) {
                     if (out < out_end && out < list_cap) {
-                        // sort direction: the one of 13 most aligned with the centre offset
-                        double cv[3];
-                        for (int a = 0; a < 3; a++) cv[a] = 0.5 * (nd.lo[a] + nd.hi[a]) + sv[a] - ca[a];
                         int best = 0;
-                        double bv = -1.0;
-                        for (int k = 0; k < SPH_NDIR; k++) {
-                            double u[3];
-                            sph_dir(k, u);
-                            const double v = fabs(cv[0] * u[0] + cv[1] * u[1] + cv[2] * u[2]);
-                            if (v > bv) { bv = v; best = k; }
+                        if (with_dir) {
+                            // sort direction: the one of 13 most aligned with the centre offset
+                            float cv[3];
+                            for (int a = 0; a < 3; a++)
+                                cv[a] = (float)(0.5 * (blo[a] + bhi[a]) + sv[a] - 0.5 * (alo[a] + ahi[a]));
+                            float bv = -1.f;
+                            for (int k = 0; k < SPH_NDIR; k++) {
+                                const float v = fabsf(cv[0] * c_dirs[k][0] + cv[1] * c_dirs[k][1] + cv[2] * c_dirs[k][2]);
+                                if (v > bv) { bv = v; best = k; }
+                            }
                         }
                         ListEntry e;
-                        e.B = nd.leaf;
+                        e.B = B;
                         e.code = code_shift | (best << 8);
                         e.dist = d;
                         list[out] = e;
@@ -478,7 +528,6 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
                 }
                 cnt++;
             } else {
-                if (box_dist(NA.lo, NA.hi, nd.lo, nd.hi, sv) > prune) continue;
                 if (sp + nd.n_child > WALK_STACK) {
                     atomicOr(flags, FLAG_INVALID);
                     continue;
@@ -688,22 +737,28 @@ sph_status relist(sph_ctx* c)
     int* counts = (int*)c->l_off.p;
     int* flags = (int*)c->flags.p;
     SPH_CHECK_HIP(hipMemsetAsync(counts, 0, (size_t)(nL + 1) * sizeof(int), c->stream));
-    k_walk<false><<<blocks_for(nL, 128), 128, 0, c->stream>>>(nL, (const int*)c->leaf_node.p, nodes,
+    const int with_dir = c->prm.prune == SPH_PRUNE_SORTED;
+    k_walk<false><<<blocks_for(nL, 128), 128, 0, c->stream>>>(nL, (const int*)c->leaf_node.p, (const WNode*)c->wnodes.p,
+                                                             (const double*)c->l_lo.p, (const double*)c->l_hi.p,
+                                                             (const int*)c->l_dom.p, (const int*)c->l_cnt.p,
                                                              (const DomainInfo*)c->dom_d.p, (const double*)c->l_hlist.p,
-                                                             counts, nullptr, nullptr, 0, flags);
+                                                             counts, nullptr, nullptr, 0, with_dir, flags);
     SPH_CHECK_LAUNCH();
     SPH_TRY(scan_exclusive(c, counts, counts, nL + 1, flags + FI_NLIST));
     int total = 0;
     SPH_TRY(read_int(c, flags + FI_NLIST, &total));
     if (total < 0) return SPH_ERR_ALLOC;
     SPH_TRY(buf_ensure(c->list, (size_t)std::max(total, 1) * sizeof(ListEntry)));
-    k_walk<true><<<blocks_for(nL, 128), 128, 0, c->stream>>>(nL, (const int*)c->leaf_node.p, nodes,
+    k_walk<true><<<blocks_for(nL, 128), 128, 0, c->stream>>>(nL, (const int*)c->leaf_node.p, (const WNode*)c->wnodes.p,
+                                                            (const double*)c->l_lo.p, (const double*)c->l_hi.p,
+                                                            (const int*)c->l_dom.p, (const int*)c->l_cnt.p,
                                                             (const DomainInfo*)c->dom_d.p, (const double*)c->l_hlist.p,
                                                             nullptr, (const int*)c->l_off.p, (ListEntry*)c->list.p,
-                                                            total, flags);
+                                                            total, with_dir, flags);
     SPH_CHECK_LAUNCH();
     c->n_list = total;
-    return task_order(c);
+    if (c->prm.exec_mode == SPH_EXEC_PERSISTENT) return task_order(c);
+    return SPH_OK;
 }
 
 sph_status build_all(sph_ctx* c)
@@ -863,12 +918,13 @@ sph_status build_all(sph_ctx* c)
     SPH_TRY(buf_ensure(c->l_off, (L1 + 1) * 4));
     SPH_TRY(buf_ensure(c->l_active, L1 * 4));
     SPH_TRY(buf_ensure(c->l_sorted, L1 * 4));
+    SPH_TRY(buf_ensure(c->l_cnt, L1 * 4));
     SPH_TRY(buf_ensure(c->l_cost, L1 * 8));
     SPH_TRY(buf_ensure(c->l_order, L1 * 4));
     k_leaf_fill<<<blocks_for(n_nodes, 256), 256, 0, c->stream>>>(
         (Node*)c->nodes.p, n_nodes, (const int*)c->leafscan.p, (int*)c->leaf_node.p, (int*)c->l_begin.p,
         (int*)c->l_count.p, (double*)c->l_origin.p, (double*)c->l_lo.p, (double*)c->l_hi.p, (double*)c->l_hlist.p,
-        (int*)c->l_dom.p);
+        (int*)c->l_dom.p, (int*)c->l_cnt.p);
     SPH_CHECK_LAUNCH();
 
     // 6. cell-relative coordinates
@@ -887,6 +943,9 @@ sph_status build_all(sph_ctx* c)
     SPH_CHECK_LAUNCH();
 
     // 7. neighbour-cell lists
+    SPH_TRY(buf_ensure(c->wnodes, (size_t)n_nodes * sizeof(WNode)));
+    k_wnodes<<<blocks_for(n_nodes, 256), 256, 0, c->stream>>>((const Node*)c->nodes.p, n_nodes, (WNode*)c->wnodes.p);
+    SPH_CHECK_LAUNCH();
     SPH_TRY(relist(c));
     SPH_TRY(read_int(c, flags, &fl));
     if (fl & FLAG_INVALID) return SPH_ERR_INVALID;
@@ -897,6 +956,12 @@ sph_status build_all(sph_ctx* c)
 
 sph_status sort_all(sph_ctx* c)
 {
+    // the per-direction order feeds only the sorted-axis pruning mode; with
+    // box pruning the interaction kernels select candidates without it
+    if (c->prm.prune != SPH_PRUNE_SORTED) {
+        c->sorted = true;
+        return SPH_OK;
+    }
     const int64_t n = c->n;
     const int nL = c->n_leaves;
     SPH_TRY(buf_ensure(c->skey, (size_t)n * SPH_NDIR * 4));

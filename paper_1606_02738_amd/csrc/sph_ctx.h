@@ -48,6 +48,7 @@ struct sph_ctx {
     const void* keys_sorted = nullptr;  // sorted Morton keys of the last build
     DevBuf tmp;                   // permutation scratch (8 B per particle)
     DevBuf nodes, nchild, coff;   // octree
+    DevBuf wnodes;                // compact cells for the list walk
     DevBuf leafmark, leafscan;    // per particle
     DevBuf leaf_node;             // leaf -> node
     DevBuf l_begin, l_count, l_origin, l_lo, l_hi, l_hlist, l_dom, l_off, l_active, l_sorted, l_cnt, l_cost, l_order;

@@ -36,6 +36,14 @@ __device__ inline void spline_w_dw(T q, T& w, T& dw)
     }
 }
 
+// q^2 w''(q) + 2 q w'(q), the q-part of the second H-derivative of H^3 W
+template <typename T>
+__device__ inline T spline_d2(T q, T dw)
+{
+    const T d2 = (q <= T(0.5)) ? (T(36) * q - T(12)) : T(12) * (T(1) - q);
+    return q * (q * d2 + T(2) * dw);
+}
+
 template <typename T>
 __device__ inline T spline_dw(T q)
 {
@@ -248,6 +256,8 @@ __device__ inline int load_batch(const ListEntry* list, int eb, int nbt, int lan
 template <typename T, bool COMP, int PRUNE>
 __device__ void density_leaf(const DensArgs& a, int A, DTile<T>& L, int lane)
 {
+    // FP32 modes accept a small final Newton update by second-order expansion
+    constexpr bool EXTRAP = sizeof(T) == 4;
     typedef typename vec4<T>::type V4;
     const V4* pos4 = (const V4*)a.pos4;
     const int bA = a.l_begin[A], nA = a.l_count[A];
@@ -270,6 +280,7 @@ __device__ void density_leaf(const DensArgs& a, int A, DTile<T>& L, int lane)
         const double Hd = a.H[i];
         const T Hi = (T)Hd, H2 = Hi * Hi, invH = T(1) / Hi;
         Acc<T, COMP> sw, sd;
+        T s2 = T(0);
         int cnt = 0;
         const double hA = wave_max(act ? Hd : 0.0);
         // bounding box of the active i (A frame) and the squared pruning radius
@@ -315,6 +326,7 @@ __device__ void density_leaf(const DensArgs& a, int A, DTile<T>& L, int lane)
                             spline_w_dw(q, w, dw);
                             sw.add(q4.w * w);
                             sd.add(q4.w * (T(3) * w + q * dw));
+                            if (EXTRAP) s2 += q4.w * spline_d2(q, dw);
                             cnt++;
                         }
                     }
@@ -351,6 +363,7 @@ __device__ void density_leaf(const DensArgs& a, int A, DTile<T>& L, int lane)
                                 spline_w_dw(q, w, dw);
                                 sw.add(q4.w * w);
                                 sd.add(q4.w * (T(3) * w + q * dw));
+                                if (EXTRAP) s2 += q4.w * spline_d2(q, dw);
                                 cnt++;
                             }
                         }
@@ -364,10 +377,11 @@ __device__ void density_leaf(const DensArgs& a, int A, DTile<T>& L, int lane)
             }
             wave_sync();
         }
-        double Sw = sw.total(), Sd = sd.total();
+        double Sw = sw.total(), Sd = sd.total(), S2 = (double)s2;
         for (int off = CI; off < 64; off <<= 1) {
             Sw += __shfl_xor(Sw, off);
             Sd += __shfl_xor(Sd, off);
+            if (EXTRAP) S2 += __shfl_xor(S2, off);
             cnt += __shfl_xor(cnt, off);
         }
         {
@@ -384,6 +398,7 @@ __device__ void density_leaf(const DensArgs& a, int A, DTile<T>& L, int lane)
             const double C = a.C_fac * a.m[i];
             const double f = INV_PI_8 * Sw - C;              // rho H^3 - C
             const double fp = INV_PI_8 * (3.0 * Sw - Sd) / H; // 3 H^2 rho + H^3 drho/dH
+            const double F2 = INV_PI_8 * S2 / (H * H);         // d^2 (rho H^3) / dH^2
             a.rho[i] = rho;
             a.drho[i] = drho;
             if (a.nngb) a.nngb[i] = cnt;
@@ -397,13 +412,29 @@ __device__ void density_leaf(const DensArgs& a, int A, DTile<T>& L, int lane)
                     done = true;
                 } else {
                     double Hn = H - f / fp;
-                    if (!(Hn > lo && Hn < hi) || !isfinite(Hn)) Hn = isinf(hi) ? 2.0 * H : 0.5 * (lo + hi);
+                    bool newton = true;
+                    if (!(Hn > lo && Hn < hi) || !isfinite(Hn)) {
+                        Hn = isinf(hi) ? 2.0 * H : 0.5 * (lo + hi);
+                        newton = false;
+                    }
                     // at most doubling per sweep: a far-off step would only force
                     // needless list and grid rebuilds before the bracket closes
                     if (Hn > 2.0 * H) Hn = 2.0 * H;
                     if (Hn > hlim) Hn = hlim;
-                    if (fabs(Hn - H) <= 4.0 * 2.220446049250313e-16 * H) {
+                    const double dH = Hn - H;
+                    if (fabs(dH) <= 4.0 * 2.220446049250313e-16 * H) {
                         done = true;  // stalled at round-off: accept H
+                    } else if (EXTRAP && newton && fabs(dH) <= 1e-3 * H && Hn <= a.l_hlist[A] && Hn <= s0min &&
+                               fabs(0.5 * F2 * dH * dH) <= 0.5 * a.h_tol * C) {
+                        // accept the Newton update: rho H^3 and its H-derivative at Hn
+                        // from their second-order expansion around H
+                        const double F1 = INV_PI_8 * Sw + fp * dH + 0.5 * F2 * dH * dH;
+                        const double F1p = fp + F2 * dH;
+                        const double H3 = Hn * Hn * Hn;
+                        a.H[i] = Hn;
+                        a.rho[i] = F1 / H3;
+                        a.drho[i] = F1p / H3 - 3.0 * F1 / (H3 * Hn);
+                        done = true;
                     } else {
                         a.H[i] = Hn;
                         a.hlo[i] = lo;
@@ -519,6 +550,7 @@ struct ForceArgs {
     double* ay;
     double* az;
     double* dudt;
+    int32_t* nngb;      // #{j : r_ij < H_i} incl. self at the final H (may be NULL)
     unsigned long long* counters;
     const int* order;
     int persistent;
@@ -532,6 +564,7 @@ struct FTile {
     T ih[64];                      // 1/H
     T acc[4][64];                  // j-side sums
     int jl[64];                    // local index in B
+    int jn[64];                    // j-side neighbour counts (r < H_j)
     EBatch<T> e;
 };
 
@@ -540,14 +573,18 @@ struct FAcc {
     Acc<T, COMP> ax, ay, az, du;
 };
 
-// One pair (i, j), d = x_i - x_j.  Returns true if within max(H_i, H_j).
+// One pair (i, j), d = x_i - x_j.  Returns true if within max(H_i, H_j);
+// counts the pair for i if r < H_i (and for j through jn if r < H_j).
 template <typename T, bool COMP, bool JSIDE>
 __device__ inline bool force_pair(T dx, T dy, T dz, T mi, T h2i, T ihi, T ki, T vxi, T vyi, T vzi,
                                   const typename vec4<T>::type& pj, const typename vec4<T>::type& fj, T h2j, T ihj,
-                                  FAcc<T, COMP>& ai, T* accj, int o)
+                                  FAcc<T, COMP>& ai, T* accj, int* jn, int o, int& ni)
 {
     const T r2 = dx * dx + dy * dy + dz * dz;
-    if (!(r2 < fmax(h2i, h2j)) || !(r2 > T(0))) return false;
+    if (!(r2 < fmax(h2i, h2j))) return false;
+    if (r2 < h2i) ni++;
+    if (JSIDE && r2 < h2j) atomicAdd(&jn[o], 1);
+    if (!(r2 > T(0))) return true;  // coincident particles exert no force
     const T ir = T(1) / sqrt(r2);
     const T r = r2 * ir;
     const T Fi = ki * spline_dw(r * ihi);      // A_i dW/dr(r, H_i)
@@ -584,6 +621,7 @@ __device__ inline void stage_force_j(FTile<T>& tl, int slot, const typename vec4
     tl.acc[2][slot] = 0;
     tl.acc[3][slot] = 0;
     tl.jl[slot] = jl;
+    tl.jn[slot] = 0;
 }
 
 template <typename T, bool COMP, int PRUNE>
@@ -597,7 +635,7 @@ __device__ void force_leaf(const ForceArgs& a, int A, FTile<T>& tl, int lane)
     const double oA[3] = {a.l_origin[3 * A], a.l_origin[3 * A + 1], a.l_origin[3 * A + 2]};
     const DomainInfo& I = a.di[a.l_dom[A]];
     const int e0 = a.l_off[A], e1 = a.l_off[A + 1];
-    unsigned long long npairs = 0;
+    unsigned long long npairs = 0, ndens_w = 0;
     for (int c0 = 0; c0 < nA; c0 += 64) {
         const int nc = min(64, nA - c0);
         const int lg = chunk_log2(nc);
@@ -611,6 +649,7 @@ __device__ void force_leaf(const ForceArgs& a, int A, FTile<T>& tl, int lane)
         const T h2i = Hi * Hi, ihi = T(1) / Hi;
         const T ki = fi.w * T(INV_PI_8) * ihi * ihi * ihi * ihi;
         FAcc<T, COMP> ai;
+        int nni = (jg == 0 && vi) ? 1 : 0;  // neighbour count of i, self included
         const double hA = wave_max(vi ? (double)Hi : 0.0);
         const T big = T(1e30);
         const T bxl = wave_min_t<T>(vi ? pi.x : big), bxh = wave_max_t<T>(vi ? pi.x : -big);
@@ -632,7 +671,7 @@ __device__ void force_leaf(const ForceArgs& a, int A, FTile<T>& tl, int lane)
                     const V4 pj = tl.p[b];
                     const T dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
                     if (force_pair<T, COMP, true>(dx, dy, dz, pi.w, h2i, ihi, ki, fi.x, fi.y, fi.z, pj, tl.v[b],
-                                                  tl.h2[b], tl.ih[b], ai, &tl.acc[0][0], b))
+                                                  tl.h2[b], tl.ih[b], ai, &tl.acc[0][0], tl.jn, b, nni))
                         npairs++;
                 }
             }
@@ -642,6 +681,7 @@ __device__ void force_leaf(const ForceArgs& a, int A, FTile<T>& tl, int lane)
                 ai.ay.add(tl.acc[1][ii]);
                 ai.az.add(tl.acc[2][ii]);
                 ai.du.add(tl.acc[3][ii]);
+                nni += tl.jn[ii];
             }
             wave_sync();
         } else {
@@ -658,7 +698,7 @@ __device__ void force_leaf(const ForceArgs& a, int A, FTile<T>& tl, int lane)
                     const V4 pj = tl.p[t];
                     const T dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
                     if (force_pair<T, COMP, false>(dx, dy, dz, pi.w, h2i, ihi, ki, fi.x, fi.y, fi.z, pj, tl.v[t],
-                                                   tl.h2[t], tl.ih[t], ai, nullptr, t))
+                                                   tl.h2[t], tl.ih[t], ai, nullptr, nullptr, t, nni))
                         if (p0 + t > c0 + ii) npairs++;
                 }
                 wave_sync();
@@ -749,11 +789,12 @@ __device__ void force_leaf(const ForceArgs& a, int A, FTile<T>& tl, int lane)
                             const V4 pj = tl.p[o];
                             const T dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
                             if (force_pair<T, COMP, true>(dx, dy, dz, pi.w, h2i, ihi, ki, fi.x, fi.y, fi.z, pj, tl.v[o],
-                                                          tl.h2[o], tl.ih[o], ai, &tl.acc[0][0], o))
+                                                          tl.h2[o], tl.ih[o], ai, &tl.acc[0][0], tl.jn, o, nni))
                                 npairs++;
                         }
                     }
                     wave_sync();
+                    int jcnt = 0;
                     if (lane < len) {
                         const int p = bB + tl.jl[lane];
                         const T gx = tl.acc[0][lane], gy = tl.acc[1][lane], gz = tl.acc[2][lane], gu = tl.acc[3][lane];
@@ -763,7 +804,10 @@ __device__ void force_leaf(const ForceArgs& a, int A, FTile<T>& tl, int lane)
                             atomicAdd(&a.az[p], (double)gz);
                             atomicAdd(&a.dudt[p], (double)gu);
                         }
+                        jcnt = tl.jn[lane];
+                        if (jcnt && a.nngb) atomicAdd(&a.nngb[p], jcnt);
                     }
+                    ndens_w += jcnt;
                     wave_sync();
                     if (direct) break;
                 }
@@ -786,15 +830,22 @@ __device__ void force_leaf(const ForceArgs& a, int A, FTile<T>& tl, int lane)
             sz += __shfl_xor(sz, off);
             su += __shfl_xor(su, off);
         }
+        for (int off = CI; off < 64; off <<= 1) nni += __shfl_xor(nni, off);
         if (jg == 0 && vi) {
             atomicAdd(&a.ax[i], sx);
             atomicAdd(&a.ay[i], sy);
             atomicAdd(&a.az[i], sz);
             atomicAdd(&a.dudt[i], su);
+            if (a.nngb) atomicAdd(&a.nngb[i], nni);
+            ndens_w += nni;
         }
     }
-    for (int off = 32; off > 0; off >>= 1) npairs += __shfl_xor(npairs, off);
+    for (int off = 32; off > 0; off >>= 1) {
+        npairs += __shfl_xor(npairs, off);
+        ndens_w += __shfl_xor(ndens_w, off);
+    }
     if (lane == 0 && npairs) atomicAdd(&a.counters[CNT_NFORCE], npairs);
+    if (lane == 0 && ndens_w) atomicAdd(&a.counters[CNT_NDENS_F], ndens_w);
 }
 
 template <typename T, bool COMP, int PRUNE>
@@ -1080,6 +1131,8 @@ sph_status force_all(sph_ctx* c)
     SPH_CHECK_HIP(hipMemsetAsync(c->P.dudt, 0, nb8, c->stream));
     SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_NFORCE], 0, 8, c->stream));
     SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_QUEUE2], 0, 8, c->stream));
+    SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_NDENS_F], 0, 8, c->stream));
+    if (c->P.nngb) SPH_CHECK_HIP(hipMemsetAsync(c->P.nngb, 0, (size_t)c->n * 4, c->stream));
     ForceArgs a;
     a.n_leaves = c->n_leaves;
     a.n = c->n;
@@ -1101,6 +1154,7 @@ sph_status force_all(sph_ctx* c)
     a.ay = c->P.ay;
     a.az = c->P.az;
     a.dudt = c->P.dudt;
+    a.nngb = c->P.nngb;
     a.counters = cnt;
     a.persistent = c->prm.exec_mode == SPH_EXEC_PERSISTENT;
     a.order = a.persistent ? (const int*)c->l_order.p : nullptr;
@@ -1123,9 +1177,11 @@ sph_status force_all(sph_ctx* c)
     }
     SPH_CHECK_HIP(hipEventRecord(c->kev[3], c->stream));
     SPH_CHECK_HIP(hipEventRecord(c->ev[5], c->stream));
-    unsigned long long nf = 0;
+    unsigned long long nf = 0, ndf = 0;
     SPH_CHECK_HIP(hipMemcpyAsync(&nf, &cnt[CNT_NFORCE], 8, hipMemcpyDeviceToHost, c->stream));
+    SPH_CHECK_HIP(hipMemcpyAsync(&ndf, &cnt[CNT_NDENS_F], 8, hipMemcpyDeviceToHost, c->stream));
     SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
+    c->st.n_dens = (int64_t)ndf;  // exact at the final H
     {
         float ms = 0.f;
         SPH_CHECK_HIP(hipEventElapsedTime(&ms, c->kev[2], c->kev[3]));

@@ -36,6 +36,16 @@ struct Node {
     int pad;
 };
 
+// Compact copy of a cell for the list walk: bounding box rounded outward to
+// float, children, particle count and leaf id.
+struct WNode {
+    float lo[3], hi[3];
+    int first_child;
+    int n_child;
+    int count;
+    int leaf;
+};
+
 // Neighbour-cell list entry of leaf A: leaf B, periodic image and the
 // sort direction to use for the pair.  A's list holds every leaf B whose
 // bounding box (image) lies closer than h_A (the radius the list was built
@@ -77,7 +87,7 @@ enum {
 enum { FI_FLAGS = 0, FI_SCRATCH = 8, FI_NCHILD = 9, FI_NLEAVES = 10, FI_NLIST = 11, FI_NFLAGS = 64 };
 
 // Counters written by kernels (device, int64).
-enum { CNT_UNCONV = 0, CNT_NDENS = 1, CNT_NFORCE = 2, CNT_QUEUE = 3, CNT_QUEUE2 = 4, CNT_DEVAL = 5, CNT_NPAIR = 6, CNT_N = 8 };
+enum { CNT_UNCONV = 0, CNT_NDENS = 1, CNT_NFORCE = 2, CNT_QUEUE = 3, CNT_QUEUE2 = 4, CNT_DEVAL = 5, CNT_NPAIR = 6, CNT_NDENS_F = 7, CNT_N = 8 };
 
 // Leaf arrays (device SoA).
 struct LeafArrays {
