@@ -215,9 +215,11 @@ struct DensArgs {
     int persistent;
 };
 
+#define NTD 4  // neighbour cells per two-phase batch (density)
+
 template <typename T>
 struct DTile {
-    typename vec4<T>::type p[64];  // selected particles of B (B frame), w = m
+    typename vec4<T>::type p[NTD][64];  // selected particles of B (B frame), w = m
     EBatch<T> e;
 };
 
@@ -299,81 +301,106 @@ __device__ void density_leaf(const DensArgs& a, int A, DTile<T>& L, int lane)
                 const int n0 = L.e.n[0];
                 if (lane < n0) pf = pos4[L.e.b[0] + lane];
             }
-            for (int k = 0; k < nv; k++) {
-                const int bB = L.e.b[k], nB = L.e.n[k];
-                const T dox = L.e.ox[k], doy = L.e.oy[k], doz = L.e.oz[k];
-                const T xi = pi.x - dox, yi = pi.y - doy, zi = pi.z - doz;  // i in B's frame
-                int len = 0;
-                if (PRUNE == PRUNE_BOX && nB <= 64) {
-                    const V4 pj = pf;
-                    if (k + 1 < nv) {
-                        const int n1 = L.e.n[k + 1];
-                        if (lane < n1) pf = pos4[L.e.b[k + 1] + lane];
-                    }
-                    const bool in = lane < nB && box_d2<T>(pj.x, pj.y, pj.z, bxl - dox, byl - doy, bzl - doz,
-                                                            bxh - dox, byh - doy, bzh - doz) < hA2;
-                    const unsigned long long mk = __ballot(in);
-                    if (in) L.p[mask_rank(mk, lane)] = pj;
-                    len = __popcll(mk);
-                    wave_sync();
-                    for (int t = jg; t < len; t += G) {
-                        const V4 q4 = L.p[t];
-                        const T dx = q4.x - xi, dy = q4.y - yi, dz = q4.z - zi;
-                        const T r2 = dx * dx + dy * dy + dz * dz;
-                        if (act && r2 < H2) {
-                            const T q = sqrt(r2) * invH;
-                            T w, dw;
-                            spline_w_dw(q, w, dw);
-                            sw.add(q4.w * w);
-                            sd.add(q4.w * (T(3) * w + q * dw));
-                            if (EXTRAP) s2 += q4.w * spline_d2(q, dw);
-                            cnt++;
+            // accumulate one in-range pair (i, particle q4 of B)
+            auto dens_acc = [&](const V4& q4, T r2) {
+                const T q = sqrt(r2) * invH;
+                T w, dw;
+                spline_w_dw(q, w, dw);
+                sw.add(q4.w * w);
+                sd.add(q4.w * (T(3) * w + q * dw));
+                if (EXTRAP) s2 += q4.w * spline_d2(q, dw);
+                cnt++;
+            };
+            // Pairs of cells in batches of NTD: phase 1 stages each neighbour
+            // cell and records the in-range pairs of every lane as bits of a
+            // mask; phase 2 evaluates only those pairs.
+            for (int k0 = 0; k0 < nv; k0 += NTD) {
+                unsigned long long msk[NTD];
+                T tox[NTD], toy[NTD], toz[NTD];
+#pragma unroll
+                for (int u = 0; u < NTD; u++) {
+                    msk[u] = 0ull;
+                    tox[u] = toy[u] = toz[u] = T(0);
+                    const int k = k0 + u;
+                    if (k >= nv) continue;
+                    const int bB = L.e.b[k], nB = L.e.n[k];
+                    const T dox = L.e.ox[k], doy = L.e.oy[k], doz = L.e.oz[k];
+                    tox[u] = dox;
+                    toy[u] = doy;
+                    toz[u] = doz;
+                    const T xi = pi.x - dox, yi = pi.y - doy, zi = pi.z - doz;  // i in B's frame
+                    V4* tile = L.p[u];
+                    if (PRUNE == PRUNE_BOX && nB <= 64) {
+                        const V4 pj = pf;
+                        if (k + 1 < nv) {
+                            const int n1 = L.e.n[k + 1];
+                            if (lane < n1) pf = pos4[L.e.b[k + 1] + lane];
                         }
-                    }
-                    wave_sync();
-                } else {
-                    // sorted-axis window (or a cell too large for one tile)
-                    int lo = 0, hi = nB;
-                    const int dir = L.e.dir[k];
-                    const bool srt = PRUNE == PRUNE_SORTED && a.l_sorted[L.e.B[k]] && nB <= 64;
-                    if (srt) {
-                        double u[3];
-                        sph_dir(dir, u);
-                        const float ki = (float)((double)xi * u[0] + (double)yi * u[1] + (double)zi * u[2]);
-                        float kmin = wave_minf(act ? ki - (float)Hd : INFINITY);
-                        float kmax = wave_maxf(act ? ki + (float)Hd : -INFINITY);
-                        const float eps = 1e-5f * (fabsf(kmin) + fabsf(kmax)) + 1e-6f * (float)hA;
-                        sorted_window(a.skey, a.n, dir, bB, nB, lane, kmin - eps, kmax + eps, lo, hi);
-                    }
-                    for (int p0 = lo; p0 < hi; p0 += 64) {
-                        len = min(64, hi - p0);
-                        if (lane < len) {
-                            const int t = p0 + lane;
-                            const int jl = srt ? (int)a.sidx[(int64_t)dir * a.n + bB + t] : t;
-                            L.p[lane] = pos4[bB + jl];
-                        }
+                        const bool in = lane < nB && box_d2<T>(pj.x, pj.y, pj.z, bxl - dox, byl - doy, bzl - doz,
+                                                                bxh - dox, byh - doy, bzh - doz) < hA2;
+                        const unsigned long long mk = __ballot(in);
+                        if (in) tile[mask_rank(mk, lane)] = pj;
+                        const int len = __popcll(mk);
                         wave_sync();
-                        for (int t = jg; t < len; t += G) {
-                            const V4 q4 = L.p[t];
-                            const T dx = q4.x - xi, dy = q4.y - yi, dz = q4.z - zi;
-                            const T r2 = dx * dx + dy * dy + dz * dz;
-                            if (act && r2 < H2) {
-                                const T q = sqrt(r2) * invH;
-                                T w, dw;
-                                spline_w_dw(q, w, dw);
-                                sw.add(q4.w * w);
-                                sd.add(q4.w * (T(3) * w + q * dw));
-                                if (EXTRAP) s2 += q4.w * spline_d2(q, dw);
-                                cnt++;
+                        if (act) {
+                            unsigned long long m = 0ull;
+                            for (int s = 0, t = jg; t < len; s++, t += G) {
+                                const V4 q4 = tile[t];
+                                const T dx = q4.x - xi, dy = q4.y - yi, dz = q4.z - zi;
+                                if (dx * dx + dy * dy + dz * dz < H2) m |= 1ull << s;
                             }
+                            msk[u] = m;
                         }
-                        wave_sync();
-                    }
-                    if (PRUNE == PRUNE_BOX && k + 1 < nv) {
-                        const int n1 = L.e.n[k + 1];
-                        if (lane < n1) pf = pos4[L.e.b[k + 1] + lane];
+                    } else {
+                        // sorted-axis window (or a cell too large for one tile): one phase
+                        int lo = 0, hi = nB;
+                        const int dir = L.e.dir[k];
+                        const bool srt = PRUNE == PRUNE_SORTED && a.l_sorted[L.e.B[k]] && nB <= 64;
+                        if (srt) {
+                            double uu[3];
+                            sph_dir(dir, uu);
+                            const float ki = (float)((double)xi * uu[0] + (double)yi * uu[1] + (double)zi * uu[2]);
+                            float kmin = wave_minf(act ? ki - (float)Hd : INFINITY);
+                            float kmax = wave_maxf(act ? ki + (float)Hd : -INFINITY);
+                            const float eps = 1e-5f * (fabsf(kmin) + fabsf(kmax)) + 1e-6f * (float)hA;
+                            sorted_window(a.skey, a.n, dir, bB, nB, lane, kmin - eps, kmax + eps, lo, hi);
+                        }
+                        for (int p0 = lo; p0 < hi; p0 += 64) {
+                            const int len = min(64, hi - p0);
+                            if (lane < len) {
+                                const int t = p0 + lane;
+                                const int jl = srt ? (int)a.sidx[(int64_t)dir * a.n + bB + t] : t;
+                                tile[lane] = pos4[bB + jl];
+                            }
+                            wave_sync();
+                            for (int t = jg; t < len; t += G) {
+                                const V4 q4 = tile[t];
+                                const T dx = q4.x - xi, dy = q4.y - yi, dz = q4.z - zi;
+                                const T r2 = dx * dx + dy * dy + dz * dz;
+                                if (act && r2 < H2) dens_acc(q4, r2);
+                            }
+                            wave_sync();
+                        }
+                        if (PRUNE == PRUNE_BOX && k + 1 < nv) {
+                            const int n1 = L.e.n[k + 1];
+                            if (lane < n1) pf = pos4[L.e.b[k + 1] + lane];
+                        }
                     }
                 }
+#pragma unroll
+                for (int u = 0; u < NTD; u++) {
+                    unsigned long long m = msk[u];
+                    const T xi = pi.x - tox[u], yi = pi.y - toy[u], zi = pi.z - toz[u];
+                    const V4* tile = L.p[u];
+                    while (m) {
+                        const int s = __ffsll((long long)m) - 1;
+                        m &= m - 1;
+                        const V4 q4 = tile[jg + G * s];
+                        const T dx = q4.x - xi, dy = q4.y - yi, dz = q4.z - zi;
+                        dens_acc(q4, dx * dx + dy * dy + dz * dz);
+                    }
+                }
+                wave_sync();
             }
             wave_sync();
         }
@@ -556,15 +583,27 @@ struct ForceArgs {
     int persistent;
 };
 
+template <typename T> struct vec2t;
+template <> struct vec2t<float> { typedef float2 type; };
+template <> struct vec2t<double> { typedef double2 type; };
+
+// One staged neighbour cell of the force stage.
+template <typename T>
+struct FSlots {
+    typename vec4<T>::type p[64];   // x, y, z (B frame), H^2
+    typename vec4<T>::type v[64];   // vx, vy, vz, k = A (8/pi) / H^4
+    typename vec2t<T>::type mh[64]; // m, 1/H
+    T acc[4][64];                   // j-side sums
+    int jl[64];                     // local index in B
+    int jn[64];                     // j-side neighbour counts (r < H_j)
+};
+
+// neighbour cells per two-phase batch (force): LDS keeps 4 waves per group
+#define NTF(T) (sizeof(T) == 4 ? 2 : 1)
+
 template <typename T>
 struct FTile {
-    typename vec4<T>::type p[64];  // x, y, z (B frame), m
-    typename vec4<T>::type v[64];  // vx, vy, vz, k = A (8/pi) / H^4
-    T h2[64];                      // H^2
-    T ih[64];                      // 1/H
-    T acc[4][64];                  // j-side sums
-    int jl[64];                    // local index in B
-    int jn[64];                    // j-side neighbour counts (r < H_j)
+    FSlots<T> s[NTF(T)];
     EBatch<T> e;
 };
 
@@ -573,61 +612,86 @@ struct FAcc {
     Acc<T, COMP> ax, ay, az, du;
 };
 
-// One pair (i, j), d = x_i - x_j.  Returns true if within max(H_i, H_j);
-// counts the pair for i if r < H_i (and for j through jn if r < H_j).
+// Evaluate one pair (i, j) known to be within max(H_i, H_j); d = x_i - x_j.
+// Counts the pair for i if r < H_i (and, with JSIDE, for j if r < H_j).
 template <typename T, bool COMP, bool JSIDE>
-__device__ inline bool force_pair(T dx, T dy, T dz, T mi, T h2i, T ihi, T ki, T vxi, T vyi, T vzi,
-                                  const typename vec4<T>::type& pj, const typename vec4<T>::type& fj, T h2j, T ihj,
-                                  FAcc<T, COMP>& ai, T* accj, int* jn, int o, int& ni)
+__device__ inline void force_eval(T dx, T dy, T dz, T r2, T mi, T h2i, T ihi, T ki, T vxi, T vyi, T vzi,
+                                  const FSlots<T>& sl, int o, FAcc<T, COMP>& ai, FSlots<T>* slw, int& ni)
 {
-    const T r2 = dx * dx + dy * dy + dz * dz;
-    if (!(r2 < fmax(h2i, h2j))) return false;
+    const typename vec4<T>::type pj = sl.p[o];
+    const typename vec4<T>::type fj = sl.v[o];
+    const typename vec2t<T>::type mh = sl.mh[o];
     if (r2 < h2i) ni++;
-    if (JSIDE && r2 < h2j) atomicAdd(&jn[o], 1);
-    if (!(r2 > T(0))) return true;  // coincident particles exert no force
+    if (JSIDE && r2 < pj.w) atomicAdd(&slw->jn[o], 1);
+    if (!(r2 > T(0))) return;  // coincident particles exert no force
     const T ir = T(1) / sqrt(r2);
     const T r = r2 * ir;
     const T Fi = ki * spline_dw(r * ihi);      // A_i dW/dr(r, H_i)
-    const T Fj = fj.w * spline_dw(r * ihj);    // A_j dW/dr(r, H_j)
+    const T Fj = fj.w * spline_dw(r * mh.y);   // A_j dW/dr(r, H_j)
     const T F = (Fi + Fj) * ir;
     const T dvdr = ((vxi - fj.x) * dx + (vyi - fj.y) * dy + (vzi - fj.z) * dz) * ir;
-    const T mjF = pj.w * F;
+    const T mjF = mh.x * F;
     ai.ax.add(-mjF * dx);
     ai.ay.add(-mjF * dy);
     ai.az.add(-mjF * dz);
-    ai.du.add(pj.w * Fi * dvdr);
+    ai.du.add(mh.x * Fi * dvdr);
     if (JSIDE) {
         const T miF = mi * F;
-        atomicAdd(&accj[0 * 64 + o], miF * dx);
-        atomicAdd(&accj[1 * 64 + o], miF * dy);
-        atomicAdd(&accj[2 * 64 + o], miF * dz);
-        atomicAdd(&accj[3 * 64 + o], mi * Fj * dvdr);
+        atomicAdd(&slw->acc[0][o], miF * dx);
+        atomicAdd(&slw->acc[1][o], miF * dy);
+        atomicAdd(&slw->acc[2][o], miF * dz);
+        atomicAdd(&slw->acc[3][o], mi * Fj * dvdr);
     }
-    return true;
 }
 
 template <typename T>
-__device__ inline void stage_force_j(FTile<T>& tl, int slot, const typename vec4<T>::type& p, typename vec4<T>::type f,
-                                     T h, int jl)
+__device__ inline void stage_force_j(FSlots<T>& sl, int slot, const typename vec4<T>::type& p,
+                                     const typename vec4<T>::type& f, T h, int jl)
 {
     const T ih = T(1) / h;
-    f.w = f.w * T(INV_PI_8) * ih * ih * ih * ih;
-    tl.p[slot] = p;
-    tl.v[slot] = f;
-    tl.h2[slot] = h * h;
-    tl.ih[slot] = ih;
-    tl.acc[0][slot] = 0;
-    tl.acc[1][slot] = 0;
-    tl.acc[2][slot] = 0;
-    tl.acc[3][slot] = 0;
-    tl.jl[slot] = jl;
-    tl.jn[slot] = 0;
+    typename vec4<T>::type q = p, g = f;
+    q.w = h * h;
+    g.w = f.w * T(INV_PI_8) * ih * ih * ih * ih;
+    typename vec2t<T>::type mh;
+    mh.x = p.w;
+    mh.y = ih;
+    sl.p[slot] = q;
+    sl.v[slot] = g;
+    sl.mh[slot] = mh;
+    sl.acc[0][slot] = 0;
+    sl.acc[1][slot] = 0;
+    sl.acc[2][slot] = 0;
+    sl.acc[3][slot] = 0;
+    sl.jl[slot] = jl;
+    sl.jn[slot] = 0;
+}
+
+// Flush the j-side sums of a staged cell (one atomic add per particle and
+// quantity; skipped for particles that received nothing).
+template <typename T>
+__device__ inline unsigned long long flush_j(const ForceArgs& a, const FSlots<T>& sl, int bB, int len, int lane)
+{
+    int jcnt = 0;
+    if (lane < len) {
+        const int p = bB + sl.jl[lane];
+        const T gx = sl.acc[0][lane], gy = sl.acc[1][lane], gz = sl.acc[2][lane], gu = sl.acc[3][lane];
+        if (gx != T(0) || gy != T(0) || gz != T(0) || gu != T(0)) {
+            atomicAdd(&a.ax[p], (double)gx);
+            atomicAdd(&a.ay[p], (double)gy);
+            atomicAdd(&a.az[p], (double)gz);
+            atomicAdd(&a.dudt[p], (double)gu);
+        }
+        jcnt = sl.jn[lane];
+        if (jcnt && a.nngb) atomicAdd(&a.nngb[p], jcnt);
+    }
+    return (unsigned long long)jcnt;
 }
 
 template <typename T, bool COMP, int PRUNE>
 __device__ void force_leaf(const ForceArgs& a, int A, FTile<T>& tl, int lane)
 {
     typedef typename vec4<T>::type V4;
+    constexpr int NT = NTF(T);
     const V4* pos4 = (const V4*)a.pos4;
     const V4* fv4 = (const V4*)a.fv4;
     const T* hf = (const T*)a.hf;
@@ -655,11 +719,12 @@ __device__ void force_leaf(const ForceArgs& a, int A, FTile<T>& tl, int lane)
         const T bxl = wave_min_t<T>(vi ? pi.x : big), bxh = wave_max_t<T>(vi ? pi.x : -big);
         const T byl = wave_min_t<T>(vi ? pi.y : big), byh = wave_max_t<T>(vi ? pi.y : -big);
         const T bzl = wave_min_t<T>(vi ? pi.z : big), bzh = wave_max_t<T>(vi ? pi.z : -big);
+        FSlots<T>& s0l = tl.s[0];
 
         // the cell's own pairs
         if (nA <= 64) {
             // triangular sweep over the unordered pairs of the cell
-            if (lane < nA) stage_force_j<T>(tl, lane, pos4[bA + lane], fv4[bA + lane], hf[bA + lane], lane);
+            if (lane < nA) stage_force_j<T>(s0l, lane, pos4[bA + lane], fv4[bA + lane], hf[bA + lane], lane);
             wave_sync();
             const int steps = nA / 2;  // pair distances 1..floor(n/2)
             const bool even = (nA & 1) == 0;
@@ -668,20 +733,23 @@ __device__ void force_leaf(const ForceArgs& a, int A, FTile<T>& tl, int lane)
                 if (b >= nA) b -= nA;
                 const bool ok = vi && !(even && t == steps - 1 && ii >= nA / 2);
                 if (ok) {
-                    const V4 pj = tl.p[b];
+                    const V4 pj = s0l.p[b];
                     const T dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-                    if (force_pair<T, COMP, true>(dx, dy, dz, pi.w, h2i, ihi, ki, fi.x, fi.y, fi.z, pj, tl.v[b],
-                                                  tl.h2[b], tl.ih[b], ai, &tl.acc[0][0], tl.jn, b, nni))
+                    const T r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 < fmax(h2i, pj.w)) {
+                        force_eval<T, COMP, true>(dx, dy, dz, r2, pi.w, h2i, ihi, ki, fi.x, fi.y, fi.z, s0l, b, ai,
+                                                  &s0l, nni);
                         npairs++;
+                    }
                 }
             }
             wave_sync();
             if (jg == 0 && vi) {
-                ai.ax.add(tl.acc[0][ii]);
-                ai.ay.add(tl.acc[1][ii]);
-                ai.az.add(tl.acc[2][ii]);
-                ai.du.add(tl.acc[3][ii]);
-                nni += tl.jn[ii];
+                ai.ax.add(s0l.acc[0][ii]);
+                ai.ay.add(s0l.acc[1][ii]);
+                ai.az.add(s0l.acc[2][ii]);
+                ai.du.add(s0l.acc[3][ii]);
+                nni += s0l.jn[ii];
             }
             wave_sync();
         } else {
@@ -690,16 +758,19 @@ __device__ void force_leaf(const ForceArgs& a, int A, FTile<T>& tl, int lane)
                 const int len = min(64, nA - p0);
                 if (lane < len) {
                     const int p = bA + p0 + lane;
-                    stage_force_j<T>(tl, lane, pos4[p], fv4[p], hf[p], p0 + lane);
+                    stage_force_j<T>(s0l, lane, pos4[p], fv4[p], hf[p], p0 + lane);
                 }
                 wave_sync();
                 for (int t = jg; t < len; t += G) {
                     if (!vi || p0 + t == c0 + ii) continue;
-                    const V4 pj = tl.p[t];
+                    const V4 pj = s0l.p[t];
                     const T dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-                    if (force_pair<T, COMP, false>(dx, dy, dz, pi.w, h2i, ihi, ki, fi.x, fi.y, fi.z, pj, tl.v[t],
-                                                   tl.h2[t], tl.ih[t], ai, nullptr, nullptr, t, nni))
+                    const T r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 < fmax(h2i, pj.w)) {
+                        force_eval<T, COMP, false>(dx, dy, dz, r2, pi.w, h2i, ihi, ki, fi.x, fi.y, fi.z, s0l, t,
+                                                   ai, nullptr, nni);
                         if (p0 + t > c0 + ii) npairs++;
+                    }
                 }
                 wave_sync();
             }
@@ -728,28 +799,27 @@ __device__ void force_leaf(const ForceArgs& a, int A, FTile<T>& tl, int lane)
                     hh = hf[p];
                 }
             }
-            for (int k = 0; k < nv; k++) {
-                const int bB = tl.e.b[k], nB = tl.e.n[k];
-                const T dox = tl.e.ox[k], doy = tl.e.oy[k], doz = tl.e.oz[k];
-                const T xi = pi.x - dox, yi = pi.y - doy, zi = pi.z - doz;
-                const T R = fmax((T)hA, tl.e.R[k]);
-                int passes_lo = 0, passes_hi = nB;
-                bool direct = PRUNE == PRUNE_BOX && nB <= 64;
-                const int dir = tl.e.dir[k];
-                const bool srt = !direct && PRUNE == PRUNE_SORTED && a.l_sorted[tl.e.B[k]] && nB <= 64;
-                if (srt) {
-                    double u[3];
-                    sph_dir(dir, u);
-                    const float ki_ = (float)((double)xi * u[0] + (double)yi * u[1] + (double)zi * u[2]);
-                    const float Rf = (float)R;
-                    float kmin = wave_minf(vi ? ki_ - Rf : INFINITY);
-                    float kmax = wave_maxf(vi ? ki_ + Rf : -INFINITY);
-                    const float eps = 1e-5f * (fabsf(kmin) + fabsf(kmax)) + 1e-6f * Rf;
-                    sorted_window(a.skey, a.n, dir, bB, nB, lane, kmin - eps, kmax + eps, passes_lo, passes_hi);
-                }
-                for (int p0 = passes_lo; p0 < passes_hi; p0 += 64) {
-                    int len;
-                    if (direct) {
+            for (int k0 = 0; k0 < nv; k0 += NT) {
+                unsigned long long msk[NT];
+                T tox[NT], toy[NT], toz[NT];
+                int tlen[NT], tbB[NT];
+#pragma unroll
+                for (int u = 0; u < NT; u++) {
+                    msk[u] = 0ull;
+                    tox[u] = toy[u] = toz[u] = T(0);
+                    tlen[u] = 0;
+                    tbB[u] = 0;
+                    const int k = k0 + u;
+                    if (k >= nv) continue;
+                    FSlots<T>& sl = tl.s[u];
+                    const int bB = tl.e.b[k], nB = tl.e.n[k];
+                    const T dox = tl.e.ox[k], doy = tl.e.oy[k], doz = tl.e.oz[k];
+                    tox[u] = dox;
+                    toy[u] = doy;
+                    toz[u] = doz;
+                    tbB[u] = bB;
+                    const T xi = pi.x - dox, yi = pi.y - doy, zi = pi.z - doz;
+                    if (PRUNE == PRUNE_BOX && nB <= 64) {
                         const V4 pj = pf, fj = ff;
                         const T hj = hh;
                         if (k + 1 < nv) {
@@ -765,61 +835,113 @@ __device__ void force_leaf(const ForceArgs& a, int A, FTile<T>& tl, int lane)
                         const bool in = lane < nB && box_d2<T>(pj.x, pj.y, pj.z, bxl - dox, byl - doy, bzl - doz,
                                                                 bxh - dox, byh - doy, bzh - doz) < Rj * Rj;
                         const unsigned long long mk = __ballot(in);
-                        if (in) stage_force_j<T>(tl, mask_rank(mk, lane), pj, fj, hj, lane);
-                        len = __popcll(mk);
+                        if (in) stage_force_j<T>(sl, mask_rank(mk, lane), pj, fj, hj, lane);
+                        const int len = __popcll(mk);
+                        tlen[u] = len;
+                        wave_sync();
+                        if (vi) {
+                            unsigned long long m = 0ull;
+                            for (int s = 0, t = jg; t < len; s++, t += G) {
+                                const V4 q = sl.p[t];
+                                const T dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
+                                if (dx * dx + dy * dy + dz * dz < fmax(h2i, q.w)) m |= 1ull << s;
+                            }
+                            msk[u] = m;
+                            npairs += __popcll(m);
+                        }
                     } else {
-                        len = min(64, passes_hi - p0);
-                        if (lane < len) {
-                            const int t = p0 + lane;
-                            const int jl = srt ? (int)a.sidx[(int64_t)dir * a.n + bB + t] : t;
-                            const int p = bB + jl;
-                            stage_force_j<T>(tl, lane, pos4[p], fv4[p], hf[p], jl);
+                        // sorted-axis window (or a cell too large for one tile): one phase
+                        const T R = fmax((T)hA, tl.e.R[k]);
+                        int lo = 0, hi = nB;
+                        const int dir = tl.e.dir[k];
+                        const bool srt = PRUNE == PRUNE_SORTED && a.l_sorted[tl.e.B[k]] && nB <= 64;
+                        if (srt) {
+                            double uu[3];
+                            sph_dir(dir, uu);
+                            const float ki_ = (float)((double)xi * uu[0] + (double)yi * uu[1] + (double)zi * uu[2]);
+                            const float Rf = (float)R;
+                            float kmin = wave_minf(vi ? ki_ - Rf : INFINITY);
+                            float kmax = wave_maxf(vi ? ki_ + Rf : -INFINITY);
+                            const float eps = 1e-5f * (fabsf(kmin) + fabsf(kmax)) + 1e-6f * Rf;
+                            sorted_window(a.skey, a.n, dir, bB, nB, lane, kmin - eps, kmax + eps, lo, hi);
+                        }
+                        for (int p0 = lo; p0 < hi; p0 += 64) {
+                            const int len = min(64, hi - p0);
+                            if (lane < len) {
+                                const int t = p0 + lane;
+                                const int jl = srt ? (int)a.sidx[(int64_t)dir * a.n + bB + t] : t;
+                                const int p = bB + jl;
+                                stage_force_j<T>(sl, lane, pos4[p], fv4[p], hf[p], jl);
+                            }
+                            wave_sync();
+                            // group jg owns slots jg, jg+G, ...; lanes of a group rotate over them
+                            const int Lg = (jg < len) ? (len - jg + G - 1) / G : 0;
+                            const int Lmax = (len + G - 1) / G;
+                            const int s0 = (Lg > 0) ? ii % Lg : 0;
+                            for (int t = 0; t < Lmax; t++) {
+                                if (vi && t < Lg) {
+                                    int s = s0 + t;
+                                    if (s >= Lg) s -= Lg;
+                                    const int o = jg + G * s;
+                                    const V4 q = sl.p[o];
+                                    const T dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
+                                    const T r2 = dx * dx + dy * dy + dz * dz;
+                                    if (r2 < fmax(h2i, q.w)) {
+                                        force_eval<T, COMP, true>(dx, dy, dz, r2, pi.w, h2i, ihi, ki, fi.x, fi.y,
+                                                                  fi.z, sl, o, ai, &sl, nni);
+                                        npairs++;
+                                    }
+                                }
+                            }
+                            wave_sync();
+                            ndens_w += flush_j<T>(a, sl, bB, len, lane);
+                            wave_sync();
+                        }
+                        if (PRUNE == PRUNE_BOX && k + 1 < nv) {
+                            const int n1 = tl.e.n[k + 1];
+                            if (lane < n1) {
+                                const int p = tl.e.b[k + 1] + lane;
+                                pf = pos4[p];
+                                ff = fv4[p];
+                                hh = hf[p];
+                            }
                         }
                     }
-                    wave_sync();
-                    // group jg owns slots jg, jg+G, ...; lanes of a group rotate over them
+                }
+                // phase 2: in-range pairs only, each lane starting at its own
+                // offset so that the lanes of a group touch different j
+#pragma unroll
+                for (int u = 0; u < NT; u++) {
+                    const unsigned long long m = msk[u];
+                    if (__ballot(m != 0ull) == 0ull) continue;
+                    FSlots<T>& sl = tl.s[u];
+                    const T xi = pi.x - tox[u], yi = pi.y - toy[u], zi = pi.z - toz[u];
+                    const int len = tlen[u];
                     const int Lg = (jg < len) ? (len - jg + G - 1) / G : 0;
-                    const int Lmax = (len + G - 1) / G;
-                    const int s0 = (Lg > 0) ? ii % Lg : 0;
-                    for (int t = 0; t < Lmax; t++) {
-                        if (vi && t < Lg) {
-                            int s = s0 + t;
-                            if (s >= Lg) s -= Lg;
-                            const int o = jg + G * s;
-                            const V4 pj = tl.p[o];
-                            const T dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
-                            if (force_pair<T, COMP, true>(dx, dy, dz, pi.w, h2i, ihi, ki, fi.x, fi.y, fi.z, pj, tl.v[o],
-                                                          tl.h2[o], tl.ih[o], ai, &tl.acc[0][0], tl.jn, o, nni))
-                                npairs++;
+                    const int r0 = (Lg > 0) ? ii % Lg : 0;
+                    unsigned long long mh = (r0 > 0) ? (m >> r0) : m;
+                    unsigned long long ml = (r0 > 0) ? (m & ((1ull << r0) - 1ull)) : 0ull;
+                    while (mh | ml) {
+                        int s;
+                        if (mh) {
+                            s = r0 + __ffsll((long long)mh) - 1;
+                            mh &= mh - 1;
+                        } else {
+                            s = __ffsll((long long)ml) - 1;
+                            ml &= ml - 1;
                         }
-                    }
-                    wave_sync();
-                    int jcnt = 0;
-                    if (lane < len) {
-                        const int p = bB + tl.jl[lane];
-                        const T gx = tl.acc[0][lane], gy = tl.acc[1][lane], gz = tl.acc[2][lane], gu = tl.acc[3][lane];
-                        if (gx != T(0) || gy != T(0) || gz != T(0) || gu != T(0)) {
-                            atomicAdd(&a.ax[p], (double)gx);
-                            atomicAdd(&a.ay[p], (double)gy);
-                            atomicAdd(&a.az[p], (double)gz);
-                            atomicAdd(&a.dudt[p], (double)gu);
-                        }
-                        jcnt = tl.jn[lane];
-                        if (jcnt && a.nngb) atomicAdd(&a.nngb[p], jcnt);
-                    }
-                    ndens_w += jcnt;
-                    wave_sync();
-                    if (direct) break;
-                }
-                if (!direct && PRUNE == PRUNE_BOX && k + 1 < nv) {
-                    const int n1 = tl.e.n[k + 1];
-                    if (lane < n1) {
-                        const int p = tl.e.b[k + 1] + lane;
-                        pf = pos4[p];
-                        ff = fv4[p];
-                        hh = hf[p];
+                        const int o = jg + G * s;
+                        const V4 q = sl.p[o];
+                        const T dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
+                        force_eval<T, COMP, true>(dx, dy, dz, dx * dx + dy * dy + dz * dz, pi.w, h2i, ihi, ki, fi.x,
+                                                  fi.y, fi.z, sl, o, ai, &sl, nni);
                     }
                 }
+                wave_sync();
+#pragma unroll
+                for (int u = 0; u < NT; u++)
+                    if (tlen[u] > 0) ndens_w += flush_j<T>(a, tl.s[u], tbB[u], tlen[u], lane);
+                wave_sync();
             }
             wave_sync();
         }
