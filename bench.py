@@ -70,9 +70,12 @@ def main():
     ap.add_argument("--exec", dest="exec_mode", default="grid", choices=["grid", "persistent"])
     ap.add_argument("--n-split", type=int, default=64)
     ap.add_argument("--prune", default="box", choices=["box", "sorted"])
+    ap.add_argument("--graph", action="store_true", help="density, ghost and force from one captured hipGraph")
     ap.add_argument("--cpu-n-side", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=2741)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 512 MiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus %d)"
@@ -87,6 +90,13 @@ def main():
 
     assert torch.cuda.is_available(), "needs a GPU"
     S.lib()
+    if args.calib_copy:
+        src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     log("generating clustered %d^3 ..." % args.n_side)
     t0 = time.perf_counter()
     d = gen.clustered(args.n_side, seed=args.seed,
@@ -94,7 +104,7 @@ def main():
     log("generated in %.1f s" % (time.perf_counter() - t0))
     n = d["x"].size
     sim = S.SPH(d["box"], precision=args.precision, exec_mode=args.exec_mode, n_split=args.n_split,
-                prune=args.prune)
+                prune=args.prune, use_graph=args.graph)
     t = S.to_device(d)
     del d
     sim.bind(t)
@@ -135,7 +145,12 @@ def main():
     prec = args.precision
     dens_flops = dens_evals * FLOPS_DENS[prec]
     force_flops = force_pairs * FLOPS_FORCE[prec]
-    if dens_ms >= force_ms:
+    if dens_ms < 0 or force_ms < 0:
+        # graph mode: the kernels inside the graph are not timed one by one;
+        # the graph's wall time bounds both from above
+        kname, kflops, kms, klaunch = ("graph(k_density,k_ghost,k_force)", dens_flops + force_flops,
+                                       t_dgf * 1e3, args.steps)
+    elif dens_ms >= force_ms:
         kname, kflops, kms, klaunch = "k_density", dens_flops, dens_ms, dens_launch
     else:
         kname, kflops, kms, klaunch = "k_force", force_flops, force_ms, args.steps
@@ -165,7 +180,7 @@ def main():
         "config": {"workload": "clustered %d^3 periodic unit box: lognormal sigma_ln=1.5 + NFW halos, "
                                "h span %.0fx (0.1-99.9%%)" % (args.n_side, h_span),
                    "n_particles": n, "precision": prec, "exec": args.exec_mode, "n_split": args.n_split,
-                   "prune": args.prune,
+                   "prune": args.prune, "graph": bool(args.graph),
                    "dt": dt},
         "interactions_per_step": inter / args.steps,
         "n_dens_per_step": sum(s["n_dens"] for s in per) / args.steps,

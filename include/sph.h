@@ -70,7 +70,8 @@ typedef struct {
                             cost-ordered device task queue */
     int n_domains;       /* number of independent periodic boxes (>= 1) */
     int persistent_wgs;  /* resident workgroups for the persistent mode (0: auto) */
-    int waves_per_wg;    /* reserved, 0 */
+    int use_graph;       /* 1: density sweeps, ghost and force run as one captured
+                            hipGraph (sph_density_ghost_force and sph_step) */
     int prune;           /* pair-candidate selection: SPH_PRUNE_BOX (neighbour-cell
                             particles within range of the bounding box of the cell's
                             particles) or SPH_PRUNE_SORTED (window of the sort stage's
@@ -117,10 +118,13 @@ typedef struct {
     double t_ghost_ms;
     double t_force_ms;
     double t_build_ms;       /* last build_cells + sort_cells */
-    double t_density_kernels_ms; /* summed duration of the density-sweep kernels of the last density call */
-    double t_force_kernel_ms;    /* duration of the force kernel of the last force call */
+    double t_density_kernels_ms; /* summed duration of the density-sweep kernels of the last density call
+                                    (-1 when sweeps ran inside the graph) */
+    double t_force_kernel_ms;    /* duration of the force kernel of the last force call (-1: inside the graph) */
     int64_t n_dens_evals;    /* interactions r_ij < H_i evaluated over all sweeps of the last density call */
     int32_t n_density_launches; /* density-sweep kernel launches of the last density call */
+    int32_t graph_captures;     /* graph (re)captures since sph_create (use_graph = 1) */
+    int32_t graph_fallbacks;    /* graph runs the host had to finish since sph_create */
     int32_t pad;
 } sph_stats;
 
@@ -167,6 +171,13 @@ sph_status sph_ghost(sph_ctx* ctx);
  * max(H_i, H_j) evaluated once and applied to both particles.  Writes ax,
  * ay, az, dudt.  Requires sph_ghost. */
 sph_status sph_force(sph_ctx* ctx);
+
+/* Density, ghost and force in one call.  With use_graph = 1 they run as one
+ * captured hipGraph holding a fixed number of density sweeps gated by a
+ * device flag (re-captured after every cell or list rebuild); work the
+ * graph cannot finish (more sweeps, list or grid rebuilds) is completed by
+ * the host-driven path.  Requires sph_sort_cells. */
+sph_status sph_density_ghost_force(sph_ctx* ctx);
 
 /* One kick-drift-kick step of length dt (integrator stage, Sec. 3.1):
  * half kick of v and u with the current forces, drift with periodic wrap,

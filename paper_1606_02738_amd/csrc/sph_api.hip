@@ -63,6 +63,7 @@ sph_status sph_create(const sph_params* params, void* hip_stream, sph_ctx** out)
     if (p.precision < SPH_FP64 || p.precision > SPH_FP32) return SPH_ERR_INVALID;
     if (p.exec_mode < SPH_EXEC_GRID || p.exec_mode > SPH_EXEC_PERSISTENT) return SPH_ERR_INVALID;
     if (p.prune < SPH_PRUNE_BOX || p.prune > SPH_PRUNE_SORTED) return SPH_ERR_INVALID;
+    if (p.use_graph < 0 || p.use_graph > 1) return SPH_ERR_INVALID;
     for (int k = 0; k < 3 * p.n_domains; k++)
         if (!(p.boxes[k] > 0.0) || !isfinite(p.boxes[k])) return SPH_ERR_INVALID;
     sph_ctx* c = new (std::nothrow) sph_ctx();
@@ -106,6 +107,8 @@ sph_status sph_destroy(sph_ctx* c)
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
     for (int k = 0; k < 4; k++)
         if (c->kev[k]) (void)hipEventDestroy(c->kev[k]);
+    if (c->graph_exec) (void)hipGraphExecDestroy((hipGraphExec_t)c->graph_exec);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
     return SPH_OK;
 }
@@ -154,6 +157,17 @@ sph_status sph_ghost(sph_ctx* c)
 sph_status sph_force(sph_ctx* c)
 {
     if (!c) return SPH_ERR_INVALID;
+    return force_all(c);
+}
+
+sph_status sph_density_ghost_force(sph_ctx* c)
+{
+    if (!c) return SPH_ERR_INVALID;
+    if (!c->sorted) return SPH_ERR_STATE;
+    c->predicted = false;
+    if (c->prm.use_graph) return dgf_graph(c);
+    SPH_TRY(density_all(c));
+    SPH_TRY(ghost_all(c));
     return force_all(c);
 }
 

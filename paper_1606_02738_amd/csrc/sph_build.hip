@@ -422,11 +422,25 @@ __global__ __launch_bounds__(256) void k_wnodes(const Node* __restrict__ nodes, 
         o.lo[a] = __double2float_rd(nd.lo[a]);
         o.hi[a] = __double2float_ru(nd.hi[a]);
     }
-    o.first_child = nd.first_child;
-    o.n_child = nd.n_child;
+    o.first_child = nd.n_child > 0 ? nd.first_child : -1;
+    o.next = -1;
     o.count = nd.count;
     o.leaf = nd.leaf;
     w[k] = o;
+}
+
+// Escape links, one level at a time from the top: a child's next node is its
+// next sibling, the last child inherits its parent's next node.
+__global__ __launch_bounds__(256) void k_wnext(const Node* __restrict__ nodes, int level_start, int n_level,
+                                               WNode* __restrict__ w)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_level) return;
+    const int p = level_start + k;
+    const Node& nd = nodes[p];
+    if (nd.n_child == 0) return;
+    const int pn = w[p].next;
+    for (int q = 0; q < nd.n_child; q++) w[nd.first_child + q].next = (q + 1 < nd.n_child) ? nd.first_child + q + 1 : pn;
 }
 
 __device__ inline float box_dist_f(const float* alo, const float* ahi, const float* blo, const float* bhi,
@@ -466,7 +480,6 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
     int cnt = 0;
     int out = FILL ? l_off[A] : 0;
     const int out_end = FILL ? l_off[A + 1] : 0;
-    int stack[WALK_STACK];
     for (int sx = -1; sx <= 1; sx++)
     for (int sy = -1; sy <= 1; sy++)
     for (int sz = -1; sz <= 1; sz++) {
@@ -483,13 +496,21 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
             svf[a] = (float)sv[a];
         }
         const int code_shift = shift_index(ps[0], ps[1], ps[2]);
-        int sp = 0;
-        stack[sp++] = I.top_offset + (nc[0] * I.n_top[1] + nc[1]) * I.n_top[2] + nc[2];
-        while (sp > 0) {
-            const WNode nd = wn[stack[--sp]];
-            if (nd.count == 0) continue;
-            if (box_dist_f(WA.lo, WA.hi, nd.lo, nd.hi, svf) > prune) continue;
-            if (nd.n_child == 0) {
+        // depth-first over the neighbour top cell without a stack: descend to
+        // the first child, or skip the subtree through its escape link
+        int k = I.top_offset + (nc[0] * I.n_top[1] + nc[1]) * I.n_top[2] + nc[2];
+        while (k >= 0) {
+            const WNode nd = wn[k];
+            if (nd.count == 0 || box_dist_f(WA.lo, WA.hi, nd.lo, nd.hi, svf) > prune) {
+                k = nd.next;
+                continue;
+            }
+            if (nd.first_child >= 0) {
+                k = nd.first_child;
+                continue;
+            }
+            k = nd.next;
+            {
                 // exact distance between the leaf boxes, in the canonical order
                 const int B = nd.leaf;
                 const double blo[3] = {l_lo[3 * B], l_lo[3 * B + 1], l_lo[3 * B + 2]};
@@ -511,9 +532,9 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
                             for (int a = 0; a < 3; a++)
                                 cv[a] = (float)(0.5 * (blo[a] + bhi[a]) + sv[a] - 0.5 * (alo[a] + ahi[a]));
                             float bv = -1.f;
-                            for (int k = 0; k < SPH_NDIR; k++) {
-                                const float v = fabsf(cv[0] * c_dirs[k][0] + cv[1] * c_dirs[k][1] + cv[2] * c_dirs[k][2]);
-                                if (v > bv) { bv = v; best = k; }
+                            for (int q = 0; q < SPH_NDIR; q++) {
+                                const float v = fabsf(cv[0] * c_dirs[q][0] + cv[1] * c_dirs[q][1] + cv[2] * c_dirs[q][2]);
+                                if (v > bv) { bv = v; best = q; }
                             }
                         }
                         ListEntry e;
@@ -527,12 +548,6 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
                     out++;
                 }
                 cnt++;
-            } else {
-                if (sp + nd.n_child > WALK_STACK) {
-                    atomicOr(flags, FLAG_INVALID);
-                    continue;
-                }
-                for (int q = nd.n_child - 1; q >= 0; q--) stack[sp++] = nd.first_child + q;
             }
         }
     }
@@ -946,6 +961,12 @@ sph_status build_all(sph_ctx* c)
     SPH_TRY(buf_ensure(c->wnodes, (size_t)n_nodes * sizeof(WNode)));
     k_wnodes<<<blocks_for(n_nodes, 256), 256, 0, c->stream>>>((const Node*)c->nodes.p, n_nodes, (WNode*)c->wnodes.p);
     SPH_CHECK_LAUNCH();
+    for (size_t l = 0; l + 1 < c->level_off.size(); l++) {
+        const int ls = c->level_off[l], nl = c->level_off[l + 1] - ls;
+        if (nl <= 0) continue;
+        k_wnext<<<blocks_for(nl, 256), 256, 0, c->stream>>>((const Node*)c->nodes.p, ls, nl, (WNode*)c->wnodes.p);
+        SPH_CHECK_LAUNCH();
+    }
     SPH_TRY(relist(c));
     SPH_TRY(read_int(c, flags, &fl));
     if (fl & FLAG_INVALID) return SPH_ERR_INVALID;

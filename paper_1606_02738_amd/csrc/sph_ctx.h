@@ -64,6 +64,9 @@ struct sph_ctx {
     DevBuf dsum_part;
 
     hipEvent_t ev[8] = {};
+    void* graph_exec = nullptr;        // hipGraphExec_t of the density-ghost-force graph
+    std::vector<uint8_t> graph_key;    // launch arguments it was captured with
+    hipStream_t cap_stream = nullptr;  // private stream used only for capture
     hipEvent_t kev[4] = {};     // per-launch kernel timing
 
     int elem_size() const { return prm.precision == SPH_FP64 ? 8 : 4; }
@@ -104,4 +107,5 @@ sph_status density_all(sph_ctx* c);
 sph_status ghost_all(sph_ctx* c);
 sph_status force_all(sph_ctx* c);
 sph_status step_all(sph_ctx* c, double dt);
+sph_status dgf_graph(sph_ctx* c);
 sph_status domain_sums(sph_ctx* c, double* host_out);

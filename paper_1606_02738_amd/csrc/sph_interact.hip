@@ -10,8 +10,10 @@
 // relative to its leaf's centre, and the offset between two leaves (with the
 // periodic image) is formed in FP64 once per pair of cells.
 #include <math.h>
+#include <string.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "sph_ctx.h"
 
@@ -51,6 +53,16 @@ __device__ inline T spline_dw(T q)
     T v = (q <= T(0.5)) ? q * (T(18) * q - T(12)) : T(-6) * t * t;
     return (q < T(1)) ? v : T(0);
 }
+
+// Square root, reciprocal square root and reciprocal: in FP32 the hardware
+// instructions (1 ulp) instead of the longer correctly rounded sequences;
+// FP64 keeps the IEEE operations.  Arguments are positive normal numbers.
+__device__ inline float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline double fast_sqrt(double x) { return sqrt(x); }
+__device__ inline float fast_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double fast_rsqrt(double x) { return 1.0 / sqrt(x); }
+__device__ inline float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double fast_rcp(double x) { return 1.0 / x; }
 
 // Compensated (Kahan) accumulation; COMP = false gives the plain sum.
 template <typename T, bool COMP>
@@ -212,6 +224,8 @@ struct DensArgs {
     int* flags;
     unsigned long long* counters;
     const int* order;   // task order (persistent mode), may be NULL
+    const int* gate;    // graph mode: skip the sweep unless *gate == 0 (NULL: always run)
+    const int* nl_dev;  // graph mode: leaf count read from the device (NULL: n_leaves)
     int persistent;
 };
 
@@ -303,7 +317,7 @@ __device__ void density_leaf(const DensArgs& a, int A, DTile<T>& L, int lane)
             }
             // accumulate one in-range pair (i, particle q4 of B)
             auto dens_acc = [&](const V4& q4, T r2) {
-                const T q = sqrt(r2) * invH;
+                const T q = fast_sqrt(r2) * invH;
                 T w, dw;
                 spline_w_dw(q, w, dw);
                 sw.add(q4.w * w);
@@ -491,28 +505,31 @@ __global__ __launch_bounds__(256) void k_density(DensArgs a)
 {
     __shared__ DTile<T> tiles[WAVES_PER_WG];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (a.gate && uniform(*a.gate) != 0) return;
+    const int nL = a.nl_dev ? uniform(*a.nl_dev) : a.n_leaves;
     if (!a.persistent) {
         const int A = uniform(blockIdx.x * WAVES_PER_WG + w);
-        if (A >= a.n_leaves) return;
+        if (A >= nL) return;
         if (!a.l_active[A]) return;
         density_leaf<T, COMP, PRUNE>(a, A, tiles[w], lane);
         return;
     }
     // persistent: waves pop leaves from a cost-ordered queue; a wave pops at
     // most n_leaves times
-    for (int it = 0; it <= a.n_leaves; it++) {
+    for (int it = 0; it <= nL; it++) {
         const int t = wave_pop(&a.counters[CNT_QUEUE], lane);
-        if (t >= a.n_leaves) break;
+        if (t >= nL) break;
         const int A = uniform(a.order ? a.order[t] : t);
-        if (A < 0 || A >= a.n_leaves) break;
+        if (A < 0 || A >= nL) break;
         if (a.l_active[A]) density_leaf<T, COMP, PRUNE>(a, A, tiles[w], lane);
     }
 }
 
 __global__ __launch_bounds__(256) void k_density_reset(int64_t n, int n_leaves, double* hlo, double* hhi, uint8_t* conv,
-                                                       int* l_active)
+                                                       int* l_active, const int* nl_dev)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (nl_dev) n_leaves = *nl_dev;
     if (i < n) {
         hlo[i] = 0.0;
         hhi[i] = INFINITY;
@@ -529,10 +546,11 @@ __global__ __launch_bounds__(256) void k_ghost(int64_t n, const double* __restri
                                                const double* __restrict__ H, const double* __restrict__ u,
                                                const double* __restrict__ vx, const double* __restrict__ vy,
                                                const double* __restrict__ vz, double gamma, double* omega, double* P,
-                                               typename vec4<T>::type* fv4, T* hf)
+                                               typename vec4<T>::type* fv4, T* hf, const int* gate)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (gate && *gate != 1) return;
     const double r = rho[i], h = H[i];
     const double om = 1.0 + h / (3.0 * r) * drho[i];
     const double p = (gamma - 1.0) * r * u[i];
@@ -580,6 +598,8 @@ struct ForceArgs {
     int32_t* nngb;      // #{j : r_ij < H_i} incl. self at the final H (may be NULL)
     unsigned long long* counters;
     const int* order;
+    const int* gate;    // graph mode: run only if *gate == 1 (NULL: always run)
+    const int* nl_dev;  // graph mode: leaf count read from the device (NULL: n_leaves)
     int persistent;
 };
 
@@ -624,7 +644,7 @@ __device__ inline void force_eval(T dx, T dy, T dz, T r2, T mi, T h2i, T ihi, T 
     if (r2 < h2i) ni++;
     if (JSIDE && r2 < pj.w) atomicAdd(&slw->jn[o], 1);
     if (!(r2 > T(0))) return;  // coincident particles exert no force
-    const T ir = T(1) / sqrt(r2);
+    const T ir = fast_rsqrt(r2);
     const T r = r2 * ir;
     const T Fi = ki * spline_dw(r * ihi);      // A_i dW/dr(r, H_i)
     const T Fj = fj.w * spline_dw(r * mh.y);   // A_j dW/dr(r, H_j)
@@ -648,7 +668,7 @@ template <typename T>
 __device__ inline void stage_force_j(FSlots<T>& sl, int slot, const typename vec4<T>::type& p,
                                      const typename vec4<T>::type& f, T h, int jl)
 {
-    const T ih = T(1) / h;
+    const T ih = fast_rcp(h);
     typename vec4<T>::type q = p, g = f;
     q.w = h * h;
     g.w = f.w * T(INV_PI_8) * ih * ih * ih * ih;
@@ -975,17 +995,19 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a)
 {
     __shared__ FTile<T> tiles[WAVES_PER_WG];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (a.gate && uniform(*a.gate) != 1) return;
+    const int nL = a.nl_dev ? uniform(*a.nl_dev) : a.n_leaves;
     if (!a.persistent) {
         const int A = uniform(blockIdx.x * WAVES_PER_WG + w);
-        if (A >= a.n_leaves) return;
+        if (A >= nL) return;
         force_leaf<T, COMP, PRUNE>(a, A, tiles[w], lane);
         return;
     }
-    for (int it = 0; it <= a.n_leaves; it++) {
+    for (int it = 0; it <= nL; it++) {
         const int t = wave_pop(&a.counters[CNT_QUEUE2], lane);
-        if (t >= a.n_leaves) break;
+        if (t >= nL) break;
         const int A = uniform(a.order ? a.order[t] : t);
-        if (A < 0 || A >= a.n_leaves) break;
+        if (A < 0 || A >= nL) break;
         force_leaf<T, COMP, PRUNE>(a, A, tiles[w], lane);
     }
 }
@@ -1097,9 +1119,13 @@ static int resident_wgs(sph_ctx* c)
     return 256 * 8;  // 256 CUs x 8 workgroups of 4 waves
 }
 
-static sph_status launch_density(sph_ctx* c)
+// Leaf capacity of the per-leaf arrays: the grid of a captured launch covers
+// it, and the kernels bound the work by the leaf count read on the device.
+static int leaf_capacity(sph_ctx* c) { return (int)std::min<size_t>(c->l_begin.cap / sizeof(int), INT32_MAX / 2); }
+
+static void dens_args(sph_ctx* c, const int* gate, bool graph, DensArgs& a, int& nb)
 {
-    DensArgs a;
+    memset(&a, 0, sizeof(a));
     a.n_leaves = c->n_leaves;
     a.n = c->n;
     a.l_begin = (const int*)c->l_begin.p;
@@ -1129,8 +1155,18 @@ static sph_status launch_density(sph_ctx* c)
     a.counters = (unsigned long long*)c->counters.p;
     a.persistent = c->prm.exec_mode == SPH_EXEC_PERSISTENT;
     a.order = a.persistent ? (const int*)c->l_order.p : nullptr;
-    const int nb = a.persistent ? std::min(resident_wgs(c), blocks_for(c->n_leaves, WAVES_PER_WG))
-                                : blocks_for(c->n_leaves, WAVES_PER_WG);
+    a.gate = gate;
+    a.nl_dev = graph ? (const int*)c->flags.p + FI_NLEAVES : nullptr;
+    if (graph) a.n_leaves = 0;  // read on the device
+    const int nl = graph ? leaf_capacity(c) : c->n_leaves;
+    nb = a.persistent ? std::min(resident_wgs(c), blocks_for(nl, WAVES_PER_WG)) : blocks_for(nl, WAVES_PER_WG);
+}
+
+static sph_status launch_density(sph_ctx* c, const int* gate, bool graph = false)
+{
+    DensArgs a;
+    int nb = 0;
+    dens_args(c, gate, graph, a, nb);
     if (nb <= 0) return SPH_OK;
     const bool srt = c->prm.prune == SPH_PRUNE_SORTED;
     if (c->prm.precision == SPH_FP64) {
@@ -1147,33 +1183,38 @@ static sph_status launch_density(sph_ctx* c)
     return SPH_OK;
 }
 
-sph_status density_all(sph_ctx* c)
+static sph_status density_reset(sph_ctx* c)
 {
-    if (!c->sorted) return SPH_ERR_STATE;
-    int* flags = (int*)c->flags.p;
-    unsigned long long* cnt = (unsigned long long*)c->counters.p;
-    SPH_CHECK_HIP(hipEventRecord(c->ev[0], c->stream));
     SPH_TRY(buf_ensure(c->hlo, (size_t)c->n * 8));
     SPH_TRY(buf_ensure(c->hhi, (size_t)c->n * 8));
     SPH_TRY(buf_ensure(c->conv, (size_t)c->n));
     k_density_reset<<<blocks_for(std::max<int64_t>(c->n, c->n_leaves), 256), 256, 0, c->stream>>>(
-        c->n, c->n_leaves, (double*)c->hlo.p, (double*)c->hhi.p, (uint8_t*)c->conv.p, (int*)c->l_active.p);
+        c->n, c->n_leaves, (double*)c->hlo.p, (double*)c->hhi.p, (uint8_t*)c->conv.p, (int*)c->l_active.p, nullptr);
     SPH_CHECK_LAUNCH();
-    SPH_CHECK_HIP(hipMemsetAsync(cnt, 0, CNT_NPAIR * 8, c->stream));
     c->st.relists = 0;
     c->st.t_density_kernels_ms = 0.0;
     c->st.n_density_launches = 0;
     c->st.n_dens_evals = 0;
+    return SPH_OK;
+}
+
+// Host-driven sweeps: one sweep, read the counters, relist or rebuild if a
+// smoothing length outgrew the lists or the grid, repeat until converged.
+// `done_sweeps` sweeps were already run on the device (graph mode).
+static sph_status density_loop(sph_ctx* c, int done_sweeps, unsigned long long unconv0)
+{
+    int* flags = (int*)c->flags.p;
+    unsigned long long* cnt = (unsigned long long*)c->counters.p;
     int sweeps = 0;
-    unsigned long long unconv = 0;
+    unsigned long long unconv = unconv0;
     int fl = 0;
     sph_status status = SPH_OK;
-    for (sweeps = 1; sweeps <= c->prm.max_h_iter; sweeps++) {
+    for (sweeps = done_sweeps + 1; sweeps <= c->prm.max_h_iter; sweeps++) {
         SPH_CHECK_HIP(hipMemsetAsync(flags, 0, sizeof(int), c->stream));
         SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_UNCONV], 0, 8, c->stream));
         SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_QUEUE], 0, 8, c->stream));
         SPH_CHECK_HIP(hipEventRecord(c->kev[0], c->stream));
-        SPH_TRY(launch_density(c));
+        SPH_TRY(launch_density(c, nullptr));
         SPH_CHECK_HIP(hipEventRecord(c->kev[1], c->stream));
         unsigned long long hc[CNT_N];
         SPH_CHECK_HIP(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, c->stream));
@@ -1195,7 +1236,7 @@ sph_status density_all(sph_ctx* c)
             SPH_TRY(build_all(c));
             SPH_TRY(sort_all(c));
             k_density_reset<<<blocks_for(std::max<int64_t>(c->n, c->n_leaves), 256), 256, 0, c->stream>>>(
-                c->n, c->n_leaves, (double*)c->hlo.p, (double*)c->hhi.p, (uint8_t*)c->conv.p, (int*)c->l_active.p);
+                c->n, c->n_leaves, (double*)c->hlo.p, (double*)c->hhi.p, (uint8_t*)c->conv.p, (int*)c->l_active.p, nullptr);
             SPH_CHECK_LAUNCH();
             SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_NDENS], 0, 8, c->stream));
             c->st.rebuilds++;
@@ -1204,7 +1245,6 @@ sph_status density_all(sph_ctx* c)
             c->st.relists++;
         }
     }
-    SPH_CHECK_HIP(hipEventRecord(c->ev[1], c->stream));
     unsigned long long nd = 0;
     SPH_CHECK_HIP(hipMemcpyAsync(&nd, &cnt[CNT_NDENS], 8, hipMemcpyDeviceToHost, c->stream));
     SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
@@ -1218,6 +1258,32 @@ sph_status density_all(sph_ctx* c)
     return unconv ? SPH_ERR_NOT_CONVERGED : SPH_OK;
 }
 
+sph_status density_all(sph_ctx* c)
+{
+    if (!c->sorted) return SPH_ERR_STATE;
+    SPH_CHECK_HIP(hipEventRecord(c->ev[0], c->stream));
+    SPH_TRY(density_reset(c));
+    SPH_CHECK_HIP(hipMemsetAsync(c->counters.p, 0, CNT_NPAIR * 8, c->stream));
+    const sph_status s = density_loop(c, 0, 1ull);
+    SPH_CHECK_HIP(hipEventRecord(c->ev[1], c->stream));
+    return s;
+}
+
+static sph_status launch_ghost(sph_ctx* c, const double* u, const double* vx, const double* vy, const double* vz,
+                               const int* gate)
+{
+    if (c->prm.precision == SPH_FP64)
+        k_ghost<double><<<blocks_for(c->n, 256), 256, 0, c->stream>>>(c->n, c->P.rho, c->P.drho_dH, c->P.H, u, vx, vy,
+                                                                     vz, c->prm.gamma, c->P.omega, c->P.P,
+                                                                     (double4*)c->fv4.p, (double*)c->hf.p, gate);
+    else
+        k_ghost<float><<<blocks_for(c->n, 256), 256, 0, c->stream>>>(c->n, c->P.rho, c->P.drho_dH, c->P.H, u, vx, vy,
+                                                                    vz, c->prm.gamma, c->P.omega, c->P.P,
+                                                                    (float4*)c->fv4.p, (float*)c->hf.p, gate);
+    SPH_CHECK_LAUNCH();
+    return SPH_OK;
+}
+
 sph_status ghost_all(sph_ctx* c)
 {
     if (!c->dens_done) return SPH_ERR_STATE;
@@ -1227,35 +1293,15 @@ sph_status ghost_all(sph_ctx* c)
     const double* vy = pr ? (const double*)c->vpy.p : c->P.vy;
     const double* vz = pr ? (const double*)c->vpz.p : c->P.vz;
     SPH_CHECK_HIP(hipEventRecord(c->ev[2], c->stream));
-    if (c->prm.precision == SPH_FP64)
-        k_ghost<double><<<blocks_for(c->n, 256), 256, 0, c->stream>>>(c->n, c->P.rho, c->P.drho_dH, c->P.H, u, vx, vy,
-                                                                     vz, c->prm.gamma, c->P.omega, c->P.P,
-                                                                     (double4*)c->fv4.p, (double*)c->hf.p);
-    else
-        k_ghost<float><<<blocks_for(c->n, 256), 256, 0, c->stream>>>(c->n, c->P.rho, c->P.drho_dH, c->P.H, u, vx, vy,
-                                                                    vz, c->prm.gamma, c->P.omega, c->P.P,
-                                                                    (float4*)c->fv4.p, (float*)c->hf.p);
-    SPH_CHECK_LAUNCH();
+    SPH_TRY(launch_ghost(c, u, vx, vy, vz, nullptr));
     SPH_CHECK_HIP(hipEventRecord(c->ev[3], c->stream));
     c->ghost_done = true;
     return SPH_OK;
 }
 
-sph_status force_all(sph_ctx* c)
+static void force_args(sph_ctx* c, const int* gate, bool graph, ForceArgs& a, int& nb)
 {
-    if (!c->ghost_done) return SPH_ERR_STATE;
-    const size_t nb8 = (size_t)c->n * 8;
-    unsigned long long* cnt = (unsigned long long*)c->counters.p;
-    SPH_CHECK_HIP(hipEventRecord(c->ev[4], c->stream));
-    SPH_CHECK_HIP(hipMemsetAsync(c->P.ax, 0, nb8, c->stream));
-    SPH_CHECK_HIP(hipMemsetAsync(c->P.ay, 0, nb8, c->stream));
-    SPH_CHECK_HIP(hipMemsetAsync(c->P.az, 0, nb8, c->stream));
-    SPH_CHECK_HIP(hipMemsetAsync(c->P.dudt, 0, nb8, c->stream));
-    SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_NFORCE], 0, 8, c->stream));
-    SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_QUEUE2], 0, 8, c->stream));
-    SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_NDENS_F], 0, 8, c->stream));
-    if (c->P.nngb) SPH_CHECK_HIP(hipMemsetAsync(c->P.nngb, 0, (size_t)c->n * 4, c->stream));
-    ForceArgs a;
+    memset(&a, 0, sizeof(a));
     a.n_leaves = c->n_leaves;
     a.n = c->n;
     a.l_begin = (const int*)c->l_begin.p;
@@ -1277,12 +1323,21 @@ sph_status force_all(sph_ctx* c)
     a.az = c->P.az;
     a.dudt = c->P.dudt;
     a.nngb = c->P.nngb;
-    a.counters = cnt;
+    a.counters = (unsigned long long*)c->counters.p;
     a.persistent = c->prm.exec_mode == SPH_EXEC_PERSISTENT;
     a.order = a.persistent ? (const int*)c->l_order.p : nullptr;
-    const int nb = a.persistent ? std::min(resident_wgs(c), blocks_for(c->n_leaves, WAVES_PER_WG))
-                                : blocks_for(c->n_leaves, WAVES_PER_WG);
-    SPH_CHECK_HIP(hipEventRecord(c->kev[2], c->stream));
+    a.gate = gate;
+    a.nl_dev = graph ? (const int*)c->flags.p + FI_NLEAVES : nullptr;
+    if (graph) a.n_leaves = 0;  // read on the device
+    const int nl = graph ? leaf_capacity(c) : c->n_leaves;
+    nb = a.persistent ? std::min(resident_wgs(c), blocks_for(nl, WAVES_PER_WG)) : blocks_for(nl, WAVES_PER_WG);
+}
+
+static sph_status launch_force(sph_ctx* c, const int* gate, bool graph = false)
+{
+    ForceArgs a;
+    int nb = 0;
+    force_args(c, gate, graph, a, nb);
     if (nb > 0) {
         const bool srt = c->prm.prune == SPH_PRUNE_SORTED;
         if (c->prm.precision == SPH_FP64) {
@@ -1297,21 +1352,259 @@ sph_status force_all(sph_ctx* c)
         }
         SPH_CHECK_LAUNCH();
     }
+    return SPH_OK;
+}
+
+sph_status force_all(sph_ctx* c)
+{
+    if (!c->ghost_done) return SPH_ERR_STATE;
+    const size_t nb8 = (size_t)c->n * 8;
+    unsigned long long* cnt = (unsigned long long*)c->counters.p;
+    SPH_CHECK_HIP(hipEventRecord(c->ev[4], c->stream));
+    SPH_CHECK_HIP(hipMemsetAsync(c->P.ax, 0, nb8, c->stream));
+    SPH_CHECK_HIP(hipMemsetAsync(c->P.ay, 0, nb8, c->stream));
+    SPH_CHECK_HIP(hipMemsetAsync(c->P.az, 0, nb8, c->stream));
+    SPH_CHECK_HIP(hipMemsetAsync(c->P.dudt, 0, nb8, c->stream));
+    SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_NFORCE], 0, 8, c->stream));
+    SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_QUEUE2], 0, 8, c->stream));
+    SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_NDENS_F], 0, 8, c->stream));
+    if (c->P.nngb) SPH_CHECK_HIP(hipMemsetAsync(c->P.nngb, 0, (size_t)c->n * 4, c->stream));
+    SPH_CHECK_HIP(hipEventRecord(c->kev[2], c->stream));
+    SPH_TRY(launch_force(c, nullptr));
     SPH_CHECK_HIP(hipEventRecord(c->kev[3], c->stream));
     SPH_CHECK_HIP(hipEventRecord(c->ev[5], c->stream));
     unsigned long long nf = 0, ndf = 0;
     SPH_CHECK_HIP(hipMemcpyAsync(&nf, &cnt[CNT_NFORCE], 8, hipMemcpyDeviceToHost, c->stream));
     SPH_CHECK_HIP(hipMemcpyAsync(&ndf, &cnt[CNT_NDENS_F], 8, hipMemcpyDeviceToHost, c->stream));
     SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
-    c->st.n_dens = (int64_t)ndf;  // exact at the final H
     {
         float ms = 0.f;
         SPH_CHECK_HIP(hipEventElapsedTime(&ms, c->kev[2], c->kev[3]));
         c->st.t_force_kernel_ms = ms;
     }
     c->st.n_force = (int64_t)nf;
+    c->st.n_dens = (int64_t)ndf;  // exact at the final H
     c->force_done = true;
     return SPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Graph mode: density sweeps, ghost and force captured in one hipGraph.  The
+// sweep count is data dependent, so the graph holds a fixed number of sweeps
+// gated by a device flag: 0 = sweeping, 1 = converged (the remaining sweeps
+// exit at once, ghost and force run), 2 = the host must take over (lists or
+// grid need rebuilding, or H hit the box limit; ghost and force are skipped).
+// Counters and outputs are cleared by kernels, not memset nodes.  Grids cover
+// the leaf capacity and the kernels read the leaf count from the device, so
+// one graph serves every rebuild that keeps the buffers in place; it is
+// captured again when any kernel argument changes.
+// ---------------------------------------------------------------------------
+#define SPH_GRAPH_SWEEPS 4
+
+__global__ void k_graph_begin(unsigned long long* cnt, int* flags, int* gate)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        for (int k = 0; k < CNT_NPAIR; k++) cnt[k] = 0ull;
+        cnt[CNT_NDENS_F] = 0ull;
+        cnt[CNT_GSWEEPS] = 0ull;
+        flags[FI_FLAGS] = 0;
+        *gate = 0;
+    }
+}
+
+__global__ void k_sweep_begin(unsigned long long* cnt, int* flags, const int* gate)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0 && *gate == 0) {
+        cnt[CNT_UNCONV] = 0ull;
+        cnt[CNT_QUEUE] = 0ull;
+        flags[FI_FLAGS] = 0;
+        cnt[CNT_GSWEEPS] += 1ull;
+    }
+}
+
+// same decision order as the host loop: box limit, converged, rebuild/relist
+__global__ void k_sweep_end(const unsigned long long* cnt, const int* flags, int* gate)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0 && *gate == 0) {
+        const int f = flags[FI_FLAGS];
+        if (f & FLAG_BOX_SMALL) *gate = 2;
+        else if (cnt[CNT_UNCONV] == 0ull) *gate = 1;
+        else if (f & (FLAG_RELIST | FLAG_REBUILD)) *gate = 2;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_force_zero(int64_t n, double* ax, double* ay, double* az, double* dudt,
+                                                    int32_t* nngb, unsigned long long* cnt, const int* gate)
+{
+    if (*gate != 1) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        cnt[CNT_NFORCE] = 0ull;
+        cnt[CNT_QUEUE2] = 0ull;
+        cnt[CNT_NDENS_F] = 0ull;
+    }
+    if (i < n) {
+        ax[i] = 0.0;
+        ay[i] = 0.0;
+        az[i] = 0.0;
+        dudt[i] = 0.0;
+        if (nngb) nngb[i] = 0;
+    }
+}
+
+template <typename X>
+static void key_put(std::vector<uint8_t>& k, const X& x)
+{
+    const uint8_t* p = (const uint8_t*)&x;
+    k.insert(k.end(), p, p + sizeof(X));
+}
+
+// Every argument and grid size the graph's launches would take now.
+static std::vector<uint8_t> graph_key(sph_ctx* c, const double* u, const double* vx, const double* vy,
+                                      const double* vz, int sweeps)
+{
+    const int* gate = (const int*)c->flags.p + FI_GATE;
+    std::vector<uint8_t> k;
+    DensArgs da;
+    ForceArgs fa;
+    int nbd = 0, nbf = 0;
+    dens_args(c, gate, true, da, nbd);
+    force_args(c, gate, true, fa, nbf);
+    key_put(k, da);
+    key_put(k, fa);
+    key_put(k, nbd);
+    key_put(k, nbf);
+    key_put(k, sweeps);
+    key_put(k, c->n);
+    key_put(k, leaf_capacity(c));
+    const void* ptrs[] = {u, vx, vy, vz, c->hlo.p, c->hhi.p, c->conv.p, c->l_active.p, c->P.omega, c->P.P, c->fv4.p,
+                          c->hf.p, c->P.rho, c->P.drho_dH, c->P.H, c->stream};
+    key_put(k, ptrs);
+    key_put(k, c->prm.precision);
+    key_put(k, c->prm.prune);
+    key_put(k, c->prm.exec_mode);
+    return k;
+}
+
+static sph_status capture_dgf(sph_ctx* c, const double* u, const double* vx, const double* vy, const double* vz,
+                              int sweeps)
+{
+    if (c->graph_exec) {
+        (void)hipGraphExecDestroy((hipGraphExec_t)c->graph_exec);
+        c->graph_exec = nullptr;
+    }
+    c->graph_key.clear();
+    // the caller's stream may be the legacy default stream, which cannot be
+    // captured: record on a private stream, launch on the caller's
+    if (!c->cap_stream) SPH_CHECK_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    const hipStream_t user = c->stream;
+    c->stream = c->cap_stream;
+    int* gate = (int*)c->flags.p + FI_GATE;
+    unsigned long long* cnt = (unsigned long long*)c->counters.p;
+    int* flags = (int*)c->flags.p;
+    const int* nl_dev = (const int*)c->flags.p + FI_NLEAVES;
+    const int nlc = leaf_capacity(c);
+    if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        c->stream = user;
+        return SPH_ERR_HIP;
+    }
+    sph_status st = SPH_OK;
+    k_density_reset<<<blocks_for(std::max<int64_t>(c->n, nlc), 256), 256, 0, c->stream>>>(
+        c->n, nlc, (double*)c->hlo.p, (double*)c->hhi.p, (uint8_t*)c->conv.p, (int*)c->l_active.p, nl_dev);
+    k_graph_begin<<<1, 64, 0, c->stream>>>(cnt, flags, gate);
+    for (int k = 0; k < sweeps && st == SPH_OK; k++) {
+        k_sweep_begin<<<1, 64, 0, c->stream>>>(cnt, flags, gate);
+        st = launch_density(c, gate, true);
+        k_sweep_end<<<1, 64, 0, c->stream>>>(cnt, flags, gate);
+    }
+    if (st == SPH_OK) st = launch_ghost(c, u, vx, vy, vz, gate);
+    k_force_zero<<<blocks_for(c->n, 256), 256, 0, c->stream>>>(c->n, c->P.ax, c->P.ay, c->P.az, c->P.dudt, c->P.nngb,
+                                                              cnt, gate);
+    if (st == SPH_OK) st = launch_force(c, gate, true);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->stream, &g);
+    c->stream = user;
+    if (st != SPH_OK || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return st != SPH_OK ? st : SPH_ERR_HIP;
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return SPH_ERR_HIP;
+    c->graph_exec = ex;
+    c->graph_key = graph_key(c, u, vx, vy, vz, sweeps);
+    c->st.graph_captures++;
+    return SPH_OK;
+}
+
+// Density, ghost and force through the captured graph; the host finishes
+// whatever the graph could not (more sweeps, list or grid rebuilds).
+sph_status dgf_graph(sph_ctx* c)
+{
+    if (!c->sorted) return SPH_ERR_STATE;
+    const bool pr = c->predicted;
+    const double* u = pr ? (const double*)c->upr.p : c->P.u;
+    const double* vx = pr ? (const double*)c->vpx.p : c->P.vx;
+    const double* vy = pr ? (const double*)c->vpy.p : c->P.vy;
+    const double* vz = pr ? (const double*)c->vpz.p : c->P.vz;
+    SPH_TRY(buf_ensure(c->hlo, (size_t)c->n * 8));
+    SPH_TRY(buf_ensure(c->hhi, (size_t)c->n * 8));
+    SPH_TRY(buf_ensure(c->conv, (size_t)c->n));
+    const int sweeps = std::min(SPH_GRAPH_SWEEPS, c->prm.max_h_iter);
+    if (!c->graph_exec || c->graph_key != graph_key(c, u, vx, vy, vz, sweeps))
+        SPH_TRY(capture_dgf(c, u, vx, vy, vz, sweeps));
+    c->st.relists = 0;
+    c->st.n_density_launches = 0;
+    c->st.n_dens_evals = 0;
+    SPH_CHECK_HIP(hipEventRecord(c->ev[0], c->stream));
+    SPH_CHECK_HIP(hipGraphLaunch((hipGraphExec_t)c->graph_exec, c->stream));
+    SPH_CHECK_HIP(hipEventRecord(c->ev[1], c->stream));
+    int hfl[FI_GATE + 1];
+    unsigned long long hc[CNT_N];
+    SPH_CHECK_HIP(hipMemcpyAsync(hfl, c->flags.p, sizeof(hfl), hipMemcpyDeviceToHost, c->stream));
+    SPH_CHECK_HIP(hipMemcpyAsync(hc, c->counters.p, sizeof(hc), hipMemcpyDeviceToHost, c->stream));
+    SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
+    const int gate = hfl[FI_GATE], fl = hfl[FI_FLAGS];
+    const int gsweeps = (int)hc[CNT_GSWEEPS];
+    // the graph's kernels are not timed one by one
+    c->st.t_density_kernels_ms = -1.0;
+    c->st.t_force_kernel_ms = -1.0;
+    c->st.n_density_launches = gsweeps;
+    c->st.n_dens_evals = (int64_t)hc[CNT_DEVAL];
+    if (gate == 1) {
+        c->st.sweeps = gsweeps;
+        c->st.n_unconverged = 0;
+        c->st.n_force = (int64_t)hc[CNT_NFORCE];
+        c->st.n_dens = (int64_t)hc[CNT_NDENS_F];
+        c->dens_done = c->ghost_done = c->force_done = true;
+        // the whole graph is accounted as the density stage
+        for (int k = 2; k < 6; k++) SPH_CHECK_HIP(hipEventRecord(c->ev[k], c->stream));
+        return SPH_OK;
+    }
+    // the host takes over from the state the graph left
+    c->st.graph_fallbacks++;
+    if (fl & FLAG_BOX_SMALL) return SPH_ERR_BOX_TOO_SMALL;
+    if (fl & FLAG_REBUILD) {
+        SPH_TRY(build_all(c));
+        SPH_TRY(sort_all(c));
+        k_density_reset<<<blocks_for(std::max<int64_t>(c->n, c->n_leaves), 256), 256, 0, c->stream>>>(
+            c->n, c->n_leaves, (double*)c->hlo.p, (double*)c->hhi.p, (uint8_t*)c->conv.p, (int*)c->l_active.p,
+            nullptr);
+        SPH_CHECK_LAUNCH();
+        SPH_CHECK_HIP(hipMemsetAsync(&((unsigned long long*)c->counters.p)[CNT_NDENS], 0, 8, c->stream));
+        c->st.rebuilds++;
+    } else if (fl & FLAG_RELIST) {
+        SPH_TRY(relist(c));
+        c->st.relists++;
+    }
+    sph_status s = density_loop(c, gsweeps, hc[CNT_UNCONV]);
+    c->st.t_density_kernels_ms = -1.0;
+    SPH_CHECK_HIP(hipEventRecord(c->ev[1], c->stream));
+    if (s != SPH_OK) return s;
+    SPH_TRY(ghost_all(c));
+    return force_all(c);
 }
 
 sph_status domain_sums(sph_ctx* c, double* host_out)
@@ -1350,11 +1643,15 @@ sph_status step_all(sph_ctx* c, double dt)
                                          dt, (double*)c->vpx.p, (double*)c->vpy.p, (double*)c->vpz.p,
                                          (double*)c->upr.p);
     SPH_CHECK_LAUNCH();
-    sph_status s = density_all(c);
-    if (s != SPH_OK) return s;
+    sph_status s;
     c->predicted = true;
-    s = ghost_all(c);
-    if (s == SPH_OK) s = force_all(c);
+    if (c->prm.use_graph) {
+        s = dgf_graph(c);
+    } else {
+        s = density_all(c);
+        if (s == SPH_OK) s = ghost_all(c);
+        if (s == SPH_OK) s = force_all(c);
+    }
     c->predicted = false;
     if (s != SPH_OK) return s;
     k_kick<<<nb, 256, 0, c->stream>>>(c->n, c->P.vx, c->P.vy, c->P.vz, c->P.u, c->P.ax, c->P.ay, c->P.az, c->P.dudt, dt);

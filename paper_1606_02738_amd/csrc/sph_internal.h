@@ -41,7 +41,7 @@ struct Node {
 struct WNode {
     float lo[3], hi[3];
     int first_child;
-    int n_child;
+    int next;         // node after this subtree in depth-first order (-1: end of the top cell)
     int count;
     int leaf;
 };
@@ -84,10 +84,10 @@ enum {
 };
 
 // Slots of the int[64] flags buffer.
-enum { FI_FLAGS = 0, FI_SCRATCH = 8, FI_NCHILD = 9, FI_NLEAVES = 10, FI_NLIST = 11, FI_NFLAGS = 64 };
+enum { FI_FLAGS = 0, FI_SCRATCH = 8, FI_NCHILD = 9, FI_NLEAVES = 10, FI_NLIST = 11, FI_GATE = 12, FI_NFLAGS = 64 };
 
 // Counters written by kernels (device, int64).
-enum { CNT_UNCONV = 0, CNT_NDENS = 1, CNT_NFORCE = 2, CNT_QUEUE = 3, CNT_QUEUE2 = 4, CNT_DEVAL = 5, CNT_NPAIR = 6, CNT_NDENS_F = 7, CNT_N = 8 };
+enum { CNT_UNCONV = 0, CNT_NDENS = 1, CNT_NFORCE = 2, CNT_QUEUE = 3, CNT_QUEUE2 = 4, CNT_DEVAL = 5, CNT_NPAIR = 6, CNT_NDENS_F = 7, CNT_GSWEEPS = 8, CNT_N = 16 };
 
 // Leaf arrays (device SoA).
 struct LeafArrays {

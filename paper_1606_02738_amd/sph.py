@@ -41,7 +41,7 @@ class Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("eta", C.c_double), ("kernel_gamma", C.c_double),
                 ("h_tol", C.c_double), ("max_h_iter", C.c_int), ("n_split", C.c_int),
                 ("precision", C.c_int), ("exec_mode", C.c_int), ("n_domains", C.c_int),
-                ("persistent_wgs", C.c_int), ("waves_per_wg", C.c_int), ("prune", C.c_int),
+                ("persistent_wgs", C.c_int), ("use_graph", C.c_int), ("prune", C.c_int),
                 ("boxes", C.POINTER(C.c_double))]
 
 
@@ -59,7 +59,8 @@ class Stats(C.Structure):
                 ("t_density_ms", C.c_double), ("t_ghost_ms", C.c_double),
                 ("t_force_ms", C.c_double), ("t_build_ms", C.c_double),
                 ("t_density_kernels_ms", C.c_double), ("t_force_kernel_ms", C.c_double),
-                ("n_dens_evals", C.c_int64), ("n_density_launches", C.c_int32), ("pad", C.c_int32)]
+                ("n_dens_evals", C.c_int64), ("n_density_launches", C.c_int32),
+                ("graph_captures", C.c_int32), ("graph_fallbacks", C.c_int32), ("pad", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -69,7 +70,7 @@ class Stats(C.Structure):
 
 _lib = None
 EXPORTS = ("sph_create", "sph_destroy", "sph_build_cells", "sph_sort_cells", "sph_density",
-           "sph_ghost", "sph_force", "sph_step", "sph_get_stats", "sph_domain_sums",
+           "sph_ghost", "sph_force", "sph_density_ghost_force", "sph_step", "sph_get_stats", "sph_domain_sums",
            "sph_status_str", "sph_version")
 
 
@@ -84,7 +85,7 @@ def lib():
         L.sph_create.argtypes = [C.POINTER(Params), vp, C.POINTER(vp)]
         L.sph_destroy.argtypes = [vp]
         L.sph_build_cells.argtypes = [vp, C.POINTER(Particles)]
-        for f in ("sph_sort_cells", "sph_density", "sph_ghost", "sph_force"):
+        for f in ("sph_sort_cells", "sph_density", "sph_ghost", "sph_force", "sph_density_ghost_force"):
             getattr(L, f).argtypes = [vp]
         L.sph_step.argtypes = [vp, C.c_double]
         L.sph_get_stats.argtypes = [vp, C.POINTER(Stats)]
@@ -137,7 +138,7 @@ class SPH:
 
     def __init__(self, boxes, precision="fp32c", exec_mode="grid", gamma=5.0 / 3.0, eta=1.2348,
                  kernel_gamma=math.sqrt(10.0 / 3.0), h_tol=None, max_h_iter=40, n_split=64,
-                 persistent_wgs=0, prune="box", stream=None):
+                 persistent_wgs=0, prune="box", use_graph=False, stream=None):
         import torch
         self._torch = torch
         b = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(-1, 3))
@@ -150,7 +151,7 @@ class SPH:
         p.gamma, p.eta, p.kernel_gamma, p.h_tol = gamma, eta, kernel_gamma, h_tol
         p.max_h_iter, p.n_split, p.precision = max_h_iter, n_split, prec
         p.exec_mode = EXEC_MODES[exec_mode] if isinstance(exec_mode, str) else int(exec_mode)
-        p.n_domains, p.persistent_wgs, p.waves_per_wg = self.n_domains, persistent_wgs, 0
+        p.n_domains, p.persistent_wgs, p.use_graph = self.n_domains, persistent_wgs, int(bool(use_graph))
         p.prune = PRUNE_MODES[prune] if isinstance(prune, str) else int(prune)
         p.boxes = b.ctypes.data_as(C.POINTER(C.c_double))
         self.params = p
@@ -198,6 +199,9 @@ class SPH:
 
     def force(self):
         _check(lib().sph_force(self.h), "sph_force")
+
+    def density_ghost_force(self):
+        _check(lib().sph_density_ghost_force(self.h), "sph_density_ghost_force")
 
     def step(self, dt):
         _check(lib().sph_step(self.h, float(dt)), "sph_step")

@@ -48,7 +48,7 @@ def _params(**kw):
     box = np.ones(3)
     p.gamma, p.eta, p.kernel_gamma, p.h_tol = 5 / 3, 1.2348, math.sqrt(10 / 3), 1e-6
     p.max_h_iter, p.n_split, p.precision, p.exec_mode = 20, 64, 1, 0
-    p.n_domains, p.persistent_wgs, p.waves_per_wg, p.prune = 1, 0, 0, 0
+    p.n_domains, p.persistent_wgs, p.use_graph, p.prune = 1, 0, 0, 0
     for k, v in kw.items():
         setattr(p, k, v)
     p.boxes = box.ctypes.data_as(C.POINTER(C.c_double))
@@ -57,7 +57,7 @@ def _params(**kw):
 
 @pytest.mark.parametrize("bad", [dict(gamma=1.0), dict(eta=0.0), dict(h_tol=0.0), dict(max_h_iter=0),
                                  dict(n_split=0), dict(n_split=65), dict(precision=7),
-                                 dict(exec_mode=3), dict(n_domains=0), dict(prune=2)])
+                                 dict(exec_mode=3), dict(n_domains=0), dict(prune=2), dict(use_graph=2)])
 def test_create_rejects_bad_params(L, bad):
     p, box = _params(**bad)
     h = C.c_void_p()
@@ -68,7 +68,7 @@ def test_create_rejects_bad_params(L, bad):
 def test_null_arguments(L):
     assert L.sph_create(None, None, None) == -1
     assert L.sph_destroy(None) == 0
-    for f in ("sph_sort_cells", "sph_density", "sph_ghost", "sph_force"):
+    for f in ("sph_sort_cells", "sph_density", "sph_ghost", "sph_force", "sph_density_ghost_force"):
         assert getattr(L, f)(None) == -1
     assert L.sph_step(None, 0.1) == -1
     assert L.sph_build_cells(None, None) == -1
