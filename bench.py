@@ -38,6 +38,27 @@ FLOPS_FORCE = {"fp32c": 64, "fp32": 52, "fp64": 52}
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when there is none or the interaction-kernel sources
+    have changed since the counters were taken."""
+    import hashlib
+    f = os.path.join(ROOT, "profiles", "%s_%s_hbm.md" % (kernel, workload))
+    if not os.path.exists(f):
+        return None
+    kv = {}
+    for line in open(f):
+        if ":" in line and not line.startswith((" ", "#", "|")):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for src in ("paper_1606_02738_amd/csrc/sph_interact.hip", "paper_1606_02738_amd/csrc/sph_internal.h"):
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if kv.get("sources_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in kv:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -155,8 +176,11 @@ def main():
     else:
         kname, kflops, kms, klaunch = "k_force", force_flops, force_ms, args.steps
     achieved = kflops / (kms / 1e3) / 1e12
+    traffic = None
+    if kname in ("k_force", "k_density") and not args.graph and args.exec_mode == "grid" and args.prune == "box":
+        traffic = measured_traffic(kname, "clustered%d_%s" % (args.n_side, prec))
     roof = {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS, "traffic": traffic,
             "launches": klaunch, "avg_launch_ms": kms / max(1, klaunch),
             "flop_per_launch": kflops / max(1, klaunch)}
     other = {"k_density": {"ms_total": dens_ms, "launches": dens_launch,
@@ -187,6 +211,8 @@ def main():
         "n_force_per_step": force_pairs / args.steps,
         "interactions_per_s_density_ghost_force": inter / t_dgf,
         "mean_sweeps": sum(s["sweeps"] for s in per) / args.steps,
+        "unconverged_after_sweep": [s["unconv_after"][:s["sweeps"]] for s in per],
+        "density_evals_per_neighbour": sum(s["n_dens_evals"] for s in per) / max(1, sum(s["n_dens"] for s in per)),
         "phase_ms_per_step": {"density": sum(s["t_density_ms"] for s in per) / args.steps,
                               "ghost": sum(s["t_ghost_ms"] for s in per) / args.steps,
                               "force": sum(s["t_force_ms"] for s in per) / args.steps},

@@ -126,6 +126,8 @@ typedef struct {
     int32_t graph_captures;     /* graph (re)captures since sph_create (use_graph = 1) */
     int32_t graph_fallbacks;    /* graph runs the host had to finish since sph_create */
     int32_t pad;
+    int32_t unconv_after[8];    /* particles left unconverged after sweep k+1 of the last
+                                   density call (-1: sweep not run) */
 } sph_stats;
 
 typedef struct sph_ctx sph_ctx;

@@ -1195,6 +1195,7 @@ static sph_status density_reset(sph_ctx* c)
     c->st.t_density_kernels_ms = 0.0;
     c->st.n_density_launches = 0;
     c->st.n_dens_evals = 0;
+    for (int k = 0; k < 8; k++) c->st.unconv_after[k] = -1;
     return SPH_OK;
 }
 
@@ -1228,6 +1229,7 @@ static sph_status density_loop(sph_ctx* c, int done_sweeps, unsigned long long u
             c->st.n_dens_evals = (int64_t)hc[CNT_DEVAL];
         }
         unconv = hc[CNT_UNCONV];
+        if (sweeps <= 8) c->st.unconv_after[sweeps - 1] = (int)std::min<unsigned long long>(unconv, INT32_MAX);
         if (fl & FLAG_BOX_SMALL) status = SPH_ERR_BOX_TOO_SMALL;
         if (unconv == 0) break;
         if (fl & FLAG_REBUILD) {
@@ -1407,6 +1409,7 @@ __global__ void k_graph_begin(unsigned long long* cnt, int* flags, int* gate)
         for (int k = 0; k < CNT_NPAIR; k++) cnt[k] = 0ull;
         cnt[CNT_NDENS_F] = 0ull;
         cnt[CNT_GSWEEPS] = 0ull;
+        for (int k = CNT_UHIST; k < CNT_N; k++) cnt[k] = 0ull;
         flags[FI_FLAGS] = 0;
         *gate = 0;
     }
@@ -1423,10 +1426,12 @@ __global__ void k_sweep_begin(unsigned long long* cnt, int* flags, const int* ga
 }
 
 // same decision order as the host loop: box limit, converged, rebuild/relist
-__global__ void k_sweep_end(const unsigned long long* cnt, const int* flags, int* gate)
+__global__ void k_sweep_end(unsigned long long* cnt, const int* flags, int* gate)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0 && *gate == 0) {
         const int f = flags[FI_FLAGS];
+        const unsigned long long k = cnt[CNT_GSWEEPS];
+        if (k >= 1 && k <= CNT_N - CNT_UHIST) cnt[CNT_UHIST + k - 1] = cnt[CNT_UNCONV];
         if (f & FLAG_BOX_SMALL) *gate = 2;
         else if (cnt[CNT_UNCONV] == 0ull) *gate = 1;
         else if (f & (FLAG_RELIST | FLAG_REBUILD)) *gate = 2;
@@ -1558,6 +1563,7 @@ sph_status dgf_graph(sph_ctx* c)
     c->st.relists = 0;
     c->st.n_density_launches = 0;
     c->st.n_dens_evals = 0;
+    for (int k = 0; k < 8; k++) c->st.unconv_after[k] = -1;
     SPH_CHECK_HIP(hipEventRecord(c->ev[0], c->stream));
     SPH_CHECK_HIP(hipGraphLaunch((hipGraphExec_t)c->graph_exec, c->stream));
     SPH_CHECK_HIP(hipEventRecord(c->ev[1], c->stream));
@@ -1573,6 +1579,10 @@ sph_status dgf_graph(sph_ctx* c)
     c->st.t_force_kernel_ms = -1.0;
     c->st.n_density_launches = gsweeps;
     c->st.n_dens_evals = (int64_t)hc[CNT_DEVAL];
+    for (int k = 0; k < 8; k++)
+        c->st.unconv_after[k] = k < gsweeps && k < CNT_N - CNT_UHIST
+                                    ? (int)std::min<unsigned long long>(hc[CNT_UHIST + k], INT32_MAX)
+                                    : -1;
     if (gate == 1) {
         c->st.sweeps = gsweeps;
         c->st.n_unconverged = 0;

@@ -60,11 +60,13 @@ class Stats(C.Structure):
                 ("t_force_ms", C.c_double), ("t_build_ms", C.c_double),
                 ("t_density_kernels_ms", C.c_double), ("t_force_kernel_ms", C.c_double),
                 ("n_dens_evals", C.c_int64), ("n_density_launches", C.c_int32),
-                ("graph_captures", C.c_int32), ("graph_fallbacks", C.c_int32), ("pad", C.c_int32)]
+                ("graph_captures", C.c_int32), ("graph_fallbacks", C.c_int32), ("pad", C.c_int32),
+                ("unconv_after", C.c_int32 * 8)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["conserved"] = list(self.conserved)
+        d["unconv_after"] = list(self.unconv_after)
         return d
 
 
