@@ -189,6 +189,99 @@ sph_status sph_density_ghost_force(sph_ctx* ctx);
  * positions). */
 sph_status sph_step(sph_ctx* ctx, double dt);
 
+/* ---------------------------------------------------------------------------
+ * Learned smoothing-length predictor.
+ *
+ * The density stage solves rho H^3 = (kernel_gamma eta)^3 m per particle by
+ * Newton-Raphson (Sec. 2); sph_step warm-starts it from the previous H.  The
+ * predictor replaces that starting point: after the drift a small network
+ * maps per-particle features to y = log(H_new / H_prev) and the iteration
+ * starts from H_prev exp(y).  The plain iteration still decides convergence,
+ * so the converged H does not depend on the prediction; a particle whose
+ * prediction is off simply needs more sweeps (reported as unconv_after[0]).
+ *
+ * Features (SPH_MLP_NF used, stored as float[SPH_MLP_XSTRIDE] rows, columns
+ * SPH_MLP_NF.. zero), from positions after the drift, velocities after the
+ * first half kick, and H, rho, P, du/dt of the previous evaluation; the
+ * feature grid of a box with edges L and n particles has
+ * G_a = clamp(floor(L_a / s + 1/2), 1, 256) cells per axis, s = 2 (V/n)^(1/3):
+ *   0  log(H / (V/n)^(1/3))
+ *   1  log(particle count of the particle's grid cell)
+ *   2  log(count of the 27 cells around it / (27 n / (G_x G_y G_z)))
+ *   3  |g|, g_a = (S+_a - S-_a) / S27, S+-_a the counts of the 9 cells at
+ *      offset +-1 along axis a (periodic), S27 the 27-cell count
+ *   4  sum_a g_a (f_a - 1/2), f_a the fractional position inside the cell
+ *   5  -dt rho du/dt / (3 P) (first-order change of log H implied by the
+ *      continuity and energy equations; 0 where P <= 0)
+ *   6  dt |v| / H
+ *
+ * Network: 16 inputs (features, zero-padded) standardised by xmu, xsd;
+ * three hidden layers of 64 SiLU units; one output o; y = ymu + ysd o.
+ * Parameter vector (float32, SPH_MLP_NP values):
+ *   W1[16][64] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] w4[64] b4
+ *   (SPH_MLP_NT trained values), then xmu[16] xsd[16] ymu ysd.
+ * W1, W2, W3 and w4 enter the network rounded to bfloat16 (nearest, ties to
+ * even); biases are used in float32; products accumulate in float32.
+ * Training minimises L = 1/(2n) sum (o - (y - ymu)/ysd)^2 with Adam.
+ * ------------------------------------------------------------------------- */
+#define SPH_MLP_NF 7
+#define SPH_MLP_XSTRIDE 8
+#define SPH_MLP_NIN 16
+#define SPH_MLP_NH 64
+#define SPH_MLP_NT 9473
+#define SPH_MLP_NP 9507
+
+/* Network output for n feature rows: y[i] = predicted log(H_new/H_prev).
+ * params: SPH_MLP_NP floats, X: n x SPH_MLP_XSTRIDE floats, y: n floats; all
+ * DEVICE pointers.  Matrix products on the MFMA units (bfloat16 weights,
+ * activations split into two bfloat16 terms, float32 accumulation).
+ * hip_stream: hipStream_t (NULL = default).  SPH_ERR_INVALID on n < 0 or a
+ * NULL pointer with n > 0. */
+sph_status sph_mlp_forward(const float* params, const float* X, int64_t n, float* y, void* hip_stream);
+
+/* Mean loss (HOST *loss, may be NULL) and its gradient with respect to the
+ * SPH_MLP_NT trained parameters (DEVICE grad) over n rows (X as above, y:
+ * n target values of log(H_new/H_prev)); float32 arithmetic with the
+ * bfloat16-rounded weights.  Synchronises the stream. */
+sph_status sph_mlp_loss_grad(const float* params, const float* X, const float* y, int64_t n, float* grad,
+                             double* loss, void* hip_stream);
+
+/* One Adam step (step number t >= 1) on the SPH_MLP_NT trained values of
+ * params with moment buffers m, v (SPH_MLP_NT floats each, DEVICE):
+ * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps). */
+sph_status sph_mlp_adam(float* params, float* m, float* v, const float* grad, int t, float lr, float beta1,
+                        float beta2, float eps, void* hip_stream);
+
+/* Features of the bound particles in their current order, with the current
+ * H, rho, P, du/dt as the previous evaluation's and step dt, into X (DEVICE,
+ * n x SPH_MLP_XSTRIDE floats).  Requires sph_build_cells. */
+sph_status sph_h_features(sph_ctx* ctx, double dt, float* X);
+
+/* Record training samples during the following sph_step calls: each step
+ * keeps about rate * n particles (chosen by a hash of seed, step count and
+ * index) as (features, log(H_converged / H_prev)) until `capacity` samples
+ * are held on the device.  capacity = 0 stops recording and frees the
+ * samples.  Returns the number held so far through *held (HOST, may be NULL). */
+sph_status sph_h_record(sph_ctx* ctx, int64_t capacity, double rate, uint64_t seed, int64_t* held);
+
+/* Train the context's network on the recorded samples with the library's
+ * forward, backward and Adam kernels: `epochs` passes in minibatches of
+ * `batch` rows (a different affine permutation of the samples per epoch),
+ * learning rate lr.  init = 1 starts from fresh weights (seeded) and sets the
+ * standardisation constants from the samples; init = 0 continues.  *loss
+ * (HOST, may be NULL) = mean minibatch loss of the last epoch. */
+sph_status sph_h_train(sph_ctx* ctx, int epochs, int batch, double lr, uint64_t seed, int init, double* loss);
+
+/* Set / read the context's network parameters (HOST, SPH_MLP_NP floats). */
+sph_status sph_h_set_params(sph_ctx* ctx, const float* params);
+sph_status sph_h_get_params(sph_ctx* ctx, float* params);
+
+/* on = 1: sph_step starts the density iteration from the network's
+ * prediction (requires parameters set or trained); on = 0: from the previous
+ * H (the plain method). */
+sph_status sph_h_predict(sph_ctx* ctx, int on);
+
 /* Copy counters and timings to *out (synchronises the stream). */
 sph_status sph_get_stats(sph_ctx* ctx, sph_stats* out);
 

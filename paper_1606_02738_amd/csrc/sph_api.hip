@@ -101,7 +101,7 @@ sph_status sph_destroy(sph_ctx* c)
                      &c->l_origin, &c->l_lo, &c->l_hi, &c->l_hlist, &c->l_dom, &c->l_off, &c->l_active, &c->l_sorted,
                      &c->l_cnt, &c->l_cost, &c->l_order, &c->list, &c->pos4, &c->fv4, &c->hf, &c->skey, &c->sidx,
                      &c->hlo, &c->hhi, &c->conv, &c->vpx, &c->vpy, &c->vpz, &c->upr, &c->flags, &c->counters,
-                     &c->scan_tmp, &c->rs_hist, &c->sums, &c->dsum_part};
+                     &c->scan_tmp, &c->rs_hist, &c->sums, &c->dsum_part, &c->fgrid, &c->fcount, &c->mlp_X, &c->mlp_hprev, &c->mlp_params, &c->mlp_packed, &c->mlp_m, &c->mlp_v, &c->ds_X, &c->ds_y, &c->ds_count};
     for (DevBuf* b : all) buf_free(*b);
     for (int k = 0; k < 8; k++)
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
@@ -126,6 +126,7 @@ sph_status sph_build_cells(sph_ctx* c, const sph_particles* p)
     c->n = p->n;
     c->bound = true;
     c->built = c->sorted = c->dens_done = c->ghost_done = c->force_done = false;
+    c->mlp_pending = false;
     SPH_CHECK_HIP(hipEventRecord(c->ev[6], c->stream));
     sph_status s = build_all(c);
     if (s == SPH_OK) c->st.rebuilds++;

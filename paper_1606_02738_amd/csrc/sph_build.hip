@@ -110,6 +110,11 @@ __global__ __launch_bounds__(256) void k_keys(int64_t n, const double* __restric
     vals[i] = (uint32_t)i;
 }
 
+struct FeatRow {
+    float4 a, b;  // one row of predictor features (SPH_MLP_XSTRIDE floats)
+};
+static_assert(sizeof(FeatRow) == SPH_MLP_XSTRIDE * sizeof(float), "feature row");
+
 template <typename V>
 __global__ __launch_bounds__(256) void k_gather(int64_t n, const uint32_t* __restrict__ perm, const V* __restrict__ src,
                                                 V* __restrict__ dst)
@@ -660,6 +665,17 @@ static sph_status permute_all(sph_ctx* c, const uint32_t* perm)
         k_gather<int32_t><<<nb, 256, 0, c->stream>>>(n, perm, c->P.domain, (int32_t*)c->tmp.p);
         SPH_CHECK_LAUNCH();
         SPH_CHECK_HIP(hipMemcpyAsync(c->P.domain, c->tmp.p, (size_t)n * 4, hipMemcpyDeviceToDevice, c->stream));
+    }
+    if (c->mlp_pending) {
+        // predictor features and previous H of this step follow their particles
+        k_gather<double><<<nb, 256, 0, c->stream>>>(n, perm, (const double*)c->mlp_hprev.p, (double*)c->tmp.p);
+        SPH_CHECK_LAUNCH();
+        SPH_CHECK_HIP(hipMemcpyAsync(c->mlp_hprev.p, c->tmp.p, (size_t)n * 8, hipMemcpyDeviceToDevice, c->stream));
+        SPH_TRY(buf_ensure(c->tmp, (size_t)n * sizeof(float4) * 2));
+        k_gather<FeatRow><<<nb, 256, 0, c->stream>>>(n, perm, (const FeatRow*)c->mlp_X.p, (FeatRow*)c->tmp.p);
+        SPH_CHECK_LAUNCH();
+        SPH_CHECK_HIP(hipMemcpyAsync(c->mlp_X.p, c->tmp.p, (size_t)n * sizeof(FeatRow), hipMemcpyDeviceToDevice,
+                                     c->stream));
     }
     return SPH_OK;
 }

@@ -69,6 +69,20 @@ struct sph_ctx {
     hipStream_t cap_stream = nullptr;  // private stream used only for capture
     hipEvent_t kev[4] = {};     // per-launch kernel timing
 
+    // learned H predictor
+    std::vector<FeatGrid> fgrid_h;
+    int64_t fgrid_n = -1, fgrid_cells = 0;
+    DevBuf fgrid, fcount;               // FeatGrid[], per-cell counts
+    DevBuf mlp_X, mlp_hprev;            // features and previous H of the current step (particle order)
+    DevBuf mlp_params, mlp_packed, mlp_m, mlp_v;
+    DevBuf ds_X, ds_y, ds_count;        // recorded samples
+    bool rec_on = false, h_pred = false, mlp_ready = false, mlp_have = false, mlp_pending = false;
+    int64_t rec_cap = 0;
+    double rec_rate = 0.0;
+    uint64_t rec_seed = 0;
+    int adam_t = 0;
+    int64_t step_count = 0;
+
     int elem_size() const { return prm.precision == SPH_FP64 ? 8 : 4; }
 };
 
@@ -108,4 +122,9 @@ sph_status ghost_all(sph_ctx* c);
 sph_status force_all(sph_ctx* c);
 sph_status step_all(sph_ctx* c, double dt);
 sph_status dgf_graph(sph_ctx* c);
+
+// learned H predictor (sph_mlp.hip)
+sph_status mlp_features(sph_ctx* c, double dt, float* X, double* hprev);
+sph_status mlp_pre_build(sph_ctx* c, double dt);
+sph_status mlp_post_step(sph_ctx* c);
 sph_status domain_sums(sph_ctx* c, double* host_out);

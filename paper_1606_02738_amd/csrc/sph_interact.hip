@@ -1642,6 +1642,8 @@ sph_status step_all(sph_ctx* c, double dt)
                                             c->P.ay, c->P.az, c->P.dudt, c->P.domain, (const DomainInfo*)c->dom_d.p,
                                             dt);
     SPH_CHECK_LAUNCH();
+    c->step_count++;
+    SPH_TRY(mlp_pre_build(c, dt));
     SPH_TRY(build_all(c));
     SPH_TRY(sort_all(c));
     const size_t nb8 = (size_t)c->n * 8;
@@ -1664,6 +1666,7 @@ sph_status step_all(sph_ctx* c, double dt)
     }
     c->predicted = false;
     if (s != SPH_OK) return s;
+    SPH_TRY(mlp_post_step(c));
     k_kick<<<nb, 256, 0, c->stream>>>(c->n, c->P.vx, c->P.vy, c->P.vz, c->P.u, c->P.ax, c->P.ay, c->P.az, c->P.dudt, dt);
     SPH_CHECK_LAUNCH();
     std::vector<double> sums((size_t)c->prm.n_domains * 5);

@@ -19,6 +19,18 @@ struct DomainInfo {
     int top_offset;   // global index of the box's first top cell
 };
 
+// Feature grid of one box for the learned H predictor: G cells per axis,
+// scale = G / L, mean spacing (V/n)^(1/3), mean count per cell, offset of
+// the box's counts in the shared count array.
+struct FeatGrid {
+    int G[3];
+    int pad;
+    double scale[3];
+    double sbox;
+    double nbar;
+    long long off;
+};
+
 // Octree cell.  Children of a cell are contiguous in the node array.
 struct Node {
     uint64_t key_lo;  // first Morton key of the cell

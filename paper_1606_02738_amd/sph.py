@@ -73,7 +73,11 @@ class Stats(C.Structure):
 _lib = None
 EXPORTS = ("sph_create", "sph_destroy", "sph_build_cells", "sph_sort_cells", "sph_density",
            "sph_ghost", "sph_force", "sph_density_ghost_force", "sph_step", "sph_get_stats", "sph_domain_sums",
-           "sph_status_str", "sph_version")
+           "sph_status_str", "sph_version", "sph_mlp_forward", "sph_mlp_loss_grad", "sph_mlp_adam",
+           "sph_h_features", "sph_h_record", "sph_h_train", "sph_h_set_params", "sph_h_get_params",
+           "sph_h_predict")
+
+MLP_NF, MLP_XSTRIDE, MLP_NIN, MLP_NH, MLP_NT, MLP_NP = 7, 8, 16, 64, 9473, 9507
 
 
 def lib():
@@ -95,6 +99,15 @@ def lib():
         L.sph_status_str.restype = C.c_char_p
         L.sph_status_str.argtypes = [C.c_int]
         L.sph_version.restype = C.c_char_p
+        L.sph_mlp_forward.argtypes = [vp, vp, C.c_int64, vp, vp]
+        L.sph_mlp_loss_grad.argtypes = [vp, vp, vp, C.c_int64, vp, C.POINTER(C.c_double), vp]
+        L.sph_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+        L.sph_h_features.argtypes = [vp, C.c_double, vp]
+        L.sph_h_record.argtypes = [vp, C.c_int64, C.c_double, C.c_uint64, C.POINTER(C.c_int64)]
+        L.sph_h_train.argtypes = [vp, C.c_int, C.c_int, C.c_double, C.c_uint64, C.c_int, C.POINTER(C.c_double)]
+        L.sph_h_set_params.argtypes = [vp, C.POINTER(C.c_float)]
+        L.sph_h_get_params.argtypes = [vp, C.POINTER(C.c_float)]
+        L.sph_h_predict.argtypes = [vp, C.c_int]
         for f in EXPORTS:
             if f not in ("sph_status_str", "sph_version"):
                 getattr(L, f).restype = C.c_int
@@ -105,6 +118,43 @@ def lib():
 def _check(st, where):
     if st != 0:
         raise SPHError(st, where)
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def mlp_forward(params, X, stream=None):
+    """Network output y (predicted log(H_new/H_prev)) for feature rows X
+    (n x 8 float32 device tensor); params: float32 device tensor of MLP_NP."""
+    import torch
+    assert params.dtype == torch.float32 and params.numel() == MLP_NP and params.is_cuda
+    assert X.dtype == torch.float32 and X.is_contiguous() and X.shape[-1] == MLP_XSTRIDE
+    n = X.shape[0]
+    y = torch.empty(n, dtype=torch.float32, device=X.device)
+    _check(lib().sph_mlp_forward(params.data_ptr(), X.data_ptr(), n, y.data_ptr(), _stream_ptr(stream)),
+           "sph_mlp_forward")
+    return y
+
+
+def mlp_loss_grad(params, X, y, stream=None):
+    """(mean loss, gradient tensor of MLP_NT floats) over the rows."""
+    import torch
+    assert X.dtype == torch.float32 and X.is_contiguous() and X.shape[-1] == MLP_XSTRIDE
+    assert y.dtype == torch.float32 and y.numel() == X.shape[0]
+    g = torch.empty(MLP_NT, dtype=torch.float32, device=X.device)
+    L = C.c_double()
+    _check(lib().sph_mlp_loss_grad(params.data_ptr(), X.data_ptr(), y.data_ptr(), X.shape[0], g.data_ptr(),
+                                   C.byref(L), _stream_ptr(stream)), "sph_mlp_loss_grad")
+    return L.value, g
+
+
+def mlp_adam(params, m, v, grad, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    """One Adam step in place on params, m, v (float32 device tensors)."""
+    _check(lib().sph_mlp_adam(params.data_ptr(), m.data_ptr(), v.data_ptr(), grad.data_ptr(), int(t), float(lr),
+                              float(beta1), float(beta2), float(eps), _stream_ptr(stream)), "sph_mlp_adam")
 
 
 def to_device(d, device="cuda"):
@@ -207,6 +257,41 @@ class SPH:
 
     def step(self, dt):
         _check(lib().sph_step(self.h, float(dt)), "sph_step")
+
+    def h_features(self, dt):
+        """Predictor features of the bound particles (n x 8 float32 tensor)."""
+        X = self._torch.empty((self.t["x"].numel(), MLP_XSTRIDE), dtype=self._torch.float32,
+                              device=self.t["x"].device)
+        _check(lib().sph_h_features(self.h, float(dt), X.data_ptr()), "sph_h_features")
+        return X
+
+    def h_record(self, capacity, rate=1.0, seed=1):
+        """Start (capacity > 0) or stop (0) recording training samples in
+        sph_step; returns the number held."""
+        held = C.c_int64()
+        _check(lib().sph_h_record(self.h, int(capacity), float(rate), int(seed), C.byref(held)), "sph_h_record")
+        return held.value
+
+    def h_train(self, epochs, batch=16384, lr=1e-3, seed=1, init=True):
+        """Train the predictor on the recorded samples; returns the mean
+        minibatch loss of the last epoch."""
+        L = C.c_double()
+        _check(lib().sph_h_train(self.h, int(epochs), int(batch), float(lr), int(seed), int(bool(init)),
+                                 C.byref(L)), "sph_h_train")
+        return L.value
+
+    def h_set_params(self, p):
+        a = np.ascontiguousarray(p, dtype=np.float32)
+        assert a.size == MLP_NP
+        _check(lib().sph_h_set_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float))), "sph_h_set_params")
+
+    def h_get_params(self):
+        a = np.zeros(MLP_NP, dtype=np.float32)
+        _check(lib().sph_h_get_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float))), "sph_h_get_params")
+        return a
+
+    def h_predict(self, on=True):
+        _check(lib().sph_h_predict(self.h, int(bool(on))), "sph_h_predict")
 
     def stats(self):
         s = Stats()
