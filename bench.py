@@ -81,6 +81,65 @@ def cpu_baseline(n_side, seed):
                       "solve + ghost + force, %.1f s" % (n_side, n_side ** 3, (n_side / 256) ** 3, dt)}
 
 
+def mlp_eval(S, sim, t, dt, steps, rec_steps=50, seed=17):
+    """Learned H predictor on the same workload: record samples over
+    `rec_steps` plain steps, train with the library's kernels, then time
+    `steps` steps from one saved state without and with the predictor."""
+    import torch
+    n = t["x"].numel()
+    rate = min(1.0, 6.0e6 / (rec_steps * n))
+    cap = int(rate * n * rec_steps * 1.2) + 1024
+    sim.h_record(cap, rate=rate, seed=seed)
+    t0 = time.perf_counter()
+    for _ in range(rec_steps):
+        sim.step(dt)
+    torch.cuda.synchronize()
+    rec_s = time.perf_counter() - t0
+    held = sim.h_record(cap, rate=rate, seed=seed)
+    log("predictor: %d samples from %d plain steps (%.1f s)" % (held, rec_steps, rec_s))
+    t0 = time.perf_counter()
+    loss = sim.h_train(epochs=4, batch=16384, lr=2e-3, seed=seed)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    log("predictor: trained in %.2f s, loss %.4g" % (train_s, loss))
+    sim.h_record(0)
+    state = {k: v.clone() for k, v in t.items()}
+    res = {}
+    for mode in ("plain", "mlp"):
+        for k in t:
+            t[k].copy_(state[k])
+        sim.bind(t)
+        sim.run()
+        sim.h_predict(mode == "mlp")
+        sim.step(dt)
+        torch.cuda.synchronize()
+        per = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sim.step(dt)
+            per.append(sim.stats())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res[mode] = {"ms_per_step": wall / steps * 1e3,
+                     "mean_sweeps": sum(q["sweeps"] for q in per) / steps,
+                     "second_sweep_fraction": sum(q["unconv_after"][0] for q in per) / (steps * n),
+                     "density_ms_per_step": sum(q["t_density_ms"] for q in per) / steps,
+                     "density_evals_per_neighbour": sum(q["n_dens_evals"] for q in per)
+                     / max(1, sum(q["n_dens"] for q in per)),
+                     "predict_ms_per_step": (sum(q["t_predict_ms"] for q in per) / steps) if mode == "mlp" else 0.0,
+                     "H": t["H"].clone()}
+        log("predictor %s: %.2f ms/step, sweeps %.2f, second-sweep fraction %.4g" % (
+            mode, res[mode]["ms_per_step"], res[mode]["mean_sweeps"], res[mode]["second_sweep_fraction"]))
+    sim.h_predict(False)
+    dH = float(((res["mlp"]["H"] - res["plain"]["H"]).abs() / res["plain"]["H"]).max())
+    for m in res.values():
+        del m["H"]
+    return {"samples": held, "record_steps": rec_steps, "train_s": train_s, "train_loss": loss,
+            "epochs": 4, "batch": 16384, "plain": res["plain"], "mlp": res["mlp"],
+            "max_rel_H_difference": dH,
+            "step_time_ratio_mlp_over_plain": res["mlp"]["ms_per_step"] / res["plain"]["ms_per_step"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +154,8 @@ def main():
     ap.add_argument("--cpu-n-side", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=2741)
+    ap.add_argument("--no-mlp", action="store_true", help="skip the learned H predictor comparison")
+    ap.add_argument("--mlp-steps", type=int, default=5)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 512 MiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -219,6 +280,8 @@ def main():
         "kernels": other,
         "roofline": roof,
     }
+    if not args.no_mlp:
+        out["h_predictor"] = mlp_eval(S, sim, t, dt, args.mlp_steps)
     sim.close()
     del t
     torch.cuda.empty_cache()

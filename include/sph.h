@@ -128,6 +128,8 @@ typedef struct {
     int32_t pad;
     int32_t unconv_after[8];    /* particles left unconverged after sweep k+1 of the last
                                    density call (-1: sweep not run) */
+    double t_predict_ms;        /* features + network inference of the last sph_step
+                                   (-1: the predictor stage did not run) */
 } sph_stats;
 
 typedef struct sph_ctx sph_ctx;

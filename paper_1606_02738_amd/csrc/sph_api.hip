@@ -107,6 +107,8 @@ sph_status sph_destroy(sph_ctx* c)
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
     for (int k = 0; k < 4; k++)
         if (c->kev[k]) (void)hipEventDestroy(c->kev[k]);
+    for (int k = 0; k < 2; k++)
+        if (c->pev[k]) (void)hipEventDestroy(c->pev[k]);
     if (c->graph_exec) (void)hipGraphExecDestroy((hipGraphExec_t)c->graph_exec);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
@@ -209,6 +211,7 @@ sph_status sph_get_stats(sph_ctx* c, sph_stats* out)
     c->st.t_ghost_ms = c->ghost_done ? elapsed(c->ev[2], c->ev[3]) : -1.0;
     c->st.t_force_ms = c->force_done ? elapsed(c->ev[4], c->ev[5]) : -1.0;
     c->st.t_build_ms = c->sorted ? elapsed(c->ev[6], c->ev[7]) : -1.0;
+    c->st.t_predict_ms = c->pev_done ? elapsed(c->pev[0], c->pev[1]) : -1.0;
     *out = c->st;
     return SPH_OK;
 }

@@ -82,6 +82,8 @@ struct sph_ctx {
     uint64_t rec_seed = 0;
     int adam_t = 0;
     int64_t step_count = 0;
+    hipEvent_t pev[2] = {};             // timing of the predictor stage of the last step
+    bool pev_done = false;
 
     int elem_size() const { return prm.precision == SPH_FP64 ? 8 : 4; }
 };

@@ -119,13 +119,15 @@ __global__ __launch_bounds__(256) void k_mlp_pack(const float* __restrict__ p, M
     }
 }
 
-// split x = hi + lo, both bfloat16, for the four values of an operand
+// split x = hi + lo, both bfloat16 (hardware conversion, nearest even), for
+// the four values of an operand
 __device__ inline void split4(const float v[4], bf16x4& hi, bf16x4& lo)
 {
     for (int j = 0; j < 4; j++) {
-        const uint16_t h = bf16_bits(v[j]);
-        hi[j] = (short)h;
-        lo[j] = (short)bf16_bits(v[j] - bf16_float(h));
+        const __bf16 h = (__bf16)v[j];
+        const __bf16 l = (__bf16)(v[j] - (float)h);
+        hi[j] = __builtin_bit_cast(short, h);
+        lo[j] = __builtin_bit_cast(short, l);
     }
 }
 
@@ -448,13 +450,27 @@ __global__ __launch_bounds__(256) void k_feat_hist(int64_t n, const double* __re
                                                    const double* __restrict__ z, const int32_t* __restrict__ dom,
                                                    const FeatGrid* __restrict__ fg, int* cnt)
 {
+    // particles arrive in the Morton order of the last cell build, so runs of
+    // lanes share a cell: one atomic per run
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const FeatGrid& F = fg[dom ? dom[i] : 0];
-    int c[3];
-    double f[3];
-    feat_cell(F, x[i], y[i], z[i], c, f);
-    atomicAdd(&cnt[F.off + ((int64_t)c[0] * F.G[1] + c[1]) * F.G[2] + c[2]], 1);
+    const int lane = threadIdx.x & 63;
+    long long cell = -1 - lane;  // distinct for inactive lanes
+    if (i < n) {
+        const FeatGrid& F = fg[dom ? dom[i] : 0];
+        int c[3];
+        double f[3];
+        feat_cell(F, x[i], y[i], z[i], c, f);
+        cell = F.off + ((long long)c[0] * F.G[1] + c[1]) * F.G[2] + c[2];
+    }
+    const long long prev = __shfl_up(cell, 1);
+    const bool head = lane == 0 || prev != cell;
+    const uint64_t heads = __ballot(head);
+    if (i < n && head) {
+        // run length: distance to the next head (or the wave end)
+        const uint64_t above = lane == 63 ? 0ull : heads >> (lane + 1);
+        const int len = above ? __ffsll((long long)above) : 64 - lane;
+        atomicAdd(&cnt[cell], len);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_features(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
@@ -703,17 +719,27 @@ sph_status mlp_features(sph_ctx* c, double dt, float* X, double* hprev)
 sph_status mlp_pre_build(sph_ctx* c, double dt)
 {
     c->mlp_pending = false;
+    c->pev_done = false;
     const bool use = c->h_pred && c->mlp_ready;
     if (!use && !c->rec_on) return SPH_OK;
+    if (!c->pev[0]) {
+        SPH_CHECK_HIP(hipEventCreate(&c->pev[0]));
+        SPH_CHECK_HIP(hipEventCreate(&c->pev[1]));
+    }
+    SPH_CHECK_HIP(hipEventRecord(c->pev[0], c->stream));
     SPH_TRY(buf_ensure(c->mlp_X, (size_t)c->n * XS * sizeof(float)));
-    SPH_TRY(buf_ensure(c->mlp_hprev, (size_t)c->n * sizeof(double)));
-    SPH_TRY(mlp_features(c, dt, (float*)c->mlp_X.p, (double*)c->mlp_hprev.p));
+    if (c->rec_on) SPH_TRY(buf_ensure(c->mlp_hprev, (size_t)c->n * sizeof(double)));
+    SPH_TRY(mlp_features(c, dt, (float*)c->mlp_X.p, c->rec_on ? (double*)c->mlp_hprev.p : nullptr));
     if (use) {
         k_mlp_infer<<<infer_grid(c->n), 256, 0, c->stream>>>((const MlpPacked*)c->mlp_packed.p,
                                                              (const float*)c->mlp_X.p, c->n, nullptr, c->P.H, 0.25f);
         SPH_CHECK_LAUNCH();
     }
-    c->mlp_pending = true;
+    SPH_CHECK_HIP(hipEventRecord(c->pev[1], c->stream));
+    c->pev_done = true;
+    // features and previous H follow the particles through the rebuild only
+    // when they are recorded after the density stage
+    c->mlp_pending = c->rec_on;
     return SPH_OK;
 }
 

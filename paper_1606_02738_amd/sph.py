@@ -61,7 +61,7 @@ class Stats(C.Structure):
                 ("t_density_kernels_ms", C.c_double), ("t_force_kernel_ms", C.c_double),
                 ("n_dens_evals", C.c_int64), ("n_density_launches", C.c_int32),
                 ("graph_captures", C.c_int32), ("graph_fallbacks", C.c_int32), ("pad", C.c_int32),
-                ("unconv_after", C.c_int32 * 8)]
+                ("unconv_after", C.c_int32 * 8), ("t_predict_ms", C.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
