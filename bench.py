@@ -38,10 +38,10 @@ FLOPS_FORCE = {"fp32c": 64, "fp32": 52, "fp64": 52}
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, cfg):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when there is none or the interaction-kernel sources
-    have changed since the counters were taken."""
+    summary, or None when there is none, it was taken with another launch
+    configuration, or the interaction-kernel sources have changed since."""
     import hashlib
     f = os.path.join(ROOT, "profiles", "%s_%s_hbm.md" % (kernel, workload))
     if not os.path.exists(f):
@@ -55,6 +55,10 @@ def measured_traffic(kernel, workload):
     for src in ("paper_1606_02738_amd/csrc/sph_interact.hip", "paper_1606_02738_amd/csrc/sph_internal.h"):
         h.update(open(os.path.join(ROOT, src), "rb").read())
     if kv.get("sources_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in kv:
+        return None
+    want = "n_split=%d exec=%s persistent_wgs=%d prune=%s" % (cfg["n_split"], cfg["exec_mode"],
+                                                            cfg["persistent_wgs"], cfg["prune"])
+    if kv.get("config") != want:
         return None
     return float(kv["traffic_bytes_per_launch"])
 
@@ -151,6 +155,9 @@ def main():
     ap.add_argument("--n-split", type=int, default=64)
     ap.add_argument("--prune", default="box", choices=["box", "sorted"])
     ap.add_argument("--graph", action="store_true", help="density, ghost and force from one captured hipGraph")
+    ap.add_argument("--persistent-wgs", type=int, default=0)
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="run the configuration given by the flags instead of the autotuner's choice")
     ap.add_argument("--cpu-n-side", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=2741)
@@ -185,8 +192,10 @@ def main():
                       n_halos=max(1, int(round(500 * (args.n_side / 256) ** 3))))
     log("generated in %.1f s" % (time.perf_counter() - t0))
     n = d["x"].size
-    sim = S.SPH(d["box"], precision=args.precision, exec_mode=args.exec_mode, n_split=args.n_split,
-                prune=args.prune, use_graph=args.graph)
+    box = d["box"]
+    cfg = dict(n_split=args.n_split, exec_mode=args.exec_mode, persistent_wgs=args.persistent_wgs,
+               prune=args.prune, use_graph=args.graph)
+    sim = S.SPH(box, precision=args.precision, **cfg)
     t = S.to_device(d)
     del d
     sim.bind(t)
@@ -203,6 +212,16 @@ def main():
     h_span = float(q[1] / q[0])
     cs = math.sqrt(5.0 / 3.0 * (2.0 / 3.0) * float(t["u"].max()))
     dt = 0.25 * float(H.min()) / math.sqrt(10.0 / 3.0) / cs
+    tune_table = None
+    if args.tune:
+        from paper_1606_02738_amd import autotune as AT
+        sim.close()
+        t0 = time.perf_counter()
+        cfg, tune_table = AT.autotune(box, t, args.precision, dt, cache=None, log=log)
+        log("autotune: %s (%.1f s)" % (cfg, time.perf_counter() - t0))
+        sim = S.SPH(box, precision=args.precision, **cfg)
+        sim.bind(t)
+        sim.run()
 
     for k in range(args.warmup):
         sim.step(dt)
@@ -216,38 +235,46 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     log("timed %d steps in %.3f s" % (args.steps, wall))
+    kper = per
+    if cfg["use_graph"]:
+        # kernels inside the graph are not timed one by one: time the same
+        # kernels, launched the same way without the graph, after the timed region
+        ksim = S.SPH(box, precision=args.precision, **dict(cfg, use_graph=False))
+        ksim.bind(t)
+        ksim.run()
+        kper = []
+        for _ in range(min(args.steps, 3)):
+            ksim.step(dt)
+            kper.append(ksim.stats())
+        ksim.close()
+        sim.bind(t)
+        sim.run()
 
     inter = sum(s["n_dens"] + 2 * s["n_force"] for s in per)
     t_dgf = sum(s["t_density_ms"] + s["t_ghost_ms"] + s["t_force_ms"] for s in per) / 1e3
-    dens_ms = sum(s["t_density_kernels_ms"] for s in per)
-    dens_launch = sum(s["n_density_launches"] for s in per)
-    dens_evals = sum(s["n_dens_evals"] for s in per)
-    force_ms = sum(s["t_force_kernel_ms"] for s in per)
     force_pairs = sum(s["n_force"] for s in per)
+    # per-kernel durations and the work of those launches
+    dens_ms = sum(s["t_density_kernels_ms"] for s in kper)
+    dens_launch = sum(s["n_density_launches"] for s in kper)
+    force_ms = sum(s["t_force_kernel_ms"] for s in kper)
     prec = args.precision
-    dens_flops = dens_evals * FLOPS_DENS[prec]
-    force_flops = force_pairs * FLOPS_FORCE[prec]
-    if dens_ms < 0 or force_ms < 0:
-        # graph mode: the kernels inside the graph are not timed one by one;
-        # the graph's wall time bounds both from above
-        kname, kflops, kms, klaunch = ("graph(k_density,k_ghost,k_force)", dens_flops + force_flops,
-                                       t_dgf * 1e3, args.steps)
-    elif dens_ms >= force_ms:
+    dens_flops = sum(s["n_dens_evals"] for s in kper) * FLOPS_DENS[prec]
+    force_flops = sum(s["n_force"] for s in kper) * FLOPS_FORCE[prec]
+    if dens_ms >= force_ms:
         kname, kflops, kms, klaunch = "k_density", dens_flops, dens_ms, dens_launch
     else:
-        kname, kflops, kms, klaunch = "k_force", force_flops, force_ms, args.steps
+        kname, kflops, kms, klaunch = "k_force", force_flops, force_ms, len(kper)
     achieved = kflops / (kms / 1e3) / 1e12
-    traffic = None
-    if kname in ("k_force", "k_density") and not args.graph and args.exec_mode == "grid" and args.prune == "box":
-        traffic = measured_traffic(kname, "clustered%d_%s" % (args.n_side, prec))
+    traffic = measured_traffic(kname, "clustered%d_%s" % (args.n_side, prec), cfg)
     roof = {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS, "traffic": traffic,
             "launches": klaunch, "avg_launch_ms": kms / max(1, klaunch),
             "flop_per_launch": kflops / max(1, klaunch)}
     other = {"k_density": {"ms_total": dens_ms, "launches": dens_launch,
                            "tflops": dens_flops / max(dens_ms, 1e-9) / 1e9},
-             "k_force": {"ms_total": force_ms, "launches": args.steps,
-                         "tflops": force_flops / max(force_ms, 1e-9) / 1e9}}
+             "k_force": {"ms_total": force_ms, "launches": len(kper),
+                         "tflops": force_flops / max(force_ms, 1e-9) / 1e9},
+             "timed_without_graph": bool(cfg["use_graph"])}
 
     out = {
         "metric": "SPH neighbour interactions/s (density+force) + step time, 256^3 clustered, vs oracle",
@@ -264,9 +291,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "clustered %d^3 periodic unit box: lognormal sigma_ln=1.5 + NFW halos, "
                                "h span %.0fx (0.1-99.9%%)" % (args.n_side, h_span),
-                   "n_particles": n, "precision": prec, "exec": args.exec_mode, "n_split": args.n_split,
-                   "prune": args.prune, "graph": bool(args.graph),
-                   "dt": dt},
+                   "n_particles": n, "precision": prec, "exec": cfg["exec_mode"], "n_split": cfg["n_split"],
+                   "persistent_wgs": cfg["persistent_wgs"], "prune": cfg["prune"], "graph": bool(cfg["use_graph"]),
+                   "autotuned": bool(args.tune), "dt": dt},
         "interactions_per_step": inter / args.steps,
         "n_dens_per_step": sum(s["n_dens"] for s in per) / args.steps,
         "n_force_per_step": force_pairs / args.steps,
@@ -280,6 +307,8 @@ def main():
         "kernels": other,
         "roofline": roof,
     }
+    if tune_table is not None:
+        out["autotune"] = [dict(c, ms_per_step=ms) for c, ms in tune_table]
     if not args.no_mlp:
         out["h_predictor"] = mlp_eval(S, sim, t, dt, args.mlp_steps)
     sim.close()

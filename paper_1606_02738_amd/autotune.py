@@ -1,0 +1,122 @@
+"""Launch-configuration autotuner of the SPH step.
+
+Times whole kick-drift-kick steps through the C-ABI for a set of candidate
+configurations on the caller's particle set and returns the fastest.  The
+tunables are the leaf size (n_split: the tile of particles one wave holds),
+the execution form (one wave per leaf over a plain grid, or persistent
+workgroups draining a cost-ordered leaf queue, with the number of resident
+workgroups), the pair-pruning mode and hipGraph capture of the density,
+ghost and force stages.  Every candidate starts from the same saved state,
+so each is timed on identical work; the particle tensors are restored
+afterwards.
+
+Results are cached in a JSON file keyed by a description of the workload
+(particle count, box count, precision, smoothing-length span, device name).
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+from . import sph as S
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "sph_hip_autotune.json")
+
+
+def _key(t, n_domains, precision):
+    import torch
+    H = t["H"]
+    n = H.numel()
+    Hs = H[:: max(1, n // 1_000_000)].float()
+    q = torch.quantile(Hs, torch.tensor([0.001, 0.999], device=Hs.device)).cpu().numpy()
+    span = float(q[1] / q[0])
+    dev = torch.cuda.get_device_name(H.device)
+    return "n=%d|boxes=%d|%s|hspan=%d|%s" % (n, n_domains, precision, int(round(math.log2(max(span, 1.0)))), dev)
+
+
+def candidates(full=False):
+    """Candidate configurations.  The default set is a coordinate sweep
+    around the plain configuration; full=True is the whole product."""
+    base = dict(n_split=64, exec_mode="grid", persistent_wgs=0, prune="box", use_graph=False)
+    if full:
+        out = []
+        for ns in (32, 48, 64):
+            for ex, wgs in (("grid", 0), ("persistent", 1024), ("persistent", 2048), ("persistent", 4096)):
+                for pr in ("box", "sorted"):
+                    for g in (False, True):
+                        out.append(dict(n_split=ns, exec_mode=ex, persistent_wgs=wgs, prune=pr, use_graph=g))
+        return out
+    out = [dict(base)]
+    for ns in (32, 40, 48, 56):
+        out.append(dict(base, n_split=ns))
+    for wgs in (1024, 2048, 4096):
+        out.append(dict(base, exec_mode="persistent", persistent_wgs=wgs))
+    out.append(dict(base, prune="sorted"))
+    out.append(dict(base, use_graph=True))
+    return out
+
+
+def _time_config(boxes, t, state, cfg, precision, dt, steps, warmup):
+    import torch
+    for k in t:
+        t[k].copy_(state[k])
+    sim = S.SPH(boxes, precision=precision, **cfg)
+    try:
+        sim.bind(t)
+        sim.run()
+        for _ in range(warmup):
+            sim.step(dt)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            sim.step(dt)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ts.sort()
+        return ts[len(ts) // 2] * 1e3
+    finally:
+        sim.close()
+
+
+def autotune(boxes, t, precision, dt, steps=3, warmup=1, cands=None, cache=DEFAULT_CACHE, log=None, refresh=False):
+    """Return (best configuration dict, table of (configuration, ms/step)).
+    t: the particle tensors (restored on return); dt: the step to time."""
+    import numpy as np
+    import torch
+    n_domains = int(np.asarray(boxes).reshape(-1, 3).shape[0])
+    key = _key(t, n_domains, precision)
+    db = {}
+    if cache and os.path.exists(cache):
+        try:
+            db = json.load(open(cache))
+        except (OSError, ValueError):
+            db = {}
+    if not refresh and key in db:
+        return db[key]["best"], db[key]["table"]
+    state = {k: v.clone() for k, v in t.items()}
+    table = []
+    try:
+        for cfg in (cands or candidates()):
+            ms = _time_config(boxes, t, state, cfg, precision, dt, steps, warmup)
+            table.append((cfg, ms))
+            if log:
+                log("autotune %s: %.2f ms/step" % (cfg, ms))
+    finally:
+        for k in t:
+            t[k].copy_(state[k])
+        del state
+        torch.cuda.empty_cache()
+    best = min(table, key=lambda r: r[1])[0]
+    if cache:
+        db[key] = {"best": best, "table": table}
+        try:
+            os.makedirs(os.path.dirname(cache), exist_ok=True)
+            with open(cache + ".tmp", "w") as f:
+                json.dump(db, f, indent=1)
+            os.replace(cache + ".tmp", cache)
+        except OSError:
+            pass
+    return best, table
