@@ -156,6 +156,8 @@ def main():
     ap.add_argument("--prune", default="box", choices=["box", "sorted"])
     ap.add_argument("--graph", action="store_true", help="density, ghost and force from one captured hipGraph")
     ap.add_argument("--persistent-wgs", type=int, default=0)
+    ap.add_argument("--rebuild-steps", type=int, default=0,
+                    help="keep cells and lists across steps with a skin for this many steps (0: rebuild every step)")
     ap.add_argument("--no-tune", dest="tune", action="store_false",
                     help="run the configuration given by the flags instead of the autotuner's choice")
     ap.add_argument("--cpu-n-side", type=int, default=128)
@@ -194,7 +196,7 @@ def main():
     n = d["x"].size
     box = d["box"]
     cfg = dict(n_split=args.n_split, exec_mode=args.exec_mode, persistent_wgs=args.persistent_wgs,
-               prune=args.prune, use_graph=args.graph)
+               prune=args.prune, use_graph=args.graph, rebuild_steps=args.rebuild_steps)
     sim = S.SPH(box, precision=args.precision, **cfg)
     t = S.to_device(d)
     del d
@@ -228,13 +230,15 @@ def main():
         log("warmup step %d done" % k)
     torch.cuda.synchronize()
     per = []
+    builds0 = sim.stats()["n_builds"]
     t0 = time.perf_counter()
     for k in range(args.steps):
         sim.step(dt)
         per.append(sim.stats())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    log("timed %d steps in %.3f s" % (args.steps, wall))
+    builds = per[-1]["n_builds"] - builds0
+    log("timed %d steps in %.3f s (%d cell builds)" % (args.steps, wall, builds))
     kper = per
     if cfg["use_graph"]:
         # kernels inside the graph are not timed one by one: time the same
@@ -293,7 +297,10 @@ def main():
                                "h span %.0fx (0.1-99.9%%)" % (args.n_side, h_span),
                    "n_particles": n, "precision": prec, "exec": cfg["exec_mode"], "n_split": cfg["n_split"],
                    "persistent_wgs": cfg["persistent_wgs"], "prune": cfg["prune"], "graph": bool(cfg["use_graph"]),
+                   "rebuild_steps": cfg["rebuild_steps"],
                    "autotuned": bool(args.tune), "dt": dt},
+        "builds": builds,
+        "build_ms_per_step": sum(s["t_build_ms"] for s in per) / args.steps,
         "interactions_per_step": inter / args.steps,
         "n_dens_per_step": sum(s["n_dens"] for s in per) / args.steps,
         "n_force_per_step": force_pairs / args.steps,

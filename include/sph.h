@@ -76,6 +76,12 @@ typedef struct {
                             particles within range of the bounding box of the cell's
                             particles) or SPH_PRUNE_SORTED (window of the sort stage's
                             per-direction order) */
+    int rebuild_steps;   /* 0: sph_step rebuilds cells and lists every step.  K > 0:
+                            lists get an extra skin of K times the step's largest
+                            displacement and sph_step keeps cells and lists while
+                            every leaf's largest H plus twice the largest
+                            displacement since the build stays inside its list
+                            radius (rebuilding when not) */
     const double* boxes; /* HOST pointer, n_domains x 3 box edge lengths; copied */
 } sph_params;
 
@@ -130,6 +136,9 @@ typedef struct {
                                    density call (-1: sweep not run) */
     double t_predict_ms;        /* features + network inference of the last sph_step
                                    (-1: the predictor stage did not run) */
+    int64_t steps_since_build;  /* sph_step calls since cells and lists were built */
+    int64_t n_builds;           /* cell and list builds since sph_create */
+    double list_margin;         /* twice the largest displacement since the build */
 } sph_stats;
 
 typedef struct sph_ctx sph_ctx;

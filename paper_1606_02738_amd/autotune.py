@@ -5,10 +5,12 @@ configurations on the caller's particle set and returns the fastest.  The
 tunables are the leaf size (n_split: the tile of particles one wave holds),
 the execution form (one wave per leaf over a plain grid, or persistent
 workgroups draining a cost-ordered leaf queue, with the number of resident
-workgroups), the pair-pruning mode and hipGraph capture of the density,
-ghost and force stages.  Every candidate starts from the same saved state,
-so each is timed on identical work; the particle tensors are restored
-afterwards.
+workgroups), the pair-pruning mode, hipGraph capture of the density, ghost
+and force stages, and how many steps the cells and lists are kept (the list
+skin).  Every candidate starts from the same saved state, so each is timed
+on identical work; the particle tensors are restored afterwards.  Steps are
+averaged (not the median) so that the occasional rebuild of a candidate
+that keeps its lists is paid for.
 
 Results are cached in a JSON file keyed by a description of the workload
 (particle count, box count, precision, smoothing-length span, device name).
@@ -39,14 +41,16 @@ def _key(t, n_domains, precision):
 def candidates(full=False):
     """Candidate configurations.  The default set is a coordinate sweep
     around the plain configuration; full=True is the whole product."""
-    base = dict(n_split=64, exec_mode="grid", persistent_wgs=0, prune="box", use_graph=False)
+    base = dict(n_split=64, exec_mode="grid", persistent_wgs=0, prune="box", use_graph=False, rebuild_steps=0)
     if full:
         out = []
         for ns in (32, 48, 64):
             for ex, wgs in (("grid", 0), ("persistent", 1024), ("persistent", 2048), ("persistent", 4096)):
                 for pr in ("box", "sorted"):
                     for g in (False, True):
-                        out.append(dict(n_split=ns, exec_mode=ex, persistent_wgs=wgs, prune=pr, use_graph=g))
+                        for rs in (0, 8):
+                            out.append(dict(n_split=ns, exec_mode=ex, persistent_wgs=wgs, prune=pr, use_graph=g,
+                                            rebuild_steps=rs))
         return out
     out = [dict(base)]
     for ns in (32, 40, 48, 56):
@@ -55,6 +59,9 @@ def candidates(full=False):
         out.append(dict(base, exec_mode="persistent", persistent_wgs=wgs))
     out.append(dict(base, prune="sorted"))
     out.append(dict(base, use_graph=True))
+    for rs in (4, 8, 16):
+        out.append(dict(base, rebuild_steps=rs))
+        out.append(dict(base, rebuild_steps=rs, use_graph=True))
     return out
 
 
@@ -69,19 +76,16 @@ def _time_config(boxes, t, state, cfg, precision, dt, steps, warmup):
         for _ in range(warmup):
             sim.step(dt)
         torch.cuda.synchronize()
-        ts = []
+        t0 = time.perf_counter()
         for _ in range(steps):
-            t0 = time.perf_counter()
             sim.step(dt)
-            torch.cuda.synchronize()
-            ts.append(time.perf_counter() - t0)
-        ts.sort()
-        return ts[len(ts) // 2] * 1e3
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps * 1e3
     finally:
         sim.close()
 
 
-def autotune(boxes, t, precision, dt, steps=3, warmup=1, cands=None, cache=DEFAULT_CACHE, log=None, refresh=False):
+def autotune(boxes, t, precision, dt, steps=8, warmup=1, cands=None, cache=DEFAULT_CACHE, log=None, refresh=False):
     """Return (best configuration dict, table of (configuration, ms/step)).
     t: the particle tensors (restored on return); dt: the step to time."""
     import numpy as np

@@ -64,6 +64,7 @@ sph_status sph_create(const sph_params* params, void* hip_stream, sph_ctx** out)
     if (p.exec_mode < SPH_EXEC_GRID || p.exec_mode > SPH_EXEC_PERSISTENT) return SPH_ERR_INVALID;
     if (p.prune < SPH_PRUNE_BOX || p.prune > SPH_PRUNE_SORTED) return SPH_ERR_INVALID;
     if (p.use_graph < 0 || p.use_graph > 1) return SPH_ERR_INVALID;
+    if (p.rebuild_steps < 0 || p.rebuild_steps > 1000) return SPH_ERR_INVALID;
     for (int k = 0; k < 3 * p.n_domains; k++)
         if (!(p.boxes[k] > 0.0) || !isfinite(p.boxes[k])) return SPH_ERR_INVALID;
     sph_ctx* c = new (std::nothrow) sph_ctx();
@@ -75,6 +76,8 @@ sph_status sph_create(const sph_params* params, void* hip_stream, sph_ctx** out)
     sph_status s = SPH_OK;
     if (s == SPH_OK) s = buf_ensure(c->flags, FI_NFLAGS * sizeof(int));
     if (s == SPH_OK) s = buf_ensure(c->counters, CNT_N * 8);
+    if (s == SPH_OK) s = buf_ensure(c->dparam, 8 * sizeof(double));
+    if (s == SPH_OK && hipMemsetAsync(c->dparam.p, 0, 8 * sizeof(double), c->stream) != hipSuccess) s = SPH_ERR_HIP;
     if (s == SPH_OK) s = buf_ensure(c->dom_d, (size_t)p.n_domains * sizeof(DomainInfo));
     if (s == SPH_OK) s = buf_ensure(c->dstat, (size_t)p.n_domains * 16);
     for (int k = 0; k < 8 && s == SPH_OK; k++)
@@ -101,7 +104,7 @@ sph_status sph_destroy(sph_ctx* c)
                      &c->l_origin, &c->l_lo, &c->l_hi, &c->l_hlist, &c->l_dom, &c->l_off, &c->l_active, &c->l_sorted,
                      &c->l_cnt, &c->l_cost, &c->l_order, &c->list, &c->pos4, &c->fv4, &c->hf, &c->skey, &c->sidx,
                      &c->hlo, &c->hhi, &c->conv, &c->vpx, &c->vpy, &c->vpz, &c->upr, &c->flags, &c->counters,
-                     &c->scan_tmp, &c->rs_hist, &c->sums, &c->dsum_part, &c->fgrid, &c->fcount, &c->mlp_X, &c->mlp_hprev, &c->mlp_params, &c->mlp_packed, &c->mlp_m, &c->mlp_v, &c->ds_X, &c->ds_y, &c->ds_count};
+                     &c->scan_tmp, &c->rs_hist, &c->sums, &c->dsum_part, &c->fgrid, &c->fcount, &c->mlp_X, &c->mlp_hprev, &c->mlp_params, &c->mlp_packed, &c->mlp_m, &c->mlp_v, &c->ds_X, &c->ds_y, &c->ds_count, &c->dparam};
     for (DevBuf* b : all) buf_free(*b);
     for (int k = 0; k < 8; k++)
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
@@ -212,6 +215,9 @@ sph_status sph_get_stats(sph_ctx* c, sph_stats* out)
     c->st.t_force_ms = c->force_done ? elapsed(c->ev[4], c->ev[5]) : -1.0;
     c->st.t_build_ms = c->sorted ? elapsed(c->ev[6], c->ev[7]) : -1.0;
     c->st.t_predict_ms = c->pev_done ? elapsed(c->pev[0], c->pev[1]) : -1.0;
+    c->st.steps_since_build = c->steps_since_build;
+    c->st.n_builds = c->n_builds;
+    c->st.list_margin = c->margin_h;
     *out = c->st;
     return SPH_OK;
 }

@@ -335,7 +335,8 @@ __global__ __launch_bounds__(256) void k_mark_leaves(const Node* __restrict__ no
 
 __global__ __launch_bounds__(256) void k_leaf_fill(Node* nodes, int n_nodes, const int* __restrict__ leafscan,
                                                    int* leaf_node, int* l_begin, int* l_count, double* l_origin,
-                                                   double* l_lo, double* l_hi, double* l_hlist, int* l_dom, int* l_top)
+                                                   double* l_lo, double* l_hi, double* l_hlist, int* l_dom, int* l_top,
+                                                   double skin_abs)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_nodes) return;
@@ -354,7 +355,7 @@ __global__ __launch_bounds__(256) void k_leaf_fill(Node* nodes, int n_nodes, con
         l_hi[3 * id + a] = nd.hi[a];
         l_origin[3 * id + a] = 0.5 * (nd.lo[a] + nd.hi[a]);
     }
-    l_hlist[id] = nd.hmax * (1.0 + SPH_LIST_SKIN);
+    l_hlist[id] = nd.hmax * (1.0 + SPH_LIST_SKIN) + skin_abs;
     l_dom[id] = nd.domain;
     l_top[id] = nd.top;
 }
@@ -381,6 +382,50 @@ __global__ __launch_bounds__(256) void k_leaf_pos(int n_leaves, const int* __res
         pos4[p] = v;
         hf[p] = (T)H[p];
     }
+}
+
+// Refresh of the cell-relative coordinates after a drift without a rebuild:
+// the nearest periodic image of each particle relative to its leaf's
+// origin, and the test that the leaf's largest H plus the displacement
+// margin still lies inside the radius its list was built for.
+template <typename T>
+__global__ __launch_bounds__(256) void k_leaf_refresh(int n_leaves, const int* __restrict__ l_begin,
+                                                      const int* __restrict__ l_count, const double* __restrict__ l_origin,
+                                                      const double* __restrict__ l_hlist, const int* __restrict__ l_dom,
+                                                      const DomainInfo* __restrict__ di, const double* __restrict__ x,
+                                                      const double* __restrict__ y, const double* __restrict__ z,
+                                                      const double* __restrict__ m, const double* __restrict__ H,
+                                                      const double* __restrict__ margin, typename vec4<T>::type* pos4,
+                                                      T* hf, int* flags)
+{
+    const int A = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6));
+    if (A >= n_leaves) return;
+    const int lane = threadIdx.x & 63;
+    const int b = l_begin[A], c = l_count[A];
+    const double o[3] = {l_origin[3 * A], l_origin[3 * A + 1], l_origin[3 * A + 2]};
+    const DomainInfo& I = di[l_dom[A]];
+    double hm = 0.0;
+    for (int p = b + lane; p < b + c; p += 64) {
+        const double q[3] = {x[p], y[p], z[p]};
+        T r[3];
+        for (int a = 0; a < 3; a++) {
+            double d = q[a] - o[a];
+            if (d > 0.5 * I.L[a]) d -= I.L[a];
+            else if (d < -0.5 * I.L[a]) d += I.L[a];
+            r[a] = (T)d;
+        }
+        typename vec4<T>::type v;
+        v.x = r[0];
+        v.y = r[1];
+        v.z = r[2];
+        v.w = (T)m[p];
+        pos4[p] = v;
+        const double h = H[p];
+        hf[p] = (T)h;
+        hm = fmax(hm, h);
+    }
+    for (int off = 32; off > 0; off >>= 1) hm = fmax(hm, __shfl_xor(hm, off));
+    if (lane == 0 && !(hm + *margin < l_hlist[A])) atomicOr(flags, FLAG_STALE);
 }
 
 // ---------------------------------------------------------------------------
@@ -562,7 +607,7 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
 // Largest H per cell, bottom-up over one level (leaves from particles,
 // internal cells from children).  One wave per cell.
 __global__ __launch_bounds__(256) void k_node_hmax(Node* nodes, int level_start, int n_level, const double* __restrict__ H,
-                                                   double* l_hlist)
+                                                   double* l_hlist, double skin_abs)
 {
     const int k = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (k >= n_level) return;
@@ -577,7 +622,7 @@ __global__ __launch_bounds__(256) void k_node_hmax(Node* nodes, int level_start,
     for (int off = 32; off > 0; off >>= 1) hm = fmax(hm, __shfl_xor(hm, off));
     if (lane == 0) {
         nd.hmax = hm;
-        if (nd.leaf >= 0) l_hlist[nd.leaf] = hm * (1.0 + SPH_LIST_SKIN);
+        if (nd.leaf >= 0) l_hlist[nd.leaf] = hm * (1.0 + SPH_LIST_SKIN) + skin_abs;
     }
 }
 
@@ -761,7 +806,8 @@ sph_status relist(sph_ctx* c)
     for (int l = (int)c->level_off.size() - 2; l >= 0; l--) {
         const int s = c->level_off[l], nl = c->level_off[l + 1] - s;
         if (nl <= 0) continue;
-        k_node_hmax<<<blocks_for(nl, 4), 256, 0, c->stream>>>(nodes, s, nl, c->P.H, (double*)c->l_hlist.p);
+        k_node_hmax<<<blocks_for(nl, 4), 256, 0, c->stream>>>(nodes, s, nl, c->P.H, (double*)c->l_hlist.p,
+                                                               c->skin_abs);
         SPH_CHECK_LAUNCH();
     }
     const int nL = c->n_leaves;
@@ -797,6 +843,13 @@ sph_status build_all(sph_ctx* c)
     const int64_t n = c->n;
     const int nd = c->prm.n_domains;
     int* flags = (int*)c->flags.p;
+
+    // a fresh build: no displacement since the lists were made
+    c->delta = 0.0;
+    c->margin_h = 0.0;
+    c->steps_since_build = 0;
+    c->n_builds++;
+    SPH_CHECK_HIP(hipMemcpyAsync(c->dparam.p, &c->margin_h, sizeof(double), hipMemcpyHostToDevice, c->stream));
 
     // 1. validate, per-box H range
     SPH_CHECK_HIP(hipMemsetAsync(flags, 0, FI_NFLAGS * sizeof(int), c->stream));
@@ -955,7 +1008,7 @@ sph_status build_all(sph_ctx* c)
     k_leaf_fill<<<blocks_for(n_nodes, 256), 256, 0, c->stream>>>(
         (Node*)c->nodes.p, n_nodes, (const int*)c->leafscan.p, (int*)c->leaf_node.p, (int*)c->l_begin.p,
         (int*)c->l_count.p, (double*)c->l_origin.p, (double*)c->l_lo.p, (double*)c->l_hi.p, (double*)c->l_hlist.p,
-        (int*)c->l_dom.p, (int*)c->l_cnt.p);
+        (int*)c->l_dom.p, (int*)c->l_cnt.p, c->skin_abs);
     SPH_CHECK_LAUNCH();
 
     // 6. cell-relative coordinates
@@ -1015,5 +1068,31 @@ sph_status sort_all(sph_ctx* c)
                                                                     (int*)c->l_sorted.p);
     SPH_CHECK_LAUNCH();
     c->sorted = true;
+    return SPH_OK;
+}
+
+// Keep the cells and lists of the last build for a step: refresh the
+// cell-relative coordinates and check every leaf against the displacement
+// margin.  *fresh = false when a rebuild is needed.
+sph_status refresh_leaves(sph_ctx* c, bool* fresh)
+{
+    int* flags = (int*)c->flags.p;
+    SPH_CHECK_HIP(hipMemsetAsync(flags, 0, sizeof(int), c->stream));
+    SPH_CHECK_HIP(hipMemcpyAsync(c->dparam.p, &c->margin_h, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    const int nL = c->n_leaves;
+    if (c->prm.precision == SPH_FP64)
+        k_leaf_refresh<double><<<blocks_for(nL, 4), 256, 0, c->stream>>>(
+            nL, (const int*)c->l_begin.p, (const int*)c->l_count.p, (const double*)c->l_origin.p,
+            (const double*)c->l_hlist.p, (const int*)c->l_dom.p, (const DomainInfo*)c->dom_d.p, c->P.x, c->P.y, c->P.z,
+            c->P.m, c->P.H, (const double*)c->dparam.p, (double4*)c->pos4.p, (double*)c->hf.p, flags);
+    else
+        k_leaf_refresh<float><<<blocks_for(nL, 4), 256, 0, c->stream>>>(
+            nL, (const int*)c->l_begin.p, (const int*)c->l_count.p, (const double*)c->l_origin.p,
+            (const double*)c->l_hlist.p, (const int*)c->l_dom.p, (const DomainInfo*)c->dom_d.p, c->P.x, c->P.y, c->P.z,
+            c->P.m, c->P.H, (const double*)c->dparam.p, (float4*)c->pos4.p, (float*)c->hf.p, flags);
+    SPH_CHECK_LAUNCH();
+    int fl = 0;
+    SPH_TRY(read_int(c, flags, &fl));
+    *fresh = !(fl & FLAG_STALE);
     return SPH_OK;
 }

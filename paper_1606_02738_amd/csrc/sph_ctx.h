@@ -69,6 +69,13 @@ struct sph_ctx {
     hipStream_t cap_stream = nullptr;  // private stream used only for capture
     hipEvent_t kev[4] = {};     // per-launch kernel timing
 
+    // lazy rebuild: displacement since the build and the list skin
+    DevBuf dparam;                      // double[8]: [0] list margin (2 x displacement), [1] max speed (bits)
+    double delta = 0.0;                 // largest displacement bound since the build
+    double skin_abs = 0.0;              // absolute list skin of the last build
+    double margin_h = 0.0;              // host copy of dparam[0] (source of its uploads)
+    int64_t steps_since_build = 0, n_builds = 0;
+
     // learned H predictor
     std::vector<FeatGrid> fgrid_h;
     int64_t fgrid_n = -1, fgrid_cells = 0;
@@ -116,6 +123,7 @@ sph_status radix_sort(sph_ctx* c, int n, int bits, DevBuf* kb, DevBuf* vb, int* 
 sph_status build_all(sph_ctx* c);
 sph_status sort_all(sph_ctx* c);
 sph_status relist(sph_ctx* c);
+sph_status refresh_leaves(sph_ctx* c, bool* fresh);
 sph_status domain_ranges(sph_ctx* c);
 
 // interaction stages (sph_interact.hip)

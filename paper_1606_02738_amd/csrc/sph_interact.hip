@@ -224,6 +224,7 @@ struct DensArgs {
     int* flags;
     unsigned long long* counters;
     const int* order;   // task order (persistent mode), may be NULL
+    const double* margin;  // list margin: twice the largest displacement since the lists were built
     const int* gate;    // graph mode: skip the sweep unless *gate == 0 (NULL: always run)
     const int* nl_dev;  // graph mode: leaf count read from the device (NULL: n_leaves)
     int persistent;
@@ -282,6 +283,10 @@ __device__ void density_leaf(const DensArgs& a, int A, DTile<T>& L, int lane)
     const double hlim = fmin(fmin(I.L[0], I.L[1]), I.L[2]) / 3.0;
     const double s0min = fmin(fmin(I.s0[0], I.s0[1]), I.s0[2]);
     const int e0 = a.l_off[A], e1 = a.l_off[A + 1];
+    // particles moved up to mg/2 since the lists were built: list radii shrink
+    // by mg and list entries are taken up to mg farther out
+    const double mg = *a.margin;
+    const double hlA = a.l_hlist[A] - mg;
     bool any_left = false;
     for (int c0 = 0; c0 < nA; c0 += 64) {
         const int nc = min(64, nA - c0);
@@ -309,7 +314,7 @@ __device__ void density_leaf(const DensArgs& a, int A, DTile<T>& L, int lane)
         for (int eb = e0; eb < e1; eb += 64) {
             const int nbt = min(64, e1 - eb);
             const int nv = load_batch<T>(a.list, eb, nbt, lane, a.l_begin, a.l_count, a.l_origin, oA, I,
-                                         [&](const ListEntry& E) { return E.dist < hA; }, L.e, nullptr, A);
+                                         [&](const ListEntry& E) { return E.dist < hA + mg; }, L.e, nullptr, A);
             V4 pf;  // prefetched first cell of the next pair
             if (PRUNE == PRUNE_BOX && nv > 0) {
                 const int n0 = L.e.n[0];
@@ -465,7 +470,7 @@ __device__ void density_leaf(const DensArgs& a, int A, DTile<T>& L, int lane)
                     const double dH = Hn - H;
                     if (fabs(dH) <= 4.0 * 2.220446049250313e-16 * H) {
                         done = true;  // stalled at round-off: accept H
-                    } else if (EXTRAP && newton && fabs(dH) <= 1e-3 * H && Hn <= a.l_hlist[A] && Hn <= s0min &&
+                    } else if (EXTRAP && newton && fabs(dH) <= 1e-3 * H && Hn <= hlA && Hn <= s0min &&
                                fabs(0.5 * F2 * dH * dH) <= 0.5 * a.h_tol * C) {
                         // accept the Newton update: rho H^3 and its H-derivative at Hn
                         // from their second-order expansion around H
@@ -480,7 +485,7 @@ __device__ void density_leaf(const DensArgs& a, int A, DTile<T>& L, int lane)
                         a.H[i] = Hn;
                         a.hlo[i] = lo;
                         a.hhi[i] = hi;
-                        if (Hn > a.l_hlist[A]) atomicOr(a.flags, FLAG_RELIST);
+                        if (Hn > hlA) atomicOr(a.flags, FLAG_RELIST);
                         if (Hn > s0min) atomicOr(a.flags, FLAG_REBUILD);
                         left = true;
                     }
@@ -598,6 +603,7 @@ struct ForceArgs {
     int32_t* nngb;      // #{j : r_ij < H_i} incl. self at the final H (may be NULL)
     unsigned long long* counters;
     const int* order;
+    const double* margin;  // list margin: twice the largest displacement since the lists were built
     const int* gate;    // graph mode: run only if *gate == 1 (NULL: always run)
     const int* nl_dev;  // graph mode: leaf count read from the device (NULL: n_leaves)
     int persistent;
@@ -719,6 +725,7 @@ __device__ void force_leaf(const ForceArgs& a, int A, FTile<T>& tl, int lane)
     const double oA[3] = {a.l_origin[3 * A], a.l_origin[3 * A + 1], a.l_origin[3 * A + 2]};
     const DomainInfo& I = a.di[a.l_dom[A]];
     const int e0 = a.l_off[A], e1 = a.l_off[A + 1];
+    const double mg = *a.margin;  // list margin (see density_leaf)
     unsigned long long npairs = 0, ndens_w = 0;
     for (int c0 = 0; c0 < nA; c0 += 64) {
         const int nc = min(64, nA - c0);
@@ -805,7 +812,7 @@ __device__ void force_leaf(const ForceArgs& a, int A, FTile<T>& tl, int lane)
                                              const int B = E.B;
                                              if (B == A) return false;
                                              if (B < A && E.dist < hl[B]) return false;  // owned by B
-                                             return E.dist < fmax(hA, hl[B]);
+                                             return E.dist < fmax(hA + mg, hl[B]);
                                          },
                                          tl.e, hl, A);
             V4 pf, ff;
@@ -1019,24 +1026,38 @@ __global__ __launch_bounds__(256) void k_kick_drift(int64_t n, double* x, double
                                                     double* vz, double* u, const double* __restrict__ ax,
                                                     const double* __restrict__ ay, const double* __restrict__ az,
                                                     const double* __restrict__ dudt, const int32_t* __restrict__ dom,
-                                                    const DomainInfo* __restrict__ di, double dt)
+                                                    const DomainInfo* __restrict__ di, double dt,
+                                                    unsigned long long* vmax_bits)
 {
+    __shared__ double wmax[4];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double h = 0.5 * dt;
-    const double v[3] = {vx[i] + ax[i] * h, vy[i] + ay[i] * h, vz[i] + az[i] * h};
-    vx[i] = v[0];
-    vy[i] = v[1];
-    vz[i] = v[2];
-    u[i] += dudt[i] * h;
-    const DomainInfo& I = di[dom ? dom[i] : 0];
-    double* c[3] = {x, y, z};
-    for (int a = 0; a < 3; a++) {
-        double q = c[a][i] + v[a] * dt;
-        q -= I.L[a] * floor(q / I.L[a]);
-        if (q >= I.L[a]) q -= I.L[a];
-        if (q < 0.0) q = 0.0;
-        c[a][i] = q;
+    double sp = 0.0;
+    if (i < n) {
+        const double h = 0.5 * dt;
+        const double v[3] = {vx[i] + ax[i] * h, vy[i] + ay[i] * h, vz[i] + az[i] * h};
+        vx[i] = v[0];
+        vy[i] = v[1];
+        vz[i] = v[2];
+        u[i] += dudt[i] * h;
+        sp = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        const DomainInfo& I = di[dom ? dom[i] : 0];
+        double* c[3] = {x, y, z};
+        for (int a = 0; a < 3; a++) {
+            double q = c[a][i] + v[a] * dt;
+            q -= I.L[a] * floor(q / I.L[a]);
+            if (q >= I.L[a]) q -= I.L[a];
+            if (q < 0.0) q = 0.0;
+            c[a][i] = q;
+        }
+    }
+    // largest speed of the drift (non-negative doubles order like their bits)
+    for (int off = 32; off > 0; off >>= 1) sp = fmax(sp, __shfl_xor(sp, off));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = sp;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = wmax[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); w++) b = fmax(b, wmax[w]);
+        atomicMax(vmax_bits, (unsigned long long)__double_as_longlong(b));
     }
 }
 
@@ -1156,6 +1177,7 @@ static void dens_args(sph_ctx* c, const int* gate, bool graph, DensArgs& a, int&
     a.persistent = c->prm.exec_mode == SPH_EXEC_PERSISTENT;
     a.order = a.persistent ? (const int*)c->l_order.p : nullptr;
     a.gate = gate;
+    a.margin = (const double*)c->dparam.p;
     a.nl_dev = graph ? (const int*)c->flags.p + FI_NLEAVES : nullptr;
     if (graph) a.n_leaves = 0;  // read on the device
     const int nl = graph ? leaf_capacity(c) : c->n_leaves;
@@ -1232,9 +1254,11 @@ static sph_status density_loop(sph_ctx* c, int done_sweeps, unsigned long long u
         if (sweeps <= 8) c->st.unconv_after[sweeps - 1] = (int)std::min<unsigned long long>(unconv, INT32_MAX);
         if (fl & FLAG_BOX_SMALL) status = SPH_ERR_BOX_TOO_SMALL;
         if (unconv == 0) break;
-        if (fl & FLAG_REBUILD) {
-            // a smoothing length outgrew the top grid: rebuild the cells and
-            // continue from the current H (brackets restart)
+        if ((fl & FLAG_REBUILD) || ((fl & FLAG_RELIST) && c->delta > 0.0)) {
+            // a smoothing length outgrew the top grid, or outgrew its list
+            // after particles moved since the build (the walk needs current
+            // boxes): rebuild the cells and continue from the current H
+            // (brackets restart)
             SPH_TRY(build_all(c));
             SPH_TRY(sort_all(c));
             k_density_reset<<<blocks_for(std::max<int64_t>(c->n, c->n_leaves), 256), 256, 0, c->stream>>>(
@@ -1329,6 +1353,7 @@ static void force_args(sph_ctx* c, const int* gate, bool graph, ForceArgs& a, in
     a.persistent = c->prm.exec_mode == SPH_EXEC_PERSISTENT;
     a.order = a.persistent ? (const int*)c->l_order.p : nullptr;
     a.gate = gate;
+    a.margin = (const double*)c->dparam.p;
     a.nl_dev = graph ? (const int*)c->flags.p + FI_NLEAVES : nullptr;
     if (graph) a.n_leaves = 0;  // read on the device
     const int nl = graph ? leaf_capacity(c) : c->n_leaves;
@@ -1596,7 +1621,7 @@ sph_status dgf_graph(sph_ctx* c)
     // the host takes over from the state the graph left
     c->st.graph_fallbacks++;
     if (fl & FLAG_BOX_SMALL) return SPH_ERR_BOX_TOO_SMALL;
-    if (fl & FLAG_REBUILD) {
+    if ((fl & FLAG_REBUILD) || ((fl & FLAG_RELIST) && c->delta > 0.0)) {
         SPH_TRY(build_all(c));
         SPH_TRY(sort_all(c));
         k_density_reset<<<blocks_for(std::max<int64_t>(c->n, c->n_leaves), 256), 256, 0, c->stream>>>(
@@ -1638,14 +1663,35 @@ sph_status step_all(sph_ctx* c, double dt)
 {
     if (!c->force_done) return SPH_ERR_STATE;
     const int nb = blocks_for(c->n, 256);
+    unsigned long long* vmax_bits = (unsigned long long*)c->dparam.p + 1;
+    SPH_CHECK_HIP(hipMemsetAsync(vmax_bits, 0, 8, c->stream));
     k_kick_drift<<<nb, 256, 0, c->stream>>>(c->n, c->P.x, c->P.y, c->P.z, c->P.vx, c->P.vy, c->P.vz, c->P.u, c->P.ax,
                                             c->P.ay, c->P.az, c->P.dudt, c->P.domain, (const DomainInfo*)c->dom_d.p,
-                                            dt);
+                                            dt, vmax_bits);
     SPH_CHECK_LAUNCH();
     c->step_count++;
     SPH_TRY(mlp_pre_build(c, dt));
-    SPH_TRY(build_all(c));
+    double vmax = 0.0;
+    SPH_CHECK_HIP(hipMemcpyAsync(&vmax, vmax_bits, 8, hipMemcpyDeviceToHost, c->stream));
+    SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
+    SPH_CHECK_HIP(hipEventRecord(c->ev[6], c->stream));
+    bool fresh = false;
+    if (c->prm.rebuild_steps > 0 && c->built) {
+        // keep the cells and lists while the displacement margin allows
+        c->delta += vmax * dt;
+        c->margin_h = 2.0 * c->delta;
+        SPH_TRY(refresh_leaves(c, &fresh));
+    }
+    if (fresh) {
+        c->steps_since_build++;
+    } else {
+        // list skin for the coming steps: rebuild_steps times this step's
+        // largest displacement
+        c->skin_abs = c->prm.rebuild_steps > 0 ? c->prm.rebuild_steps * vmax * dt : 0.0;
+        SPH_TRY(build_all(c));
+    }
     SPH_TRY(sort_all(c));
+    SPH_CHECK_HIP(hipEventRecord(c->ev[7], c->stream));
     const size_t nb8 = (size_t)c->n * 8;
     SPH_TRY(buf_ensure(c->vpx, nb8));
     SPH_TRY(buf_ensure(c->vpy, nb8));

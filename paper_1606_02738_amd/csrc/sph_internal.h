@@ -93,6 +93,7 @@ enum {
     FLAG_RELIST = 2,       // some H grew beyond the radius the lists were built for
     FLAG_REBUILD = 4,      // some H grew beyond the top-cell edge
     FLAG_BOX_SMALL = 8,    // some H reached the box limit with f < 0
+    FLAG_STALE = 16,       // a leaf's H plus the displacement margin left its list radius
 };
 
 // Slots of the int[64] flags buffer.

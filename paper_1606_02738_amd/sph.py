@@ -42,6 +42,7 @@ class Params(C.Structure):
                 ("h_tol", C.c_double), ("max_h_iter", C.c_int), ("n_split", C.c_int),
                 ("precision", C.c_int), ("exec_mode", C.c_int), ("n_domains", C.c_int),
                 ("persistent_wgs", C.c_int), ("use_graph", C.c_int), ("prune", C.c_int),
+                ("rebuild_steps", C.c_int),
                 ("boxes", C.POINTER(C.c_double))]
 
 
@@ -61,7 +62,8 @@ class Stats(C.Structure):
                 ("t_density_kernels_ms", C.c_double), ("t_force_kernel_ms", C.c_double),
                 ("n_dens_evals", C.c_int64), ("n_density_launches", C.c_int32),
                 ("graph_captures", C.c_int32), ("graph_fallbacks", C.c_int32), ("pad", C.c_int32),
-                ("unconv_after", C.c_int32 * 8), ("t_predict_ms", C.c_double)]
+                ("unconv_after", C.c_int32 * 8), ("t_predict_ms", C.c_double),
+                ("steps_since_build", C.c_int64), ("n_builds", C.c_int64), ("list_margin", C.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -190,7 +192,7 @@ class SPH:
 
     def __init__(self, boxes, precision="fp32c", exec_mode="grid", gamma=5.0 / 3.0, eta=1.2348,
                  kernel_gamma=math.sqrt(10.0 / 3.0), h_tol=None, max_h_iter=40, n_split=64,
-                 persistent_wgs=0, prune="box", use_graph=False, stream=None):
+                 persistent_wgs=0, prune="box", use_graph=False, rebuild_steps=0, stream=None):
         import torch
         self._torch = torch
         b = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(-1, 3))
@@ -205,6 +207,7 @@ class SPH:
         p.exec_mode = EXEC_MODES[exec_mode] if isinstance(exec_mode, str) else int(exec_mode)
         p.n_domains, p.persistent_wgs, p.use_graph = self.n_domains, persistent_wgs, int(bool(use_graph))
         p.prune = PRUNE_MODES[prune] if isinstance(prune, str) else int(prune)
+        p.rebuild_steps = int(rebuild_steps)
         p.boxes = b.ctypes.data_as(C.POINTER(C.c_double))
         self.params = p
         s = stream if stream is not None else torch.cuda.current_stream()

@@ -66,3 +66,44 @@ def test_repeatable_fp32c():
         assert np.array_equal(o["H"], outs[0]["H"])
         sa = np.max(np.abs(outs[0]["ax"]))
         assert np.max(np.abs(o["ax"] - outs[0]["ax"])) < 1e-12 * sa
+
+
+@pytest.mark.parametrize("prec,rsteps", [("fp64", 8), ("fp64", 1), ("fp32c", 8)])
+def test_lazy_rebuild_matches_rebuild_every_step(prec, rsteps):
+    """Cells and lists kept across steps (rebuild only when a leaf's H plus
+    twice the largest displacement leaves its list radius) give the same
+    trajectory as a rebuild every step.  With a skin of one step's
+    displacement the margin check forces rebuilds."""
+    from paper_1606_02738_amd import sph as S
+    log("case lazy rebuild clustered 32^3 %s rebuild_steps=%d" % (prec, rsteps))
+    d = gen.clustered(32, n_halos=20, seed=2741)
+    res = {}
+    for rs in (0, rsteps):
+        sim = S.SPH(d["box"], precision=prec, rebuild_steps=rs)
+        t = S.to_device(d)
+        sim.bind(t)
+        sim.run()
+        dt = 0.25 * float(t["H"].min()) / 1.83 / 1.05
+        builds0 = sim.stats()["n_builds"]
+        lazy = 0
+        for _ in range(6):
+            sim.step(dt)
+            lazy += sim.stats()["steps_since_build"] > 0
+        torch.cuda.synchronize()
+        st = sim.stats()
+        res[rs] = (S.to_host(t), st, st["n_builds"] - builds0, lazy)
+        sim.close()
+    a, b = res[0][0], res[rsteps][0]
+    log("builds over 6 steps: every step %d, lazy %d (steps without a build %d)" % (
+        res[0][2], res[rsteps][2], res[rsteps][3]))
+    assert res[0][2] == 6
+    if rsteps == 8:
+        assert res[rsteps][3] >= 3
+    tol = 1e-10 if prec == "fp64" else 2e-5
+    for k in ("x", "y", "z"):
+        assert np.max(np.abs(a[k] - b[k])) < tol * 0.1, k
+    for k in ("vx", "vy", "vz", "u", "H", "rho"):
+        scale = np.max(np.abs(a[k])) + 1e-30
+        assert np.max(np.abs(a[k] - b[k])) / scale < tol * 10, k
+    if prec == "fp64":
+        assert np.array_equal(a["nngb"], b["nngb"])
