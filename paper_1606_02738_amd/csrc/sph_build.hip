@@ -336,7 +336,7 @@ __global__ __launch_bounds__(256) void k_mark_leaves(const Node* __restrict__ no
 __global__ __launch_bounds__(256) void k_leaf_fill(Node* nodes, int n_nodes, const int* __restrict__ leafscan,
                                                    int* leaf_node, int* l_begin, int* l_count, double* l_origin,
                                                    double* l_lo, double* l_hi, double* l_hlist, int* l_dom, int* l_top,
-                                                   double skin_abs)
+                                                   double skin_abs, int* max_leaf)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_nodes) return;
@@ -345,6 +345,7 @@ __global__ __launch_bounds__(256) void k_leaf_fill(Node* nodes, int n_nodes, con
         nd.leaf = -1;
         return;
     }
+    if (nd.count > 64) atomicMax(max_leaf, nd.count);
     const int id = leafscan[nd.begin];
     nd.leaf = id;
     leaf_node[id] = k;
@@ -1008,8 +1009,9 @@ sph_status build_all(sph_ctx* c)
     k_leaf_fill<<<blocks_for(n_nodes, 256), 256, 0, c->stream>>>(
         (Node*)c->nodes.p, n_nodes, (const int*)c->leafscan.p, (int*)c->leaf_node.p, (int*)c->l_begin.p,
         (int*)c->l_count.p, (double*)c->l_origin.p, (double*)c->l_lo.p, (double*)c->l_hi.p, (double*)c->l_hlist.p,
-        (int*)c->l_dom.p, (int*)c->l_cnt.p, c->skin_abs);
+        (int*)c->l_dom.p, (int*)c->l_cnt.p, c->skin_abs, flags + FI_MAXLEAF);
     SPH_CHECK_LAUNCH();
+    SPH_TRY(read_int(c, flags + FI_MAXLEAF, &c->max_leaf));
 
     // 6. cell-relative coordinates
     const int es = c->elem_size();

@@ -30,6 +30,7 @@ struct sph_ctx {
 
     // octree / leaves / lists
     int n_nodes = 0, n_leaves = 0, depth = 0;
+    int max_leaf = 0;            // particles in the fullest leaf
     int64_t n_list = 0, n_pair_tasks = 0;
     std::vector<int> level_off;  // node index of the first node of each level
 

@@ -228,6 +228,7 @@ struct DensArgs {
     const int* gate;    // graph mode: skip the sweep unless *gate == 0 (NULL: always run)
     const int* nl_dev;  // graph mode: leaf count read from the device (NULL: n_leaves)
     int persistent;
+    int big_only;       // skip leaves of at most 64 particles (done by the packed kernel)
 };
 
 #define NTD 4  // neighbour cells per two-phase batch (density)
@@ -268,6 +269,231 @@ __device__ inline int load_batch(const ListEntry* list, int eb, int nbt, int lan
     }
     wave_sync();
     return __popcll(mask);
+}
+
+// Sums of one sweep -> rho, d rho/dH, neighbour count, and the FP64 Newton
+// step of rho H^3 = C inside the particle's bracket (Sec. 2).  The lanes of
+// group 0 (jg == 0) own particle i; partial sums of the other groups are
+// folded in first.  Returns true if particle i is left unconverged.
+template <typename T>
+__device__ inline bool dens_finish(const DensArgs& a, int i, bool act, int jg, int CI, double Hd, double Sw0,
+                                   double Sd0, double S20, int cnt, double hlA, double hlim, double s0min)
+{
+    constexpr bool EXTRAP = sizeof(T) == 4;
+    const int lane = threadIdx.x & 63;
+    double Sw = Sw0, Sd = Sd0, S2 = S20;
+    for (int off = CI; off < 64; off <<= 1) {
+        Sw += __shfl_xor(Sw, off);
+        Sd += __shfl_xor(Sd, off);
+        if (EXTRAP) S2 += __shfl_xor(S2, off);
+        cnt += __shfl_xor(cnt, off);
+    }
+    {
+        // interactions evaluated by this sweep (lanes of group 0 hold the totals)
+        unsigned long long ev = (jg == 0 && act) ? (unsigned long long)cnt : 0ull;
+        for (int off = 32; off > 0; off >>= 1) ev += __shfl_xor(ev, off);
+        if (lane == 0 && ev) atomicAdd(&a.counters[CNT_DEVAL], ev);
+    }
+    bool left = false;
+    if (jg == 0 && act) {
+        const double H = Hd;
+        const double rho = INV_PI_8 / (H * H * H) * Sw;
+        const double drho = -INV_PI_8 / (H * H * H * H) * Sd;
+        const double C = a.C_fac * a.m[i];
+        const double f = INV_PI_8 * Sw - C;              // rho H^3 - C
+        const double fp = INV_PI_8 * (3.0 * Sw - Sd) / H; // 3 H^2 rho + H^3 drho/dH
+        const double F2 = INV_PI_8 * S2 / (H * H);         // d^2 (rho H^3) / dH^2
+        a.rho[i] = rho;
+        a.drho[i] = drho;
+        if (a.nngb) a.nngb[i] = cnt;
+        bool done = fabs(f) <= a.h_tol * C;
+        if (!done) {
+            double lo = a.hlo[i], hi = a.hhi[i];
+            if (f < 0.0) lo = H;
+            else hi = H;
+            if (f < 0.0 && H >= hlim) {
+                atomicOr(a.flags, FLAG_BOX_SMALL);
+                done = true;
+            } else {
+                double Hn = H - f / fp;
+                bool newton = true;
+                if (!(Hn > lo && Hn < hi) || !isfinite(Hn)) {
+                    Hn = isinf(hi) ? 2.0 * H : 0.5 * (lo + hi);
+                    newton = false;
+                }
+                // at most doubling per sweep: a far-off step would only force
+                // needless list and grid rebuilds before the bracket closes
+                if (Hn > 2.0 * H) Hn = 2.0 * H;
+                if (Hn > hlim) Hn = hlim;
+                const double dH = Hn - H;
+                if (fabs(dH) <= 4.0 * 2.220446049250313e-16 * H) {
+                    done = true;  // stalled at round-off: accept H
+                } else if (EXTRAP && newton && fabs(dH) <= 1e-3 * H && Hn <= hlA && Hn <= s0min &&
+                           fabs(0.5 * F2 * dH * dH) <= 0.5 * a.h_tol * C) {
+                    // accept the Newton update: rho H^3 and its H-derivative at Hn
+                    // from their second-order expansion around H
+                    const double F1 = INV_PI_8 * Sw + fp * dH + 0.5 * F2 * dH * dH;
+                    const double F1p = fp + F2 * dH;
+                    const double H3 = Hn * Hn * Hn;
+                    a.H[i] = Hn;
+                    a.rho[i] = F1 / H3;
+                    a.drho[i] = F1p / H3 - 3.0 * F1 / (H3 * Hn);
+                    done = true;
+                } else {
+                    a.H[i] = Hn;
+                    a.hlo[i] = lo;
+                    a.hhi[i] = hi;
+                    if (Hn > hlA) atomicOr(a.flags, FLAG_RELIST);
+                    if (Hn > s0min) atomicOr(a.flags, FLAG_REBUILD);
+                    left = true;
+                }
+            }
+        }
+        if (done) {
+            a.conv[i] = 1;
+            atomicAdd(&a.counters[CNT_NDENS], (unsigned long long)cnt);
+        }
+    }
+    return left;
+}
+
+// Candidate buffer of the packed density path (one wave): candidates j of
+// all neighbour cells in A's frame, packed 64 at a time, and A's particles.
+template <typename T>
+struct PTile {
+    typename vec4<T>::type cand[128];  // j in A's frame, w = m
+    typename vec4<T>::type si[64];     // i of A: x, y, z (A frame), H^2 (negative when inactive)
+    EBatch<T> e;
+};
+
+// Density sweep of one leaf (at most 64 particles, box pruning).  The
+// candidates of every neighbour cell that pass the box test are packed into
+// full tiles of 64; per tile, phase 1 runs j-major (lane = candidate, a
+// uniform loop over A's active particles, one ballot per particle gives
+// that particle's in-range mask) and phase 2 i-major (lane = particle,
+// evaluating only the set bits).  Phase 1 keeps every lane busy whatever
+// the leaf's occupancy.
+template <typename T, bool COMP>
+__device__ void density_leaf_packed(const DensArgs& a, int A, PTile<T>& L, int lane)
+{
+    constexpr bool EXTRAP = sizeof(T) == 4;
+    typedef typename vec4<T>::type V4;
+    const V4* pos4 = (const V4*)a.pos4;
+    const int bA = a.l_begin[A], nA = a.l_count[A];
+    const double oA[3] = {a.l_origin[3 * A], a.l_origin[3 * A + 1], a.l_origin[3 * A + 2]};
+    const DomainInfo& I = a.di[a.l_dom[A]];
+    const double hlim = fmin(fmin(I.L[0], I.L[1]), I.L[2]) / 3.0;
+    const double s0min = fmin(fmin(I.s0[0], I.s0[1]), I.s0[2]);
+    const int e0 = a.l_off[A], e1 = a.l_off[A + 1];
+    const double mg = *a.margin;  // list margin (see density_leaf)
+    const double hlA = a.l_hlist[A] - mg;
+    const bool vi = lane < nA;
+    const int i = bA + (vi ? lane : 0);
+    const bool act = vi && !a.conv[i];
+    const unsigned long long amask = __ballot(act);
+    if (amask == 0ull) {
+        if (lane == 0) a.l_active[A] = 0;
+        return;
+    }
+    const V4 pi = pos4[i];
+    const double Hd = a.H[i];
+    const T Hi = (T)Hd, H2 = Hi * Hi, invH = T(1) / Hi;
+    {
+        V4 q = pi;
+        q.w = act ? H2 : T(-1);
+        L.si[lane] = q;
+    }
+    Acc<T, COMP> sw, sd;
+    T s2 = T(0);
+    int cnt = 0;
+    const double hA = wave_max(act ? Hd : 0.0);
+    const T big = T(1e30);
+    const T bxl = wave_min_t<T>(act ? pi.x : big), bxh = wave_max_t<T>(act ? pi.x : -big);
+    const T byl = wave_min_t<T>(act ? pi.y : big), byh = wave_max_t<T>(act ? pi.y : -big);
+    const T bzl = wave_min_t<T>(act ? pi.z : big), bzh = wave_max_t<T>(act ? pi.z : -big);
+    const T hAm = (T)(hA * (1.0 + 1e-5));
+    const T hA2 = hAm * hAm;
+    auto dens_acc = [&](const V4& q4, T r2) {
+        const T q = fast_sqrt(r2) * invH;
+        T w, dw;
+        spline_w_dw(q, w, dw);
+        sw.add(q4.w * w);
+        sd.add(q4.w * (T(3) * w + q * dw));
+        if (EXTRAP) s2 += q4.w * spline_d2(q, dw);
+        cnt++;
+    };
+    // both phases on the first `len` packed candidates
+    auto run_tile = [&](int len) {
+        wave_sync();
+        const V4 pj = L.cand[lane];
+        const bool lv = lane < len;
+        int mlo = 0, mhi = 0;
+        for (unsigned long long m = amask; m; m &= m - 1ull) {
+            const int ii = __ffsll((long long)m) - 1;
+            const V4 q = L.si[ii];
+            const T dx = pj.x - q.x, dy = pj.y - q.y, dz = pj.z - q.z;
+            const unsigned long long hm = __ballot(lv && dx * dx + dy * dy + dz * dz < q.w);
+            if (lane == ii) {
+                mlo = (int)(uint32_t)hm;
+                mhi = (int)(uint32_t)(hm >> 32);
+            }
+        }
+        if (act) {
+            unsigned long long m = ((unsigned long long)(uint32_t)mhi << 32) | (uint32_t)mlo;
+            while (m) {
+                const int s = __ffsll((long long)m) - 1;
+                m &= m - 1ull;
+                const V4 q4 = L.cand[s];
+                const T dx = q4.x - pi.x, dy = q4.y - pi.y, dz = q4.z - pi.z;
+                dens_acc(q4, dx * dx + dy * dy + dz * dz);
+            }
+        }
+        wave_sync();
+    };
+    int ncand = 0;
+    for (int eb = e0; eb < e1; eb += 64) {
+        const int nbt = min(64, e1 - eb);
+        const int nv = load_batch<T>(a.list, eb, nbt, lane, a.l_begin, a.l_count, a.l_origin, oA, I,
+                                     [&](const ListEntry& E) { return E.dist < hA + mg; }, L.e, nullptr, A);
+        V4 pf;  // prefetched first chunk of the next cell
+        if (nv > 0 && lane < L.e.n[0]) pf = pos4[L.e.b[0] + lane];
+        for (int k = 0; k < nv; k++) {
+            const int bB = L.e.b[k], nB = L.e.n[k];
+            const T dox = L.e.ox[k], doy = L.e.oy[k], doz = L.e.oz[k];
+            V4 cur = pf;
+            if (k + 1 < nv && lane < L.e.n[k + 1]) pf = pos4[L.e.b[k + 1] + lane];
+            for (int p0 = 0; p0 < nB; p0 += 64) {
+                const int len = min(64, nB - p0);
+                bool in = false;
+                V4 q;
+                if (lane < len) {
+                    q = p0 == 0 ? cur : pos4[bB + p0 + lane];
+                    q.x += dox;
+                    q.y += doy;
+                    q.z += doz;
+                    in = box_d2<T>(q.x, q.y, q.z, bxl, byl, bzl, bxh, byh, bzh) < hA2;
+                }
+                const unsigned long long mk = __ballot(in);
+                if (in) L.cand[ncand + mask_rank(mk, lane)] = q;
+                ncand += __popcll(mk);
+                if (ncand >= 64) {
+                    run_tile(64);
+                    const int rest = ncand - 64;
+                    V4 t;
+                    if (lane < rest) t = L.cand[64 + lane];
+                    wave_sync();
+                    if (lane < rest) L.cand[lane] = t;
+                    ncand = rest;
+                }
+            }
+        }
+        wave_sync();
+    }
+    if (ncand > 0) run_tile(ncand);
+    const bool left = dens_finish<T>(a, i, act, 0, 64, Hd, sw.total(), sd.total(), (double)s2, cnt, hlA, hlim, s0min);
+    const unsigned long long lm = __ballot(left);
+    if (lm && lane == 0) atomicAdd(&a.counters[CNT_UNCONV], (unsigned long long)__popcll(lm));
+    if (lane == 0) a.l_active[A] = lm ? 1 : 0;
 }
 
 template <typename T, bool COMP, int PRUNE>
@@ -423,79 +649,8 @@ __device__ void density_leaf(const DensArgs& a, int A, DTile<T>& L, int lane)
             }
             wave_sync();
         }
-        double Sw = sw.total(), Sd = sd.total(), S2 = (double)s2;
-        for (int off = CI; off < 64; off <<= 1) {
-            Sw += __shfl_xor(Sw, off);
-            Sd += __shfl_xor(Sd, off);
-            if (EXTRAP) S2 += __shfl_xor(S2, off);
-            cnt += __shfl_xor(cnt, off);
-        }
-        {
-            // interactions evaluated by this sweep (lanes of group 0 hold the totals)
-            unsigned long long ev = (jg == 0 && act) ? (unsigned long long)cnt : 0ull;
-            for (int off = 32; off > 0; off >>= 1) ev += __shfl_xor(ev, off);
-            if (lane == 0 && ev) atomicAdd(&a.counters[CNT_DEVAL], ev);
-        }
-        bool left = false;
-        if (jg == 0 && act) {
-            const double H = Hd;
-            const double rho = INV_PI_8 / (H * H * H) * Sw;
-            const double drho = -INV_PI_8 / (H * H * H * H) * Sd;
-            const double C = a.C_fac * a.m[i];
-            const double f = INV_PI_8 * Sw - C;              // rho H^3 - C
-            const double fp = INV_PI_8 * (3.0 * Sw - Sd) / H; // 3 H^2 rho + H^3 drho/dH
-            const double F2 = INV_PI_8 * S2 / (H * H);         // d^2 (rho H^3) / dH^2
-            a.rho[i] = rho;
-            a.drho[i] = drho;
-            if (a.nngb) a.nngb[i] = cnt;
-            bool done = fabs(f) <= a.h_tol * C;
-            if (!done) {
-                double lo = a.hlo[i], hi = a.hhi[i];
-                if (f < 0.0) lo = H;
-                else hi = H;
-                if (f < 0.0 && H >= hlim) {
-                    atomicOr(a.flags, FLAG_BOX_SMALL);
-                    done = true;
-                } else {
-                    double Hn = H - f / fp;
-                    bool newton = true;
-                    if (!(Hn > lo && Hn < hi) || !isfinite(Hn)) {
-                        Hn = isinf(hi) ? 2.0 * H : 0.5 * (lo + hi);
-                        newton = false;
-                    }
-                    // at most doubling per sweep: a far-off step would only force
-                    // needless list and grid rebuilds before the bracket closes
-                    if (Hn > 2.0 * H) Hn = 2.0 * H;
-                    if (Hn > hlim) Hn = hlim;
-                    const double dH = Hn - H;
-                    if (fabs(dH) <= 4.0 * 2.220446049250313e-16 * H) {
-                        done = true;  // stalled at round-off: accept H
-                    } else if (EXTRAP && newton && fabs(dH) <= 1e-3 * H && Hn <= hlA && Hn <= s0min &&
-                               fabs(0.5 * F2 * dH * dH) <= 0.5 * a.h_tol * C) {
-                        // accept the Newton update: rho H^3 and its H-derivative at Hn
-                        // from their second-order expansion around H
-                        const double F1 = INV_PI_8 * Sw + fp * dH + 0.5 * F2 * dH * dH;
-                        const double F1p = fp + F2 * dH;
-                        const double H3 = Hn * Hn * Hn;
-                        a.H[i] = Hn;
-                        a.rho[i] = F1 / H3;
-                        a.drho[i] = F1p / H3 - 3.0 * F1 / (H3 * Hn);
-                        done = true;
-                    } else {
-                        a.H[i] = Hn;
-                        a.hlo[i] = lo;
-                        a.hhi[i] = hi;
-                        if (Hn > hlA) atomicOr(a.flags, FLAG_RELIST);
-                        if (Hn > s0min) atomicOr(a.flags, FLAG_REBUILD);
-                        left = true;
-                    }
-                }
-            }
-            if (done) {
-                a.conv[i] = 1;
-                atomicAdd(&a.counters[CNT_NDENS], (unsigned long long)cnt);
-            }
-        }
+        const bool left = dens_finish<T>(a, i, act, jg, CI, Hd, sw.total(), sd.total(), (double)s2, cnt, hlA, hlim,
+                                         s0min);
         const unsigned long long lm = __ballot(left);
         if (lm) {
             any_left = true;
@@ -516,6 +671,7 @@ __global__ __launch_bounds__(256) void k_density(DensArgs a)
         const int A = uniform(blockIdx.x * WAVES_PER_WG + w);
         if (A >= nL) return;
         if (!a.l_active[A]) return;
+        if (a.big_only && a.l_count[A] <= 64) return;
         density_leaf<T, COMP, PRUNE>(a, A, tiles[w], lane);
         return;
     }
@@ -527,6 +683,37 @@ __global__ __launch_bounds__(256) void k_density(DensArgs a)
         const int A = uniform(a.order ? a.order[t] : t);
         if (A < 0 || A >= nL) break;
         if (a.l_active[A]) density_leaf<T, COMP, PRUNE>(a, A, tiles[w], lane);
+    }
+}
+
+
+// Packed density sweep over the leaves of at most 64 particles (box
+// pruning); the LDS is only the packed candidate buffer, so more waves fit
+// on a CU than with the two-phase tiles.
+#ifndef SPH_DENS_WAVES
+#define SPH_DENS_WAVES 8  // measured best: spills stay outside the inner loops
+#endif
+template <typename T, bool COMP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPH_DENS_WAVES, 8))) void k_density_packed(
+    DensArgs a)
+{
+    __shared__ PTile<T> tiles[WAVES_PER_WG];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (a.gate && uniform(*a.gate) != 0) return;
+    const int nL = a.nl_dev ? uniform(*a.nl_dev) : a.n_leaves;
+    if (!a.persistent) {
+        const int A = uniform(blockIdx.x * WAVES_PER_WG + w);
+        if (A >= nL) return;
+        if (!a.l_active[A] || a.l_count[A] > 64) return;
+        density_leaf_packed<T, COMP>(a, A, tiles[w], lane);
+        return;
+    }
+    for (int it = 0; it <= nL; it++) {
+        const int t = wave_pop(&a.counters[CNT_QUEUE], lane);
+        if (t >= nL) break;
+        const int A = uniform(a.order ? a.order[t] : t);
+        if (A < 0 || A >= nL) break;
+        if (a.l_active[A] && a.l_count[A] <= 64) density_leaf_packed<T, COMP>(a, A, tiles[w], lane);
     }
 }
 
@@ -624,8 +811,16 @@ struct FSlots {
     int jn[64];                     // j-side neighbour counts (r < H_j)
 };
 
-// neighbour cells per two-phase batch (force): LDS keeps 4 waves per group
-#define NTF(T) (sizeof(T) == 4 ? 2 : 1)
+// neighbour cells per two-phase batch (force), and the occupancy target:
+// one cell per batch keeps the LDS at 6 KB per wave, and 5 waves per SIMD
+// (96 VGPRs, spills outside the pair loops) measured fastest
+#ifndef SPH_NTF_F32
+#define SPH_NTF_F32 1
+#endif
+#ifndef SPH_FORCE_WAVES
+#define SPH_FORCE_WAVES 5
+#endif
+#define NTF(T) (sizeof(T) == 4 ? SPH_NTF_F32 : 1)
 
 template <typename T>
 struct FTile {
@@ -998,7 +1193,7 @@ __device__ void force_leaf(const ForceArgs& a, int A, FTile<T>& tl, int lane)
 }
 
 template <typename T, bool COMP, int PRUNE>
-__global__ __launch_bounds__(256) void k_force(ForceArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPH_FORCE_WAVES, 8))) void k_force(ForceArgs a)
 {
     __shared__ FTile<T> tiles[WAVES_PER_WG];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1191,6 +1386,18 @@ static sph_status launch_density(sph_ctx* c, const int* gate, bool graph = false
     dens_args(c, gate, graph, a, nb);
     if (nb <= 0) return SPH_OK;
     const bool srt = c->prm.prune == SPH_PRUNE_SORTED;
+    if (!srt) {
+        if (c->prm.precision == SPH_FP64) k_density_packed<double, false><<<nb, 256, 0, c->stream>>>(a);
+        else if (c->prm.precision == SPH_FP32C) k_density_packed<float, true><<<nb, 256, 0, c->stream>>>(a);
+        else k_density_packed<float, false><<<nb, 256, 0, c->stream>>>(a);
+        SPH_CHECK_LAUNCH();
+        // leaves above 64 particles (cells that cannot be split further):
+        // the chunked two-phase kernel over a plain grid
+        if (c->max_leaf <= 64) return SPH_OK;
+        a.big_only = 1;
+        a.persistent = 0;
+        nb = blocks_for(graph ? leaf_capacity(c) : c->n_leaves, WAVES_PER_WG);
+    }
     if (c->prm.precision == SPH_FP64) {
         if (srt) k_density<double, false, PRUNE_SORTED><<<nb, 256, 0, c->stream>>>(a);
         else k_density<double, false, PRUNE_BOX><<<nb, 256, 0, c->stream>>>(a);
@@ -1513,6 +1720,7 @@ static std::vector<uint8_t> graph_key(sph_ctx* c, const double* u, const double*
     key_put(k, c->prm.precision);
     key_put(k, c->prm.prune);
     key_put(k, c->prm.exec_mode);
+    key_put(k, (int)(c->max_leaf > 64));  // whether the big-leaf density pass is launched
     return k;
 }
 

@@ -97,7 +97,7 @@ enum {
 };
 
 // Slots of the int[64] flags buffer.
-enum { FI_FLAGS = 0, FI_SCRATCH = 8, FI_NCHILD = 9, FI_NLEAVES = 10, FI_NLIST = 11, FI_GATE = 12, FI_NFLAGS = 64 };
+enum { FI_FLAGS = 0, FI_SCRATCH = 8, FI_NCHILD = 9, FI_NLEAVES = 10, FI_NLIST = 11, FI_GATE = 12, FI_MAXLEAF = 13, FI_NFLAGS = 64 };
 
 // Counters written by kernels (device, int64).
 enum { CNT_UNCONV = 0, CNT_NDENS = 1, CNT_NFORCE = 2, CNT_QUEUE = 3, CNT_QUEUE2 = 4, CNT_DEVAL = 5, CNT_NPAIR = 6, CNT_NDENS_F = 7, CNT_GSWEEPS = 8, CNT_UHIST = 9, CNT_N = 16 };
