@@ -508,7 +508,10 @@ __device__ inline float box_dist_f(const float* alo, const float* ahi, const flo
     return sqrtf(d2);
 }
 
-template <bool FILL>
+// MODE 0: count the entries of each leaf; 1: write them at the scanned
+// offsets l_off; 2: write up to list_cap entries of leaf A at A * list_cap
+// and count them all (one pass when no leaf exceeds the capacity).
+template <int MODE>
 __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restrict__ leaf_node, const WNode* __restrict__ wn,
                                               const double* __restrict__ l_lo, const double* __restrict__ l_hi,
                                               const int* __restrict__ l_dom, const int* __restrict__ l_top,
@@ -516,7 +519,7 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
                                               int* counts, const int* __restrict__ l_off, ListEntry* __restrict__ list,
                                               int list_cap, int with_dir, int* flags)
 {
-    const int A = blockIdx.x * blockDim.x + threadIdx.x;
+    const int A = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (A >= n_leaves) return;
     const DomainInfo& I = di[l_dom[A]];
     const int loc = l_top[A] - I.top_offset;
@@ -528,9 +531,10 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
     const WNode& WA = wn[leaf_node[A]];
     const double alo[3] = {l_lo[3 * A], l_lo[3 * A + 1], l_lo[3 * A + 2]};
     const double ahi[3] = {l_hi[3 * A], l_hi[3 * A + 1], l_hi[3 * A + 2]};
+    constexpr bool FILL = MODE != 0;
     int cnt = 0;
-    int out = FILL ? l_off[A] : 0;
-    const int out_end = FILL ? l_off[A + 1] : 0;
+    int out = MODE == 1 ? l_off[A] : (MODE == 2 ? A * list_cap : 0);
+    const int out_end = MODE == 1 ? l_off[A + 1] : (MODE == 2 ? A * list_cap + list_cap : 0);
     for (int sx = -1; sx <= 1; sx++)
     for (int sy = -1; sy <= 1; sy++)
     for (int sz = -1; sz <= 1; sz++) {
@@ -575,7 +579,7 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
                 }
                 if (!(d < hA)) continue;
                 if (FILL) {
-                    if (out < out_end && out < list_cap) {
+                    if (out < out_end && (MODE == 2 || out < list_cap)) {
                         int best = 0;
                         if (with_dir) {
                             // sort direction: the one of 13 most aligned with the centre offset
@@ -593,7 +597,7 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
                         e.code = code_shift | (best << 8);
                         e.dist = d;
                         list[out] = e;
-                    } else {
+                    } else if (MODE == 1) {
                         atomicOr(flags, FLAG_INVALID);
                     }
                     out++;
@@ -602,7 +606,20 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
             }
         }
     }
-    if (!FILL) counts[A] = cnt;
+    if (MODE != 1) counts[A] = cnt;
+    if (MODE == 2 && cnt > list_cap) atomicMax(flags + FI_MAXLIST, cnt);
+}
+
+// Move the entries of the one-pass walk from the per-leaf slots to the
+// scanned offsets.  One wave per leaf.
+__global__ __launch_bounds__(256) void k_list_compact(int n_leaves, int cap, const ListEntry* __restrict__ scratch,
+                                                      const int* __restrict__ l_off, ListEntry* __restrict__ list)
+{
+    const int A = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+    if (A >= n_leaves) return;
+    const int lane = threadIdx.x & 63;
+    const int o = l_off[A], n = l_off[A + 1] - o;
+    for (int e = lane; e < n; e += 64) list[o + e] = scratch[(size_t)A * cap + e];
 }
 
 // Largest H per cell, bottom-up over one level (leaves from particles,
@@ -816,23 +833,47 @@ sph_status relist(sph_ctx* c)
     int* flags = (int*)c->flags.p;
     SPH_CHECK_HIP(hipMemsetAsync(counts, 0, (size_t)(nL + 1) * sizeof(int), c->stream));
     const int with_dir = c->prm.prune == SPH_PRUNE_SORTED;
-    k_walk<false><<<blocks_for(nL, 128), 128, 0, c->stream>>>(nL, (const int*)c->leaf_node.p, (const WNode*)c->wnodes.p,
-                                                             (const double*)c->l_lo.p, (const double*)c->l_hi.p,
-                                                             (const int*)c->l_dom.p, (const int*)c->l_cnt.p,
-                                                             (const DomainInfo*)c->dom_d.p, (const double*)c->l_hlist.p,
-                                                             counts, nullptr, nullptr, 0, with_dir, flags);
+    // one pass into per-leaf slots of walk_cap entries, counting every entry
+    const int cap = c->walk_cap;
+    const bool one_pass = (size_t)nL * cap < ((size_t)1 << 31) - (size_t)cap;
+    if (one_pass) {
+        SPH_TRY(buf_ensure(c->walk_scratch, (size_t)nL * cap * sizeof(ListEntry)));
+        SPH_CHECK_HIP(hipMemsetAsync(flags + FI_MAXLIST, 0, sizeof(int), c->stream));
+        k_walk<2><<<blocks_for(nL, 128), 128, 0, c->stream>>>(
+            nL, (const int*)c->leaf_node.p, (const WNode*)c->wnodes.p, (const double*)c->l_lo.p,
+            (const double*)c->l_hi.p, (const int*)c->l_dom.p, (const int*)c->l_cnt.p, (const DomainInfo*)c->dom_d.p,
+            (const double*)c->l_hlist.p, counts, nullptr, (ListEntry*)c->walk_scratch.p, cap, with_dir, flags);
+    } else {
+        k_walk<0><<<blocks_for(nL, 128), 128, 0, c->stream>>>(
+            nL, (const int*)c->leaf_node.p, (const WNode*)c->wnodes.p, (const double*)c->l_lo.p,
+            (const double*)c->l_hi.p, (const int*)c->l_dom.p, (const int*)c->l_cnt.p, (const DomainInfo*)c->dom_d.p,
+            (const double*)c->l_hlist.p, counts, nullptr, nullptr, 0, with_dir, flags);
+    }
     SPH_CHECK_LAUNCH();
     SPH_TRY(scan_exclusive(c, counts, counts, nL + 1, flags + FI_NLIST));
-    int total = 0;
-    SPH_TRY(read_int(c, flags + FI_NLIST, &total));
+    int hf[FI_MAXLIST - FI_NLIST + 1];
+    SPH_CHECK_HIP(hipMemcpyAsync(hf, flags + FI_NLIST, sizeof(hf), hipMemcpyDeviceToHost, c->stream));
+    SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
+    const int total = hf[0], over = hf[FI_MAXLIST - FI_NLIST];
     if (total < 0) return SPH_ERR_ALLOC;
     SPH_TRY(buf_ensure(c->list, (size_t)std::max(total, 1) * sizeof(ListEntry)));
-    k_walk<true><<<blocks_for(nL, 128), 128, 0, c->stream>>>(nL, (const int*)c->leaf_node.p, (const WNode*)c->wnodes.p,
-                                                            (const double*)c->l_lo.p, (const double*)c->l_hi.p,
-                                                            (const int*)c->l_dom.p, (const int*)c->l_cnt.p,
-                                                            (const DomainInfo*)c->dom_d.p, (const double*)c->l_hlist.p,
-                                                            nullptr, (const int*)c->l_off.p, (ListEntry*)c->list.p,
-                                                            total, with_dir, flags);
+    if (one_pass && over == 0) {
+        k_list_compact<<<blocks_for(nL, 4), 256, 0, c->stream>>>(nL, cap, (const ListEntry*)c->walk_scratch.p,
+                                                                 (const int*)c->l_off.p, (ListEntry*)c->list.p);
+    } else {
+        // some leaf had more entries than its slot: second walk at the offsets,
+        // and a larger slot for the next builds
+        if (over > 0) {
+            int nc = cap;
+            while (nc < over && nc < 4096) nc *= 2;
+            c->walk_cap = nc;
+        }
+        k_walk<1><<<blocks_for(nL, 128), 128, 0, c->stream>>>(
+            nL, (const int*)c->leaf_node.p, (const WNode*)c->wnodes.p, (const double*)c->l_lo.p,
+            (const double*)c->l_hi.p, (const int*)c->l_dom.p, (const int*)c->l_cnt.p, (const DomainInfo*)c->dom_d.p,
+            (const double*)c->l_hlist.p, nullptr, (const int*)c->l_off.p, (ListEntry*)c->list.p, total, with_dir,
+            flags);
+    }
     SPH_CHECK_LAUNCH();
     c->n_list = total;
     if (c->prm.exec_mode == SPH_EXEC_PERSISTENT) return task_order(c);

@@ -54,6 +54,8 @@ struct sph_ctx {
     DevBuf leaf_node;             // leaf -> node
     DevBuf l_begin, l_count, l_origin, l_lo, l_hi, l_hlist, l_dom, l_off, l_active, l_sorted, l_cnt, l_cost, l_order;
     DevBuf list;
+    DevBuf walk_scratch;          // per-leaf slots of the one-pass list walk
+    int walk_cap = 128;           // entries per slot (grows after an overflow)
     DevBuf pos4, fv4, hf;         // kernel-side particle data (T = float or double)
     DevBuf skey, sidx;            // per-direction sorted projections
     DevBuf hlo, hhi, conv;        // Newton brackets and converged flags

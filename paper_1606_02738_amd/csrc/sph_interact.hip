@@ -668,7 +668,7 @@ __global__ __launch_bounds__(256) void k_density(DensArgs a)
     if (a.gate && uniform(*a.gate) != 0) return;
     const int nL = a.nl_dev ? uniform(*a.nl_dev) : a.n_leaves;
     if (!a.persistent) {
-        const int A = uniform(blockIdx.x * WAVES_PER_WG + w);
+        const int A = uniform(xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_WG + w);
         if (A >= nL) return;
         if (!a.l_active[A]) return;
         if (a.big_only && a.l_count[A] <= 64) return;
@@ -702,7 +702,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPH_DENS_WA
     if (a.gate && uniform(*a.gate) != 0) return;
     const int nL = a.nl_dev ? uniform(*a.nl_dev) : a.n_leaves;
     if (!a.persistent) {
-        const int A = uniform(blockIdx.x * WAVES_PER_WG + w);
+        const int A = uniform(xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_WG + w);
         if (A >= nL) return;
         if (!a.l_active[A] || a.l_count[A] > 64) return;
         density_leaf_packed<T, COMP>(a, A, tiles[w], lane);
@@ -1200,7 +1200,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPH_FORCE_W
     if (a.gate && uniform(*a.gate) != 1) return;
     const int nL = a.nl_dev ? uniform(*a.nl_dev) : a.n_leaves;
     if (!a.persistent) {
-        const int A = uniform(blockIdx.x * WAVES_PER_WG + w);
+        const int A = uniform(xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_WG + w);
         if (A >= nL) return;
         force_leaf<T, COMP, PRUNE>(a, A, tiles[w], lane);
         return;

@@ -97,7 +97,7 @@ enum {
 };
 
 // Slots of the int[64] flags buffer.
-enum { FI_FLAGS = 0, FI_SCRATCH = 8, FI_NCHILD = 9, FI_NLEAVES = 10, FI_NLIST = 11, FI_GATE = 12, FI_MAXLEAF = 13, FI_NFLAGS = 64 };
+enum { FI_FLAGS = 0, FI_SCRATCH = 8, FI_NCHILD = 9, FI_NLEAVES = 10, FI_NLIST = 11, FI_GATE = 12, FI_MAXLEAF = 13, FI_MAXLIST = 14, FI_NFLAGS = 64 };
 
 // Counters written by kernels (device, int64).
 enum { CNT_UNCONV = 0, CNT_NDENS = 1, CNT_NFORCE = 2, CNT_QUEUE = 3, CNT_QUEUE2 = 4, CNT_DEVAL = 5, CNT_NPAIR = 6, CNT_NDENS_F = 7, CNT_GSWEEPS = 8, CNT_UHIST = 9, CNT_N = 16 };
@@ -122,6 +122,16 @@ struct PhysParams {
     double C_fac;     // (kernel_gamma * eta)^3
     double h_tol;
 };
+
+// Workgroups are dealt to the 8 XCDs of the chip round-robin (workgroup b
+// runs on XCD b mod 8), and each XCD has its own L2.  The logical block
+// index below gives every XCD one contiguous range of blocks, so
+// neighbouring leaves (Morton order) share an L2.  A bijection on [0, G).
+__device__ inline int xcd_block(int b, int G)
+{
+    const int q = G >> 3, r = G & 7, x = b & 7;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + (b >> 3);
+}
 
 // Device helpers shared by the kernels.
 template <typename T> struct vec4;
