@@ -79,10 +79,19 @@ def cpu_baseline(n_side, seed):
     o = oracle.full(d, tree=True)
     dt = time.perf_counter() - t0
     inter = o["n_dens"] + 2 * o["n_force"]
+    model = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": inter / dt, "unit": "interactions/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": "clustered recipe at %d^3 = %d particles (%.3g of the workload), full density "
-                      "solve + ghost + force, %.1f s" % (n_side, n_side ** 3, (n_side / 256) ** 3, dt)}
+                      "solve + ghost + force, %.1f s; %s, %d cores in the affinity mask" % (
+                          n_side, n_side ** 3, (n_side / 256) ** 3, dt, model, len(os.sched_getaffinity(0)))}
 
 
 def mlp_eval(S, sim, t, dt, steps, rec_steps=50, seed=17):
@@ -144,11 +153,88 @@ def mlp_eval(S, sim, t, dt, steps, rec_steps=50, seed=17):
             "step_time_ratio_mlp_over_plain": res["mlp"]["ms_per_step"] / res["plain"]["ms_per_step"]}
 
 
+def ensemble_eval(S, prec, steps=3, seed=2743):
+    """64 independent periodic boxes (n_side ~ U{16..96}): every stage of a
+    step as one launch over all boxes, against 64 contexts stepped one after
+    the other (the plain solves).  Same dt for both; per-box FP64 totals."""
+    import numpy as np
+    import torch
+    import gen
+    t0 = time.perf_counter()
+    d = gen.ensemble(64, seed=seed)
+    log("ensemble: %d particles in 64 boxes (%.1f s)" % (d["x"].size, time.perf_counter() - t0))
+    boxes = d["boxes"]
+    out = {"n_particles": int(d["x"].size), "boxes": 64,
+           "box_sizes": [int(v) for v in np.bincount(d["domain"], minlength=64)]}
+    # sequential plain solves: one context per box
+    parts = []
+    for b in range(64):
+        idx = np.nonzero(d["domain"] == b)[0]
+        sub = {k: np.ascontiguousarray(d[k][idx]) for k in ("x", "y", "z", "vx", "vy", "vz", "u", "m", "H", "id")}
+        parts.append((boxes[b], sub))
+    t_all = S.to_device(d)
+    union = {}
+    dt = None
+    for mode in ("persistent", "grid"):
+        tt = {k: v.clone() for k, v in t_all.items()}
+        sim = S.SPH(boxes, precision=prec, exec_mode=mode)
+        sim.bind(tt)
+        sim.run()
+        if dt is None:
+            cs = math.sqrt(5.0 / 3.0 * (2.0 / 3.0) * float(tt["u"].max()))
+            dt = 0.25 * float(tt["H"].min()) / math.sqrt(10.0 / 3.0) / cs
+        sim.step(dt)
+        torch.cuda.synchronize()
+        sums0 = sim.domain_sums()
+        per = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sim.step(dt)
+            per.append(sim.stats())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        sums1 = sim.domain_sums()
+        inter = sum(q["n_dens"] + 2 * q["n_force"] for q in per)
+        union[mode] = {"ms_per_step": wall / steps * 1e3, "interactions_per_s": inter / wall,
+                       "max_rel_mass_change": float(np.max(np.abs(sums1[:, 0] - sums0[:, 0]) / sums0[:, 0])),
+                       "max_rel_energy_change": float(np.max(np.abs(sums1[:, 4] - sums0[:, 4]) / sums0[:, 4]))}
+        sim.close()
+        del tt
+        log("ensemble union (%s): %.2f ms/step" % (mode, union[mode]["ms_per_step"]))
+    del t_all
+    sims = []
+    for box, sub in parts:
+        tb = S.to_device(sub)
+        sb = S.SPH(box, precision=prec)
+        sb.bind(tb)
+        sb.run()
+        sb.step(dt)
+        sims.append((sb, tb))
+    torch.cuda.synchronize()
+    inter = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for sb, tb in sims:
+            sb.step(dt)
+            q = sb.stats()
+            inter += q["n_dens"] + 2 * q["n_force"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for sb, tb in sims:
+        sb.close()
+    seq = {"ms_per_step": wall / steps * 1e3, "interactions_per_s": inter / wall}
+    log("ensemble sequential: %.2f ms/step" % seq["ms_per_step"])
+    best = min(union.values(), key=lambda r: r["ms_per_step"])
+    out.update({"precision": prec, "dt": dt, "steps": steps, "union": union, "sequential": seq,
+                "speedup_union_over_sequential": seq["ms_per_step"] / best["ms_per_step"]})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n-side", type=int, default=256)
     ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp32", "fp64"])
     ap.add_argument("--exec", dest="exec_mode", default="grid", choices=["grid", "persistent"])
@@ -164,6 +250,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=2741)
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned H predictor comparison")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-box ensemble comparison")
     ap.add_argument("--mlp-steps", type=int, default=5)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 512 MiB device copy first (calibrates HBM byte counters)")
@@ -231,12 +318,15 @@ def main():
     torch.cuda.synchronize()
     per = []
     builds0 = sim.stats()["n_builds"]
+    tstep = []
     t0 = time.perf_counter()
     for k in range(args.steps):
         sim.step(dt)
-        per.append(sim.stats())
+        per.append(sim.stats())  # synchronises the stream
+        tstep.append(time.perf_counter())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    dts = np.diff([t0] + tstep) * 1e3
     builds = per[-1]["n_builds"] - builds0
     log("timed %d steps in %.3f s (%d cell builds)" % (args.steps, wall, builds))
     kper = per
@@ -288,6 +378,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": wall / args.steps * 1e3,
+        "ms_per_step_median": float(np.median(dts)),
+        "ms_per_step_mean_without_first_last": float(np.mean(dts[1:-1])) if len(dts) > 2 else float(np.mean(dts)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -321,6 +413,9 @@ def main():
     sim.close()
     del t
     torch.cuda.empty_cache()
+    if not args.no_ensemble:
+        out["ensemble"] = ensemble_eval(S, args.precision)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n_side, args.seed)

@@ -28,14 +28,13 @@
 template <typename T>
 __device__ inline void spline_w_dw(T q, T& w, T& dw)
 {
+    // both pieces and a select: lanes of a wave fall on both sides of q = 1/2
     const T t = T(1) - q;
-    if (q <= T(0.5)) {
-        w = T(1) + q * q * (T(6) * q - T(6));
-        dw = q * (T(18) * q - T(12));
-    } else {
-        w = T(2) * t * t * t;
-        dw = T(-6) * t * t;
-    }
+    const bool in = q <= T(0.5);
+    const T wi = T(1) + q * q * (T(6) * q - T(6)), dwi = q * (T(18) * q - T(12));
+    const T wo = T(2) * t * t * t, dwo = T(-6) * t * t;
+    w = in ? wi : wo;
+    dw = in ? dwi : dwo;
 }
 
 // q^2 w''(q) + 2 q w'(q), the q-part of the second H-derivative of H^3 W
@@ -111,6 +110,9 @@ __device__ inline int wave_pop(unsigned long long* counter, int lane)
 
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// v_writelane_b32: replace lane `lane` of `old` by the wave-uniform `src`
+__device__ int amdgcn_writelane(int src, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
 __device__ inline void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -181,14 +183,14 @@ __device__ inline int mask_rank(unsigned long long mask, int lane)
 }
 
 // Neighbour-entry batch of one wave, in LDS.
-template <typename T>
+template <typename T, int NE = 64>
 struct EBatch {
-    int b[64];     // first particle of B
-    int n[64];     // particles of B
-    int B[64];     // leaf index of B
-    int dir[64];   // sort direction of the pair
-    T ox[64], oy[64], oz[64];  // origin(B) + periodic shift - origin(A)
-    T R[64];       // interaction range of the pair (force)
+    int b[NE];     // first particle of B
+    int n[NE];     // particles of B
+    int B[NE];     // leaf index of B
+    int dir[NE];   // sort direction of the pair
+    T ox[NE], oy[NE], oz[NE];  // origin(B) + periodic shift - origin(A)
+    T R[NE];       // interaction range of the pair (force)
 };
 
 // ---------------------------------------------------------------------------
@@ -241,9 +243,9 @@ struct DTile {
 
 // Load the entries [eb, eb + nbt) of A's list, keep those that pass
 // keep(E), compact them into the batch; returns their number.
-template <typename T, typename Keep>
+template <typename T, typename Keep, int NE = 64>
 __device__ inline int load_batch(const ListEntry* list, int eb, int nbt, int lane, const int* l_begin, const int* l_count,
-                                 const double* l_origin, const double* oA, const DomainInfo& I, Keep keep, EBatch<T>& E,
+                                 const double* l_origin, const double* oA, const DomainInfo& I, Keep keep, EBatch<T, NE>& E,
                                  const double* l_hlist, int A)
 {
     bool ok = false;
@@ -429,14 +431,12 @@ __device__ void density_leaf_packed(const DensArgs& a, int A, PTile<T>& L, int l
         const bool lv = lane < len;
         int mlo = 0, mhi = 0;
         for (unsigned long long m = amask; m; m &= m - 1ull) {
-            const int ii = __ffsll((long long)m) - 1;
+            const int ii = uniform(__ffsll((long long)m) - 1);
             const V4 q = L.si[ii];
             const T dx = pj.x - q.x, dy = pj.y - q.y, dz = pj.z - q.z;
             const unsigned long long hm = __ballot(lv && dx * dx + dy * dy + dz * dz < q.w);
-            if (lane == ii) {
-                mlo = (int)(uint32_t)hm;
-                mhi = (int)(uint32_t)(hm >> 32);
-            }
+            mlo = amdgcn_writelane((int)(uint32_t)hm, ii, mlo);
+            mhi = amdgcn_writelane((int)(uint32_t)(hm >> 32), ii, mhi);
         }
         if (act) {
             unsigned long long m = ((unsigned long long)(uint32_t)mhi << 32) | (uint32_t)mlo;

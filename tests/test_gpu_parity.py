@@ -166,3 +166,25 @@ def test_unsplittable_cell(prec, prune):
         assert_close(g, o, TOL_FP64, stats=st)
     else:
         assert_close(g, o, TOL_FP32, counts_exact=False)
+
+
+@pytest.mark.parametrize("prec,mode", [("fp64", "persistent"), ("fp32c", "grid")])
+def test_ensemble_boxes_equal_standalone_runs(prec, mode):
+    """Each box of a multi-box run equals the same box run alone (the boxes
+    are independent; only the summation order may differ)."""
+    import torch
+    from paper_1606_02738_amd import sph as S
+    log("case ensemble vs standalone %s %s" % (prec, mode))
+    d = gen.ensemble(6, side_range=(10, 18), seed=31)
+    g, st = gpu_run(d, precision=prec, exec_mode=mode)
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    for b in oracle.split_domains(d):
+        gb, sb = gpu_run(b | {"boxes": b["box"].reshape(1, 3)}, precision=prec, exec_mode=mode)
+        idx = b["index"]
+        for k in ("rho", "H"):
+            assert np.max(np.abs(g[k][idx] - gb[k]) / gb[k]) < tol, k
+        sa = np.abs(gb["ax"]) + np.abs(gb["ay"]) + np.abs(gb["az"]) + 1e-300
+        for k in ("ax", "ay", "az"):
+            assert np.max(np.abs(g[k][idx] - gb[k]) / sa) < 100 * tol, k
+        if prec == "fp64":
+            assert np.array_equal(g["nngb"][idx], gb["nngb"])
