@@ -153,7 +153,7 @@ def mlp_eval(S, sim, t, dt, steps, rec_steps=50, seed=17):
             "step_time_ratio_mlp_over_plain": res["mlp"]["ms_per_step"] / res["plain"]["ms_per_step"]}
 
 
-def ensemble_eval(S, prec, steps=3, seed=2743):
+def ensemble_eval(S, prec, steps=3, seed=2743, rebuild_steps=0):
     """64 independent periodic boxes (n_side ~ U{16..96}): every stage of a
     step as one launch over all boxes, against 64 contexts stepped one after
     the other (the plain solves).  Same dt for both; per-box FP64 totals."""
@@ -177,7 +177,7 @@ def ensemble_eval(S, prec, steps=3, seed=2743):
     dt = None
     for mode in ("persistent", "grid"):
         tt = {k: v.clone() for k, v in t_all.items()}
-        sim = S.SPH(boxes, precision=prec, exec_mode=mode)
+        sim = S.SPH(boxes, precision=prec, exec_mode=mode, rebuild_steps=rebuild_steps)
         sim.bind(tt)
         sim.run()
         if dt is None:
@@ -196,6 +196,10 @@ def ensemble_eval(S, prec, steps=3, seed=2743):
         sums1 = sim.domain_sums()
         inter = sum(q["n_dens"] + 2 * q["n_force"] for q in per)
         union[mode] = {"ms_per_step": wall / steps * 1e3, "interactions_per_s": inter / wall,
+                       "mean_sweeps": sum(q["sweeps"] for q in per) / steps,
+                       "phase_ms_per_step": {k: sum(q["t_%s_ms" % k] for q in per) / steps
+                                             for k in ("density", "ghost", "force")},
+                       "builds": per[-1]["n_builds"] - per[0]["n_builds"] + (per[0]["steps_since_build"] == 0),
                        "max_rel_mass_change": float(np.max(np.abs(sums1[:, 0] - sums0[:, 0]) / sums0[:, 0])),
                        "max_rel_energy_change": float(np.max(np.abs(sums1[:, 4] - sums0[:, 4]) / sums0[:, 4]))}
         sim.close()
@@ -205,7 +209,7 @@ def ensemble_eval(S, prec, steps=3, seed=2743):
     sims = []
     for box, sub in parts:
         tb = S.to_device(sub)
-        sb = S.SPH(box, precision=prec)
+        sb = S.SPH(box, precision=prec, rebuild_steps=rebuild_steps)
         sb.bind(tb)
         sb.run()
         sb.step(dt)
@@ -225,7 +229,8 @@ def ensemble_eval(S, prec, steps=3, seed=2743):
     seq = {"ms_per_step": wall / steps * 1e3, "interactions_per_s": inter / wall}
     log("ensemble sequential: %.2f ms/step" % seq["ms_per_step"])
     best = min(union.values(), key=lambda r: r["ms_per_step"])
-    out.update({"precision": prec, "dt": dt, "steps": steps, "union": union, "sequential": seq,
+    out.update({"precision": prec, "rebuild_steps": rebuild_steps, "dt": dt, "steps": steps, "union": union,
+                "sequential": seq,
                 "speedup_union_over_sequential": seq["ms_per_step"] / best["ms_per_step"]})
     return out
 
@@ -414,7 +419,7 @@ def main():
     del t
     torch.cuda.empty_cache()
     if not args.no_ensemble:
-        out["ensemble"] = ensemble_eval(S, args.precision)
+        out["ensemble"] = ensemble_eval(S, args.precision, rebuild_steps=cfg["rebuild_steps"])
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

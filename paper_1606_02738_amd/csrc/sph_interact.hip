@@ -204,6 +204,8 @@ struct DensArgs {
     const int* l_count;
     const double* l_origin;
     const double* l_hlist;
+    const double* l_lo;   // leaf boxes at the build (3 per leaf)
+    const double* l_hi;
     const int* l_dom;
     const int* l_off;
     const ListEntry* list;
@@ -359,13 +361,56 @@ __device__ inline bool dens_finish(const DensArgs& a, int i, bool act, int jg, i
     return left;
 }
 
+// Neighbour-entry batch with each cell's box (at the build, A's frame,
+// grown by `grow`), for the packed density path.
+template <typename T, int NE>
+struct EBatchBox {
+    int b[NE], n[NE];
+    T ox[NE], oy[NE], oz[NE];
+    T lo[3][NE], hi[3][NE];
+};
+
+template <typename T, typename Keep, int NE>
+__device__ inline int load_batch_box(const ListEntry* list, int eb, int nbt, int lane, const int* l_begin,
+                                     const int* l_count, const double* l_origin, const double* l_lo, const double* l_hi,
+                                     const double* oA, const DomainInfo& I, double grow, Keep keep,
+                                     EBatchBox<T, NE>& E)
+{
+    bool ok = false;
+    ListEntry en;
+    if (lane < nbt) {
+        en = list[eb + lane];
+        ok = keep(en);
+    }
+    const unsigned long long mask = __ballot(ok);
+    if (ok) {
+        const int s = mask_rank(mask, lane);
+        const int B = en.B;
+        double sv[3];
+        shift_vec(en.code, I, sv);
+        E.b[s] = l_begin[B];
+        E.n[s] = l_count[B];
+        E.ox[s] = (T)(l_origin[3 * B] + sv[0] - oA[0]);
+        E.oy[s] = (T)(l_origin[3 * B + 1] + sv[1] - oA[1]);
+        E.oz[s] = (T)(l_origin[3 * B + 2] + sv[2] - oA[2]);
+        for (int d = 0; d < 3; d++) {
+            E.lo[d][s] = (T)(l_lo[3 * B + d] + sv[d] - oA[d] - grow);
+            E.hi[d][s] = (T)(l_hi[3 * B + d] + sv[d] - oA[d] + grow);
+        }
+    }
+    wave_sync();
+    return __popcll(mask);
+}
+
+#define PD_ENTRIES 32  // list entries per batch of the packed density path
+
 // Candidate buffer of the packed density path (one wave): candidates j of
 // all neighbour cells in A's frame, packed 64 at a time, and A's particles.
 template <typename T>
 struct PTile {
     typename vec4<T>::type cand[128];  // j in A's frame, w = m
     typename vec4<T>::type si[64];     // i of A: x, y, z (A frame), H^2 (negative when inactive)
-    EBatch<T> e;
+    EBatchBox<T, PD_ENTRIES> e;
 };
 
 // Density sweep of one leaf (at most 64 particles, box pruning).  The
@@ -424,13 +469,19 @@ __device__ void density_leaf_packed(const DensArgs& a, int A, PTile<T>& L, int l
         if (EXTRAP) s2 += q4.w * spline_d2(q, dw);
         cnt++;
     };
+    // box of the buffered candidates (union of their cells' boxes)
+    T tlo[3] = {big, big, big}, thi[3] = {-big, -big, -big};
     // both phases on the first `len` packed candidates
     auto run_tile = [&](int len) {
         wave_sync();
         const V4 pj = L.cand[lane];
         const bool lv = lane < len;
+        // particles of A farther than their H from the box of every candidate
+        // have no pair in this tile
+        const unsigned long long imask =
+            amask & __ballot(box_d2<T>(pi.x, pi.y, pi.z, tlo[0], tlo[1], tlo[2], thi[0], thi[1], thi[2]) < H2);
         int mlo = 0, mhi = 0;
-        for (unsigned long long m = amask; m; m &= m - 1ull) {
+        for (unsigned long long m = imask; m; m &= m - 1ull) {
             const int ii = uniform(__ffsll((long long)m) - 1);
             const V4 q = L.si[ii];
             const T dx = pj.x - q.x, dy = pj.y - q.y, dz = pj.z - q.z;
@@ -451,15 +502,19 @@ __device__ void density_leaf_packed(const DensArgs& a, int A, PTile<T>& L, int l
         wave_sync();
     };
     int ncand = 0;
-    for (int eb = e0; eb < e1; eb += 64) {
-        const int nbt = min(64, e1 - eb);
-        const int nv = load_batch<T>(a.list, eb, nbt, lane, a.l_begin, a.l_count, a.l_origin, oA, I,
-                                     [&](const ListEntry& E) { return E.dist < hA + mg; }, L.e, nullptr, A);
+    // cell boxes grow by the displacement since the build plus float rounding
+    const double grow = 0.5 * mg + 1e-5 * fmax(hlA, hA);
+    for (int eb = e0; eb < e1; eb += PD_ENTRIES) {
+        const int nbt = min(PD_ENTRIES, e1 - eb);
+        const int nv = load_batch_box<T>(a.list, eb, nbt, lane, a.l_begin, a.l_count, a.l_origin, a.l_lo, a.l_hi, oA, I,
+                                         grow, [&](const ListEntry& E) { return E.dist < hA + mg; }, L.e);
         V4 pf;  // prefetched first chunk of the next cell
         if (nv > 0 && lane < L.e.n[0]) pf = pos4[L.e.b[0] + lane];
         for (int k = 0; k < nv; k++) {
             const int bB = L.e.b[k], nB = L.e.n[k];
             const T dox = L.e.ox[k], doy = L.e.oy[k], doz = L.e.oz[k];
+            const T klo[3] = {L.e.lo[0][k], L.e.lo[1][k], L.e.lo[2][k]};
+            const T khi[3] = {L.e.hi[0][k], L.e.hi[1][k], L.e.hi[2][k]};
             V4 cur = pf;
             if (k + 1 < nv && lane < L.e.n[k + 1]) pf = pos4[L.e.b[k + 1] + lane];
             for (int p0 = 0; p0 < nB; p0 += 64) {
@@ -476,6 +531,12 @@ __device__ void density_leaf_packed(const DensArgs& a, int A, PTile<T>& L, int l
                 const unsigned long long mk = __ballot(in);
                 if (in) L.cand[ncand + mask_rank(mk, lane)] = q;
                 ncand += __popcll(mk);
+                if (mk) {
+                    for (int d = 0; d < 3; d++) {
+                        tlo[d] = fmin(tlo[d], klo[d]);
+                        thi[d] = fmax(thi[d], khi[d]);
+                    }
+                }
                 if (ncand >= 64) {
                     run_tile(64);
                     const int rest = ncand - 64;
@@ -484,6 +545,11 @@ __device__ void density_leaf_packed(const DensArgs& a, int A, PTile<T>& L, int l
                     wave_sync();
                     if (lane < rest) L.cand[lane] = t;
                     ncand = rest;
+                    // the carried candidates all come from this cell
+                    for (int d = 0; d < 3; d++) {
+                        tlo[d] = rest ? klo[d] : big;
+                        thi[d] = rest ? khi[d] : -big;
+                    }
                 }
             }
         }
@@ -691,7 +757,7 @@ __global__ __launch_bounds__(256) void k_density(DensArgs a)
 // pruning); the LDS is only the packed candidate buffer, so more waves fit
 // on a CU than with the two-phase tiles.
 #ifndef SPH_DENS_WAVES
-#define SPH_DENS_WAVES 8  // measured best: spills stay outside the inner loops
+#define SPH_DENS_WAVES 6  // measured best (8 waves spill more than they gain)
 #endif
 template <typename T, bool COMP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPH_DENS_WAVES, 8))) void k_density_packed(
@@ -1348,6 +1414,8 @@ static void dens_args(sph_ctx* c, const int* gate, bool graph, DensArgs& a, int&
     a.l_count = (const int*)c->l_count.p;
     a.l_origin = (const double*)c->l_origin.p;
     a.l_hlist = (const double*)c->l_hlist.p;
+    a.l_lo = (const double*)c->l_lo.p;
+    a.l_hi = (const double*)c->l_hi.p;
     a.l_dom = (const int*)c->l_dom.p;
     a.l_off = (const int*)c->l_off.p;
     a.list = (const ListEntry*)c->list.p;
