@@ -41,7 +41,8 @@ __device__ inline void spline_w_dw(T q, T& w, T& dw)
 template <typename T>
 __device__ inline T spline_d2(T q, T dw)
 {
-    const T d2 = (q <= T(0.5)) ? (T(36) * q - T(12)) : T(12) * (T(1) - q);
+    const T di = T(36) * q - T(12), dout = T(12) * (T(1) - q);  // both pieces, then a select
+    const T d2 = (q <= T(0.5)) ? di : dout;
     return q * (q * d2 + T(2) * dw);
 }
 
@@ -49,7 +50,8 @@ template <typename T>
 __device__ inline T spline_dw(T q)
 {
     const T t = T(1) - q;
-    T v = (q <= T(0.5)) ? q * (T(18) * q - T(12)) : T(-6) * t * t;
+    const T vi = q * (T(18) * q - T(12)), vo = T(-6) * t * t;  // both pieces, then a select
+    const T v = (q <= T(0.5)) ? vi : vo;
     return (q < T(1)) ? v : T(0);
 }
 
