@@ -153,6 +153,39 @@ def mlp_eval(S, sim, t, dt, steps, rec_steps=50, seed=17):
             "step_time_ratio_mlp_over_plain": res["mlp"]["ms_per_step"] / res["plain"]["ms_per_step"]}
 
 
+def precision_eval(S, box, t, dt, cfg, steps=5):
+    """Form (1) against the plain precisions: the same state stepped with
+    each arithmetic (FP64, FP32 plain sums, FP32 cell-relative compensated),
+    same launch configuration; ms per step and interactions per second."""
+    import torch
+    state = {k: v.clone() for k, v in t.items()}
+    res = {}
+    for prec in ("fp64", "fp32", "fp32c"):
+        for k in t:
+            t[k].copy_(state[k])
+        sim = S.SPH(box, precision=prec, **cfg)
+        sim.bind(t)
+        sim.run()
+        sim.step(dt)
+        torch.cuda.synchronize()
+        per = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sim.step(dt)
+            per.append(sim.stats())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        sim.close()
+        res[prec] = {"ms_per_step": wall / steps * 1e3,
+                     "interactions_per_s": sum(q["n_dens"] + 2 * q["n_force"] for q in per) / wall,
+                     "force_kernel_ms": sum(q["t_force_kernel_ms"] for q in per) / steps,
+                     "density_kernels_ms": sum(q["t_density_kernels_ms"] for q in per) / steps}
+        log("precision %s: %.2f ms/step" % (prec, res[prec]["ms_per_step"]))
+    for k in t:
+        t[k].copy_(state[k])
+    return res
+
+
 def ensemble_eval(S, prec, steps=3, seed=2743, rebuild_steps=0):
     """64 independent periodic boxes (n_side ~ U{16..96}): every stage of a
     step as one launch over all boxes, against 64 contexts stepped one after
@@ -256,6 +289,7 @@ def main():
     ap.add_argument("--seed", type=int, default=2741)
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned H predictor comparison")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-box ensemble comparison")
+    ap.add_argument("--no-forms", action="store_true", help="skip the FP64 / FP32 / FP32C step comparison")
     ap.add_argument("--mlp-steps", type=int, default=5)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 512 MiB device copy first (calibrates HBM byte counters)")
@@ -413,6 +447,12 @@ def main():
     }
     if tune_table is not None:
         out["autotune"] = [dict(c, ms_per_step=ms) for c, ms in tune_table]
+    if not args.no_forms:
+        sim.close()
+        out["precision_forms"] = precision_eval(S, box, t, dt, cfg)
+        sim = S.SPH(box, precision=args.precision, **cfg)
+        sim.bind(t)
+        sim.run()
     if not args.no_mlp:
         out["h_predictor"] = mlp_eval(S, sim, t, dt, args.mlp_steps)
     sim.close()

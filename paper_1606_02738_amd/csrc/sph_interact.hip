@@ -1320,7 +1320,9 @@ __global__ __launch_bounds__(256) void k_kick_drift(int64_t n, double* x, double
     if (threadIdx.x == 0) {
         double b = wmax[0];
         for (int w = 1; w < (int)(blockDim.x >> 6); w++) b = fmax(b, wmax[w]);
-        atomicMax(vmax_bits, (unsigned long long)__double_as_longlong(b));
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(b);
+        // most blocks are below the running maximum: skip their atomics
+        if (bits > __atomic_load_n(vmax_bits, __ATOMIC_RELAXED)) atomicMax(vmax_bits, bits);
     }
 }
 
@@ -1352,18 +1354,18 @@ __global__ __launch_bounds__(256) void k_kick(int64_t n, double* vx, double* vy,
     u[i] += dudt[i] * h;
 }
 
-#define SUM_CHUNKS 64
-// partial[(d * SUM_CHUNKS + chunk) * 5 + k]
+// partial[(d * chunks + chunk) * 5 + k]; chunks per box is chosen so that
+// the grid holds about 4096 workgroups (at least 64 per box)
 __global__ __launch_bounds__(256) void k_sums_partial(const int* __restrict__ ranges, const double* __restrict__ m,
                                                       const double* __restrict__ vx, const double* __restrict__ vy,
                                                       const double* __restrict__ vz, const double* __restrict__ u,
-                                                      double* partial)
+                                                      double* partial, int chunks)
 {
     __shared__ double red[5][256];
     const int d = blockIdx.y, ch = blockIdx.x, tid = threadIdx.x;
     const int b = ranges[d], e = ranges[d + 1];
     double s[5] = {0, 0, 0, 0, 0};
-    for (int64_t i = b + (int64_t)ch * 256 + tid; i < e; i += (int64_t)SUM_CHUNKS * 256) {
+    for (int64_t i = b + (int64_t)ch * 256 + tid; i < e; i += (int64_t)chunks * 256) {
         const double mm = m[i], v0 = vx[i], v1 = vy[i], v2 = vz[i];
         s[0] += mm;
         s[1] += mm * v0;
@@ -1378,16 +1380,16 @@ __global__ __launch_bounds__(256) void k_sums_partial(const int* __restrict__ ra
             for (int k = 0; k < 5; k++) red[k][tid] += red[k][tid + st];
         __syncthreads();
     }
-    if (tid < 5) partial[((int64_t)d * SUM_CHUNKS + ch) * 5 + tid] = red[tid][0];
+    if (tid < 5) partial[((int64_t)d * chunks + ch) * 5 + tid] = red[tid][0];
 }
 
-__global__ void k_sums_final(int ndom, const double* __restrict__ partial, double* out)
+__global__ void k_sums_final(int ndom, const double* __restrict__ partial, double* out, int chunks)
 {
     const int d = blockIdx.x * blockDim.x + threadIdx.x;
     if (d >= ndom) return;
     for (int k = 0; k < 5; k++) {
         double s = 0.0;
-        for (int ch = 0; ch < SUM_CHUNKS; ch++) s += partial[((int64_t)d * SUM_CHUNKS + ch) * 5 + k];
+        for (int ch = 0; ch < chunks; ch++) s += partial[((int64_t)d * chunks + ch) * 5 + k];
         out[5 * d + k] = s;
     }
 }
@@ -1923,14 +1925,15 @@ sph_status dgf_graph(sph_ctx* c)
 sph_status domain_sums(sph_ctx* c, double* host_out)
 {
     const int nd = c->prm.n_domains;
-    SPH_TRY(buf_ensure(c->dsum_part, (size_t)nd * SUM_CHUNKS * 5 * 8 + (size_t)nd * 5 * 8));
+    const int chunks = std::max(64, std::min(4096, 4096 / std::max(nd, 1)));
+    SPH_TRY(buf_ensure(c->dsum_part, (size_t)nd * chunks * 5 * 8 + (size_t)nd * 5 * 8));
     const int* ranges = (const int*)c->dranges.p;
     double* part = (double*)c->dsum_part.p;
-    double* out = part + (size_t)nd * SUM_CHUNKS * 5;
-    dim3 g(SUM_CHUNKS, nd);
-    k_sums_partial<<<g, 256, 0, c->stream>>>(ranges, c->P.m, c->P.vx, c->P.vy, c->P.vz, c->P.u, part);
+    double* out = part + (size_t)nd * chunks * 5;
+    dim3 g(chunks, nd);
+    k_sums_partial<<<g, 256, 0, c->stream>>>(ranges, c->P.m, c->P.vx, c->P.vy, c->P.vz, c->P.u, part, chunks);
     SPH_CHECK_LAUNCH();
-    k_sums_final<<<blocks_for(nd, 64), 64, 0, c->stream>>>(nd, part, out);
+    k_sums_final<<<blocks_for(nd, 64), 64, 0, c->stream>>>(nd, part, out, chunks);
     SPH_CHECK_LAUNCH();
     SPH_CHECK_HIP(hipMemcpyAsync(host_out, out, (size_t)nd * 5 * 8, hipMemcpyDeviceToHost, c->stream));
     SPH_CHECK_HIP(hipStreamSynchronize(c->stream));

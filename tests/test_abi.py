@@ -72,3 +72,33 @@ def test_null_arguments(L):
         assert getattr(L, f)(None) == -1
     assert L.sph_step(None, 0.1) == -1
     assert L.sph_build_cells(None, None) == -1
+
+
+def test_predictor_calls_reject_bad_arguments(L):
+    """The predictor entry points check their arguments before any GPU work."""
+    vp = C.c_void_p
+    assert L.sph_mlp_forward(None, None, 0, None, None) == 0        # nothing to do
+    assert L.sph_mlp_forward(None, None, 5, None, None) == -1
+    assert L.sph_mlp_forward(vp(1), vp(1), -1, vp(1), None) == -1
+    assert L.sph_mlp_loss_grad(None, None, None, 0, None, None, None) == -1
+    assert L.sph_mlp_adam(None, None, None, None, 1, C.c_float(1e-3), C.c_float(0.9), C.c_float(0.999),
+                          C.c_float(1e-8), None) == -1
+    assert L.sph_mlp_adam(vp(1), vp(1), vp(1), vp(1), 0, C.c_float(1e-3), C.c_float(0.9), C.c_float(0.999),
+                          C.c_float(1e-8), None) == -1
+    assert L.sph_h_features(None, 0.1, None) == -1
+    held = C.c_int64()
+    assert L.sph_h_record(None, 10, 0.5, 1, C.byref(held)) == -1
+    assert L.sph_h_train(None, 1, 16, 1e-3, 1, 1, None) == -1
+    assert L.sph_h_set_params(None, None) == -1
+    assert L.sph_h_get_params(None, None) == -1
+    assert L.sph_h_predict(None, 1) == -1
+
+
+def test_predictor_layout_constants_match_the_oracle():
+    from oracle import mlp as M
+    txt = open(os.path.join(ROOT, "include", "sph.h")).read()
+    consts = dict(re.findall(r"#define (SPH_MLP_\w+) (\d+)", txt))
+    assert int(consts["SPH_MLP_NT"]) == M.NT == S.MLP_NT
+    assert int(consts["SPH_MLP_NP"]) == M.NP == S.MLP_NP
+    assert int(consts["SPH_MLP_NIN"]) == M.NIN and int(consts["SPH_MLP_NH"]) == M.NH
+    assert int(consts["SPH_MLP_NF"]) == M.NF

@@ -93,3 +93,26 @@ def test_graph_steps_reuse():
         assert np.max(np.abs(a[k] - b[k])) / scale < 1e-9, k
     ca, cb = res[False][1]["conserved"], res[True][1]["conserved"]
     assert np.allclose(ca, cb, rtol=1e-9, atol=1e-12)
+
+
+def test_autotune_picks_a_timed_candidate_and_restores_state():
+    import torch
+    from paper_1606_02738_amd import autotune as AT
+    from paper_1606_02738_amd import sph as S
+    log("case autotune clustered 24^3")
+    d = gen.clustered(24, n_halos=8, seed=2741)
+    t = S.to_device(d)
+    sim = S.SPH(d["box"], precision="fp32c")
+    sim.bind(t)
+    sim.run()
+    sim.close()
+    before = {k: v.clone() for k, v in t.items()}
+    cands = [dict(n_split=64, exec_mode="grid", persistent_wgs=0, prune="box", use_graph=False, rebuild_steps=0),
+             dict(n_split=32, exec_mode="persistent", persistent_wgs=512, prune="box", use_graph=True,
+                  rebuild_steps=4)]
+    best, table = AT.autotune(d["box"], t, "fp32c", 1e-5, steps=2, cands=cands, cache=None)
+    torch.cuda.synchronize()
+    log("table: %s" % [(c["n_split"], c["exec_mode"], round(ms, 3)) for c, ms in table])
+    assert best in cands and len(table) == 2 and all(ms > 0 for _, ms in table)
+    for k in t:
+        assert torch.equal(t[k], before[k]), k
