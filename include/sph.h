@@ -131,7 +131,8 @@ typedef struct {
     int32_t n_density_launches; /* density-sweep kernel launches of the last density call */
     int32_t graph_captures;     /* graph (re)captures since sph_create (use_graph = 1) */
     int32_t graph_fallbacks;    /* graph runs the host had to finish since sph_create */
-    int32_t pad;
+    int32_t precision_rebuilds; /* FP32 modes: rebuilds since sph_create because H had shrunk
+                                   below the cells' extent rule after converging */
     int32_t unconv_after[8];    /* particles left unconverged after sweep k+1 of the last
                                    density call (-1: sweep not run) */
     double t_predict_ms;        /* features + network inference of the last sph_step
@@ -199,6 +200,22 @@ sph_status sph_density_ghost_force(sph_ctx* ctx);
  * conservation sums.  Requires a previous sph_force (forces of the current
  * positions). */
 sph_status sph_step(sph_ctx* ctx, double dt);
+
+/* SPH interpolation, Sec. 2, eq. (interp): out[k] = sum_i m_i Q_i / rho_i
+ * W(|p_k - r_i|, H_i) for m_pts points p_k = (px[k], py[k], pz[k]) of box
+ * pdom[k] (pdom may be NULL with one box), each particle contributing inside
+ * its own support H_i (the scatter reading of the equation), distances
+ * minimum-image in the periodic box.  Q holds one double per bound particle
+ * in the bound arrays' CURRENT order (sph_build_cells permutes them), e.g. the
+ * bound u or a derived field; rho and H are those of the last density stage.
+ * All pointers are DEVICE pointers; points outside [0, L) are wrapped into the
+ * box, and a point with a non-finite coordinate or a box index outside
+ * [0, n_domains) gets NaN.  Asynchronous on the context's stream; out must
+ * not alias Q.  SPH_ERR_INVALID on a NULL pointer with m_pts > 0, m_pts < 0
+ * or > 2^31 - 1, or pdom NULL with several boxes; SPH_ERR_STATE before
+ * sph_density. */
+sph_status sph_interpolate(sph_ctx* ctx, const double* Q, const double* px, const double* py, const double* pz,
+                           const int32_t* pdom, int64_t m_pts, double* out);
 
 /* ---------------------------------------------------------------------------
  * Learned smoothing-length predictor.

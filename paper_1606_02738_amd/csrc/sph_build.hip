@@ -640,7 +640,7 @@ __global__ __launch_bounds__(256) void k_node_hmax(Node* nodes, int level_start,
     for (int off = 32; off > 0; off >>= 1) hm = fmax(hm, __shfl_xor(hm, off));
     if (lane == 0) {
         nd.hmax = hm;
-        if (nd.leaf >= 0) l_hlist[nd.leaf] = hm * (1.0 + SPH_LIST_SKIN) + skin_abs;
+        if (nd.leaf >= 0 && l_hlist) l_hlist[nd.leaf] = hm * (1.0 + SPH_LIST_SKIN) + skin_abs;
     }
 }
 
@@ -817,17 +817,24 @@ sph_status domain_ranges(sph_ctx* c)
     return SPH_OK;
 }
 
-sph_status relist(sph_ctx* c)
+// Largest H per cell from the current H, deepest level first; with
+// set_hlist the leaves' list radii become it plus the skins.
+sph_status node_hmax_all(sph_ctx* c, bool set_hlist)
 {
-    // largest H per cell, deepest level first
     Node* nodes = (Node*)c->nodes.p;
     for (int l = (int)c->level_off.size() - 2; l >= 0; l--) {
         const int s = c->level_off[l], nl = c->level_off[l + 1] - s;
         if (nl <= 0) continue;
-        k_node_hmax<<<blocks_for(nl, 4), 256, 0, c->stream>>>(nodes, s, nl, c->P.H, (double*)c->l_hlist.p,
-                                                               c->skin_abs);
+        k_node_hmax<<<blocks_for(nl, 4), 256, 0, c->stream>>>(
+            nodes, s, nl, c->P.H, set_hlist ? (double*)c->l_hlist.p : nullptr, c->skin_abs);
         SPH_CHECK_LAUNCH();
     }
+    return SPH_OK;
+}
+
+sph_status relist(sph_ctx* c)
+{
+    SPH_TRY(node_hmax_all(c, true));
     const int nL = c->n_leaves;
     int* counts = (int*)c->l_off.p;
     int* flags = (int*)c->flags.p;

@@ -126,6 +126,7 @@ sph_status radix_sort(sph_ctx* c, int n, int bits, DevBuf* kb, DevBuf* vb, int* 
 sph_status build_all(sph_ctx* c);
 sph_status sort_all(sph_ctx* c);
 sph_status relist(sph_ctx* c);
+sph_status node_hmax_all(sph_ctx* c, bool set_hlist);
 sph_status refresh_leaves(sph_ctx* c, bool* fresh);
 sph_status domain_ranges(sph_ctx* c);
 

@@ -1503,6 +1503,31 @@ static sph_status density_reset(sph_ctx* c)
 // Host-driven sweeps: one sweep, read the counters, relist or rebuild if a
 // smoothing length outgrew the lists or the grid, repeat until converged.
 // `done_sweeps` sweeps were already run on the device (graph mode).
+// FP32 modes: cells are split at the build until their extent is at most
+// SPH_FP32_EXTENT_RATIO times their smallest H, which bounds the error of
+// the cell-relative coordinates against H.  H can shrink far below its value
+// at the build during the iteration (a poor initial guess); this flags a
+// leaf that could still be split and whose extent (plus the motion since
+// the build) now exceeds twice that ratio times its smallest converged H.
+__global__ __launch_bounds__(256) void k_extent_check(int n_leaves, const int* __restrict__ l_begin,
+                                                      const int* __restrict__ l_count, const double* __restrict__ l_lo,
+                                                      const double* __restrict__ l_hi, const int* __restrict__ leaf_node,
+                                                      const Node* __restrict__ nodes, int max_level,
+                                                      const double* __restrict__ H, double grow, int* flags)
+{
+    const int A = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6));
+    if (A >= n_leaves) return;
+    const int lane = threadIdx.x & 63;
+    const int b = l_begin[A], n = l_count[A];
+    if (n < 2 || nodes[leaf_node[A]].level >= max_level) return;
+    double hm = INFINITY;
+    for (int p = b + lane; p < b + n; p += 64) hm = fmin(hm, H[p]);
+    for (int off = 32; off > 0; off >>= 1) hm = fmin(hm, __shfl_xor(hm, off));
+    const double ext = fmax(fmax(l_hi[3 * A] - l_lo[3 * A], l_hi[3 * A + 1] - l_lo[3 * A + 1]),
+                            l_hi[3 * A + 2] - l_lo[3 * A + 2]) + grow;
+    if (lane == 0 && ext > 2.0 * SPH_FP32_EXTENT_RATIO * hm) atomicOr(flags, FLAG_REBUILD);
+}
+
 static sph_status density_loop(sph_ctx* c, int done_sweeps, unsigned long long unconv0)
 {
     int* flags = (int*)c->flags.p;
@@ -1510,6 +1535,7 @@ static sph_status density_loop(sph_ctx* c, int done_sweeps, unsigned long long u
     int sweeps = 0;
     unsigned long long unconv = unconv0;
     int fl = 0;
+    bool prec_rebuilt = false;
     sph_status status = SPH_OK;
     for (sweeps = done_sweeps + 1; sweeps <= c->prm.max_h_iter; sweeps++) {
         SPH_CHECK_HIP(hipMemsetAsync(flags, 0, sizeof(int), c->stream));
@@ -1532,6 +1558,33 @@ static sph_status density_loop(sph_ctx* c, int done_sweeps, unsigned long long u
         unconv = hc[CNT_UNCONV];
         if (sweeps <= 8) c->st.unconv_after[sweeps - 1] = (int)std::min<unsigned long long>(unconv, INT32_MAX);
         if (fl & FLAG_BOX_SMALL) status = SPH_ERR_BOX_TOO_SMALL;
+        if (unconv == 0 && c->prm.precision != SPH_FP64 && !prec_rebuilt && status == SPH_OK &&
+            sweeps < c->prm.max_h_iter) {
+            SPH_CHECK_HIP(hipMemsetAsync(flags, 0, sizeof(int), c->stream));
+            k_extent_check<<<blocks_for(c->n_leaves, 4), 256, 0, c->stream>>>(
+                c->n_leaves, (const int*)c->l_begin.p, (const int*)c->l_count.p, (const double*)c->l_lo.p,
+                (const double*)c->l_hi.p, (const int*)c->leaf_node.p, (const Node*)c->nodes.p, c->D, c->P.H,
+                2.0 * c->delta, flags);
+            SPH_CHECK_LAUNCH();
+            SPH_CHECK_HIP(hipMemcpyAsync(&fl, flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+            SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
+            if (fl & FLAG_REBUILD) {
+                // converged on cells too coarse for the final H: rebuild once
+                // and evaluate again from the converged H
+                prec_rebuilt = true;
+                unconv = 1;
+                SPH_TRY(build_all(c));
+                SPH_TRY(sort_all(c));
+                k_density_reset<<<blocks_for(std::max<int64_t>(c->n, c->n_leaves), 256), 256, 0, c->stream>>>(
+                    c->n, c->n_leaves, (double*)c->hlo.p, (double*)c->hhi.p, (uint8_t*)c->conv.p,
+                    (int*)c->l_active.p, nullptr);
+                SPH_CHECK_LAUNCH();
+                SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_NDENS], 0, 8, c->stream));
+                c->st.rebuilds++;
+                c->st.precision_rebuilds++;
+                continue;
+            }
+        }
         if (unconv == 0) break;
         if ((fl & FLAG_REBUILD) || ((fl & FLAG_RELIST) && c->delta > 0.0)) {
             // a smoothing length outgrew the top grid, or outgrew its list

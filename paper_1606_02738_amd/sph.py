@@ -61,7 +61,7 @@ class Stats(C.Structure):
                 ("t_force_ms", C.c_double), ("t_build_ms", C.c_double),
                 ("t_density_kernels_ms", C.c_double), ("t_force_kernel_ms", C.c_double),
                 ("n_dens_evals", C.c_int64), ("n_density_launches", C.c_int32),
-                ("graph_captures", C.c_int32), ("graph_fallbacks", C.c_int32), ("pad", C.c_int32),
+                ("graph_captures", C.c_int32), ("graph_fallbacks", C.c_int32), ("precision_rebuilds", C.c_int32),
                 ("unconv_after", C.c_int32 * 8), ("t_predict_ms", C.c_double),
                 ("steps_since_build", C.c_int64), ("n_builds", C.c_int64), ("list_margin", C.c_double)]
 
@@ -77,7 +77,7 @@ EXPORTS = ("sph_create", "sph_destroy", "sph_build_cells", "sph_sort_cells", "sp
            "sph_ghost", "sph_force", "sph_density_ghost_force", "sph_step", "sph_get_stats", "sph_domain_sums",
            "sph_status_str", "sph_version", "sph_mlp_forward", "sph_mlp_loss_grad", "sph_mlp_adam",
            "sph_h_features", "sph_h_record", "sph_h_train", "sph_h_set_params", "sph_h_get_params",
-           "sph_h_predict")
+           "sph_h_predict", "sph_interpolate")
 
 MLP_NF, MLP_XSTRIDE, MLP_NIN, MLP_NH, MLP_NT, MLP_NP = 7, 8, 16, 64, 9473, 9507
 
@@ -110,6 +110,7 @@ def lib():
         L.sph_h_set_params.argtypes = [vp, C.POINTER(C.c_float)]
         L.sph_h_get_params.argtypes = [vp, C.POINTER(C.c_float)]
         L.sph_h_predict.argtypes = [vp, C.c_int]
+        L.sph_interpolate.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int64, vp]
         for f in EXPORTS:
             if f not in ("sph_status_str", "sph_version"):
                 getattr(L, f).restype = C.c_int
@@ -260,6 +261,22 @@ class SPH:
 
     def step(self, dt):
         _check(lib().sph_step(self.h, float(dt)), "sph_step")
+
+    def interpolate(self, Q, px, py, pz, pdom=None):
+        """Eq. (interp) at the given points (device float64 tensors; Q in the
+        bound arrays' current order); returns a float64 tensor."""
+        T = self._torch
+        m_pts = px.numel()
+        for t in (Q, px, py, pz):
+            assert t.dtype == T.float64 and t.is_contiguous() and t.is_cuda
+        assert py.numel() == m_pts and pz.numel() == m_pts and Q.numel() == self.t["x"].numel()
+        if pdom is not None:
+            assert pdom.dtype == T.int32 and pdom.numel() == m_pts and pdom.is_contiguous()
+        out = T.empty(m_pts, dtype=T.float64, device=px.device)
+        _check(lib().sph_interpolate(self.h, Q.data_ptr(), px.data_ptr(), py.data_ptr(), pz.data_ptr(),
+                                     None if pdom is None else pdom.data_ptr(), m_pts, out.data_ptr()),
+               "sph_interpolate")
+        return out
 
     def h_features(self, dt):
         """Predictor features of the bound particles (n x 8 float32 tensor)."""

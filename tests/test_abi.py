@@ -72,6 +72,7 @@ def test_null_arguments(L):
         assert getattr(L, f)(None) == -1
     assert L.sph_step(None, 0.1) == -1
     assert L.sph_build_cells(None, None) == -1
+    assert L.sph_interpolate(None, None, None, None, None, None, 0, None) == -1
 
 
 def test_predictor_calls_reject_bad_arguments(L):

@@ -188,3 +188,34 @@ def test_ensemble_boxes_equal_standalone_runs(prec, mode):
             assert np.max(np.abs(g[k][idx] - gb[k]) / sa) < 100 * tol, k
         if prec == "fp64":
             assert np.array_equal(g["nngb"][idx], gb["nngb"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_wide_h_range_stress(prec):
+    """A more extreme clustered box (log-density sigma 3, half the particles
+    in concentrated halos over 4 decades of mass): smoothing lengths span
+    about three decades; deep octrees and the FP32 extent rule.
+
+    The initial H are far from the converged ones (18 sweeps), so cells built
+    for them end up too coarse for the final H in the FP32 modes (rho error
+    1.2e-5 when measured without the check): the density stage then rebuilds
+    once from the converged H and evaluates again."""
+    log("case wide h range 40^3 %s" % prec)
+    d = gen.clustered(40, seed=77, n_halos=40, sigma_ln=3.0, halo_frac=0.5, c_range=(15.0, 40.0), decades=4.0)
+    g, st = gpu_run(d, precision=prec)
+    o = oracle_run(d)
+    q = np.quantile(o["H"], [0.001, 0.999])
+    log("H span (0.1-99.9%%) %.0f, min-max %.0f, depth %d, leaves %d, sweeps %d, precision rebuilds %d" % (
+        q[1] / q[0], o["H"].max() / o["H"].min(), st["depth"], st["n_leaves"], st["sweeps"],
+        st["precision_rebuilds"]))
+    er = np.abs(g["rho"] - o["rho"]) / o["rho"]
+    w = int(np.argmax(er))
+    log("largest rho error %.3g at Omega %.3g" % (er[w], o["omega"][w]))
+    assert o["H"].max() / o["H"].min() > 1000
+    assert st["n_unconverged"] == 0
+    if prec == "fp64":
+        assert st["precision_rebuilds"] == 0
+        assert_close(g, o, TOL_FP64, stats=st)
+    else:
+        assert st["precision_rebuilds"] == 1
+        assert_close(g, o, TOL_FP32, counts_exact=False)
