@@ -67,6 +67,52 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_interp(d, o, seed, n_pts=16):
+    """The interpolation oracle (brute force over all particles, numpy on
+    the host) on the oracle's own converged state of the baseline sample."""
+    import numpy as np
+    from oracle import interp as OI
+    rng = np.random.default_rng(seed + 99)
+    P = rng.random((n_pts, 3)) * d["box"]
+    t0 = time.perf_counter()
+    OI.interpolate(P[:, 0], P[:, 1], P[:, 2], d["x"], d["y"], d["z"], d["m"], o["rho"], o["H"], d["u"],
+                   d["box"], chunk=4)
+    dt = time.perf_counter() - t0
+    return {"value": n_pts / dt, "unit": "points/s", "kind": "oracle",
+            "sample": "%d random points over the %d particles of the baseline sample (all particles "
+                      "visited per point), %.1f s" % (n_pts, d["x"].size, dt)}
+
+
+def interp_eval(sim, t, box, n_grid=128, reps=5):
+    """Eq. (interp) of u onto the cell centres of an n_grid^3 mesh from the
+    current state (after the timed steps), timed with events on the
+    library's stream."""
+    import torch
+    dev = t["x"].device
+    L = [float(b) for b in box]
+    axes = [(torch.arange(n_grid, device=dev, dtype=torch.float64) + 0.5) * (L[a] / n_grid) for a in range(3)]
+    X, Y, Z = torch.meshgrid(*axes, indexing="ij")
+    px, py, pz = X.contiguous().view(-1), Y.contiguous().view(-1), Z.contiguous().view(-1)
+    del X, Y, Z
+    out = sim.interpolate(t["u"], px, py, pz)  # warm-up
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    for _ in range(reps):
+        out = sim.interpolate(t["u"], px, py, pz)
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    m_pts = px.numel()
+    # the mesh mean of the interpolant estimates its exact box average
+    # sum_i (m_i/rho_i) u_i / V (each kernel integrates to one): equal up to
+    # the mesh sampling (a consistency figure of the field, not a parity check)
+    exact = float((t["m"] / t["rho"] * t["u"]).sum()) / (L[0] * L[1] * L[2])
+    log("interpolation: %d points in %.3f ms" % (m_pts, ms))
+    return {"points": m_pts, "ms_per_call": ms, "points_per_s": m_pts / (ms / 1e3), "field": "u",
+            "mesh_mean": float(out.mean()), "box_average": exact}
+
+
 def cpu_baseline(n_side, seed):
     """The FP64 oracle (k-d tree, OpenMP over the host's threads) on the same
     clustered recipe at n_side^3 particles: density solve from the same kind
@@ -87,8 +133,9 @@ def cpu_baseline(n_side, seed):
                 break
     except OSError:
         pass
+    interp = cpu_interp(d, o, seed)
     return {"value": inter / dt, "unit": "interactions/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "interpolation": interp,
             "sample": "clustered recipe at %d^3 = %d particles (%.3g of the workload), full density "
                       "solve + ghost + force, %.1f s; %s, %d cores in the affinity mask" % (
                           n_side, n_side ** 3, (n_side / 256) ** 3, dt, model, len(os.sched_getaffinity(0)))}
@@ -271,7 +318,7 @@ def ensemble_eval(S, prec, steps=3, seed=2743, rebuild_steps=0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n-side", type=int, default=256)
     ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp32", "fp64"])
@@ -453,6 +500,7 @@ def main():
         sim = S.SPH(box, precision=args.precision, **cfg)
         sim.bind(t)
         sim.run()
+    out["interpolation"] = interp_eval(sim, t, box)
     if not args.no_mlp:
         out["h_predictor"] = mlp_eval(S, sim, t, dt, args.mlp_steps)
     sim.close()

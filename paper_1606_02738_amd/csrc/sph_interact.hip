@@ -1383,15 +1383,23 @@ __global__ __launch_bounds__(256) void k_sums_partial(const int* __restrict__ ra
     if (tid < 5) partial[((int64_t)d * chunks + ch) * 5 + tid] = red[tid][0];
 }
 
-__global__ void k_sums_final(int ndom, const double* __restrict__ partial, double* out, int chunks)
+// One workgroup per box: strided partial sums over the chunks, then a tree
+// in LDS (fixed order, so the totals are reproducible).
+__global__ __launch_bounds__(256) void k_sums_final(const double* __restrict__ partial, double* out, int chunks)
 {
-    const int d = blockIdx.x * blockDim.x + threadIdx.x;
-    if (d >= ndom) return;
-    for (int k = 0; k < 5; k++) {
-        double s = 0.0;
-        for (int ch = 0; ch < chunks; ch++) s += partial[((int64_t)d * chunks + ch) * 5 + k];
-        out[5 * d + k] = s;
+    __shared__ double red[5][256];
+    const int d = blockIdx.x, tid = threadIdx.x;
+    double s[5] = {0, 0, 0, 0, 0};
+    for (int ch = tid; ch < chunks; ch += 256)
+        for (int k = 0; k < 5; k++) s[k] += partial[((int64_t)d * chunks + ch) * 5 + k];
+    for (int k = 0; k < 5; k++) red[k][tid] = s[k];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (tid < st)
+            for (int k = 0; k < 5; k++) red[k][tid] += red[k][tid + st];
+        __syncthreads();
     }
+    if (tid < 5) out[5 * d + tid] = red[tid][0];
 }
 
 // ---------------------------------------------------------------------------
@@ -1978,7 +1986,10 @@ sph_status dgf_graph(sph_ctx* c)
 sph_status domain_sums(sph_ctx* c, double* host_out)
 {
     const int nd = c->prm.n_domains;
-    const int chunks = std::max(64, std::min(4096, 4096 / std::max(nd, 1)));
+    // one 256-thread workgroup per chunk of a box; at most one chunk per 1024
+    // particles (>= 4 per thread) and about 4096 chunks over all boxes
+    const int chunks = (int)std::max<int64_t>(
+        1, std::min<int64_t>(std::max(64, 4096 / std::max(nd, 1)), (c->n + 1023) / 1024));
     SPH_TRY(buf_ensure(c->dsum_part, (size_t)nd * chunks * 5 * 8 + (size_t)nd * 5 * 8));
     const int* ranges = (const int*)c->dranges.p;
     double* part = (double*)c->dsum_part.p;
@@ -1986,7 +1997,7 @@ sph_status domain_sums(sph_ctx* c, double* host_out)
     dim3 g(chunks, nd);
     k_sums_partial<<<g, 256, 0, c->stream>>>(ranges, c->P.m, c->P.vx, c->P.vy, c->P.vz, c->P.u, part, chunks);
     SPH_CHECK_LAUNCH();
-    k_sums_final<<<blocks_for(nd, 64), 64, 0, c->stream>>>(nd, part, out, chunks);
+    k_sums_final<<<nd, 256, 0, c->stream>>>(part, out, chunks);
     SPH_CHECK_LAUNCH();
     SPH_CHECK_HIP(hipMemcpyAsync(host_out, out, (size_t)nd * 5 * 8, hipMemcpyDeviceToHost, c->stream));
     SPH_CHECK_HIP(hipStreamSynchronize(c->stream));

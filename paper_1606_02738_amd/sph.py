@@ -220,7 +220,9 @@ class SPH:
 
     def close(self):
         if getattr(self, "h", None) and self.h.value:
-            lib().sph_destroy(self.h)
+            if _lib is None:  # interpreter shutdown: the module state is gone
+                return
+            _lib.sph_destroy(self.h)
             self.h = C.c_void_p()
 
     __del__ = close
