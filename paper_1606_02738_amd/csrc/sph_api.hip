@@ -99,7 +99,7 @@ sph_status sph_destroy(sph_ctx* c)
     if (!c) return SPH_OK;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
-    DevBuf* all[] = {&c->dom_d, &c->dstat, &c->keys[0], &c->keys[1], &c->vals[0], &c->vals[1], &c->okeys[0], &c->okeys[1], &c->ovals[0], &c->ovals[1], &c->dranges, &c->tmp, &c->nodes, &c->wnodes,
+    DevBuf* all[] = {&c->dom_d, &c->dstat, &c->keys[0], &c->keys[1], &c->vals[0], &c->vals[1], &c->okeys[0], &c->okeys[1], &c->ovals[0], &c->ovals[1], &c->ikeys[0], &c->ikeys[1], &c->ivals[0], &c->ivals[1], &c->dranges, &c->tmp, &c->nodes, &c->wnodes,
                      &c->nchild, &c->coff, &c->leafmark, &c->leafscan, &c->leaf_node, &c->l_begin, &c->l_count,
                      &c->l_origin, &c->l_lo, &c->l_hi, &c->l_hlist, &c->l_dom, &c->l_off, &c->l_active, &c->l_sorted,
                      &c->l_cnt, &c->l_cost, &c->l_order, &c->list, &c->pos4, &c->fv4, &c->hf, &c->skey, &c->sidx,

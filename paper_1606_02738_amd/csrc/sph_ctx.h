@@ -45,6 +45,7 @@ struct sph_ctx {
     DevBuf dom_d, dstat;          // DomainInfo[], per-domain (hmax, hmin) as u64 bits
     DevBuf keys[2], vals[2];      // radix sort ping-pong
     DevBuf okeys[2], ovals[2];    // task-order sort ping-pong
+    DevBuf ikeys[2], ivals[2];    // interpolation point-order sort ping-pong
     DevBuf dranges;               // per-box particle ranges [n_domains + 1]
     const void* keys_sorted = nullptr;  // sorted Morton keys of the last build
     DevBuf tmp;                   // permutation scratch (8 B per particle)

@@ -24,11 +24,18 @@ def _dev():
     oracle.build()
 
 
-def _points(d, box, n_rand, seed):
-    """Random points, particle positions, points on the faces and outside."""
+def _points(d, box, n_rand, seed, n_mesh=0):
+    """Random points, particle positions, points on the faces and outside,
+    and the cell centres of an n_mesh^3 mesh (dense enough that the 64
+    points of a wave after the sort share one top cell: the wave-cooperative
+    walk)."""
     rng = np.random.default_rng(seed)
     L = np.asarray(box, dtype=np.float64)
     P = [rng.random((n_rand, 3)) * L]
+    if n_mesh:
+        g = (np.arange(n_mesh) + 0.5) / n_mesh
+        X, Y, Z = np.meshgrid(g * L[0], g * L[1], g * L[2], indexing="ij")
+        P.append(np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1))
     idx = rng.choice(d["x"].size, size=min(200, d["x"].size), replace=False)
     P.append(np.stack([d["x"][idx], d["y"][idx], d["z"][idx]], 1))
     f = rng.random((64, 3)) * L
@@ -71,7 +78,7 @@ def test_interp_after_density(prec, tol):
     t = S.to_device(d)
     sim.bind(t)
     sim.run()
-    px, py, pz = _points(d, d["box"], 3000, 4403)
+    px, py, pz = _points(d, d["box"], 3000, 4403, n_mesh=24)
     g = _gpu_interp(sim, t, Q, px, py, pz)
     # the unit field through the same call: the normalisation sum
     g1 = _gpu_interp(sim, t, np.ones_like(Q), px, py, pz)
@@ -97,7 +104,7 @@ def test_interp_clustered_deep_tree():
     sim.bind(t)
     sim.run()
     # half of the points at particles (dense regions), half random
-    px, py, pz = _points(d, d["box"], 1000, 4413)
+    px, py, pz = _points(d, d["box"], 1000, 4413, n_mesh=16)
     idx = rng.choice(d["x"].size, 1000, replace=False)
     px = np.concatenate([px, d["x"][idx]])
     py = np.concatenate([py, d["y"][idx]])
@@ -131,7 +138,7 @@ def test_interp_after_lazy_steps():
     st = sim.stats()
     assert st["steps_since_build"] > 0 and st["list_margin"] > 0.0
     h = S.to_host(t)
-    px, py, pz = _points(h, d["box"], 3000, 4423)
+    px, py, pz = _points(h, d["box"], 3000, 4423, n_mesh=24)
     g = _gpu_interp(sim, t, Q, px, py, pz)
     sim.close()
     o = oracle.full(d, tree=True)
@@ -162,7 +169,7 @@ def test_interp_ensemble_with_box_index():
     o = oracle_run(d)
     PX, PY, PZ, PD, OV, SA = [], [], [], [], [], []
     for b, sub in enumerate(oracle.split_domains(d)):
-        px, py, pz = _points(sub, sub["box"], 500, 4433 + b)
+        px, py, pz = _points(sub, sub["box"], 500, 4433 + b, n_mesh=12)
         ix = sub["index"]
         args = (sub["x"], sub["y"], sub["z"], sub["m"], o["rho"][ix], o["H"][ix])
         OV.append(OI.interpolate(px, py, pz, *args, Q[ix], sub["box"]))
