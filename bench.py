@@ -141,10 +141,13 @@ def cpu_baseline(n_side, seed):
                           n_side, n_side ** 3, (n_side / 256) ** 3, dt, model, len(os.sched_getaffinity(0)))}
 
 
-def mlp_eval(S, sim, t, dt, steps, rec_steps=50, seed=17):
+def mlp_eval(S, sim, t, dt, steps, make_sim, rec_steps=50, seed=17):
     """Learned H predictor on the same workload: record samples over
     `rec_steps` plain steps, train with the library's kernels, then time
-    `steps` steps from one saved state without and with the predictor."""
+    `steps` steps from one saved state with the plain start of the H
+    iteration (previous H carried along the flow; and the previous H as
+    is, in a context made by `make_sim(h_drift=False)`) and with the
+    predictor."""
     import torch
     n = t["x"].numel()
     rate = min(1.0, 6.0e6 / (rec_steps * n))
@@ -165,21 +168,25 @@ def mlp_eval(S, sim, t, dt, steps, rec_steps=50, seed=17):
     sim.h_record(0)
     state = {k: v.clone() for k, v in t.items()}
     res = {}
-    for mode in ("plain", "mlp"):
+    for mode in ("plain", "plain_previous_h", "mlp"):
         for k in t:
             t[k].copy_(state[k])
-        sim.bind(t)
-        sim.run()
-        sim.h_predict(mode == "mlp")
-        sim.step(dt)
+        ss = make_sim(h_drift=False) if mode == "plain_previous_h" else sim
+        ss.bind(t)
+        ss.run()
+        if ss is sim:
+            sim.h_predict(mode == "mlp")
+        ss.step(dt)
         torch.cuda.synchronize()
         per = []
         t0 = time.perf_counter()
         for _ in range(steps):
-            sim.step(dt)
-            per.append(sim.stats())
+            ss.step(dt)
+            per.append(ss.stats())
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        if ss is not sim:
+            ss.close()
         res[mode] = {"ms_per_step": wall / steps * 1e3,
                      "mean_sweeps": sum(q["sweeps"] for q in per) / steps,
                      "second_sweep_fraction": sum(q["unconv_after"][0] for q in per) / (steps * n),
@@ -195,7 +202,8 @@ def mlp_eval(S, sim, t, dt, steps, rec_steps=50, seed=17):
     for m in res.values():
         del m["H"]
     return {"samples": held, "record_steps": rec_steps, "train_s": train_s, "train_loss": loss,
-            "epochs": 4, "batch": 16384, "plain": res["plain"], "mlp": res["mlp"],
+            "epochs": 4, "batch": 16384, "plain": res["plain"], "plain_previous_h": res["plain_previous_h"],
+            "mlp": res["mlp"],
             "max_rel_H_difference": dH,
             "step_time_ratio_mlp_over_plain": res["mlp"]["ms_per_step"] / res["plain"]["ms_per_step"]}
 
@@ -333,6 +341,8 @@ def main():
                     help="run the configuration given by the flags instead of the autotuner's choice")
     ap.add_argument("--cpu-n-side", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-h-drift", action="store_true",
+                    help="start the H iteration of a step from the previous H as is")
     ap.add_argument("--seed", type=int, default=2741)
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned H predictor comparison")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-box ensemble comparison")
@@ -369,7 +379,8 @@ def main():
     n = d["x"].size
     box = d["box"]
     cfg = dict(n_split=args.n_split, exec_mode=args.exec_mode, persistent_wgs=args.persistent_wgs,
-               prune=args.prune, use_graph=args.graph, rebuild_steps=args.rebuild_steps)
+               prune=args.prune, use_graph=args.graph, rebuild_steps=args.rebuild_steps,
+               h_drift=not args.no_h_drift)
     sim = S.SPH(box, precision=args.precision, **cfg)
     t = S.to_device(d)
     del d
@@ -393,6 +404,7 @@ def main():
         sim.close()
         t0 = time.perf_counter()
         cfg, tune_table = AT.autotune(box, t, args.precision, dt, cache=None, log=log)
+        cfg = dict(cfg, h_drift=not args.no_h_drift)
         log("autotune: %s (%.1f s)" % (cfg, time.perf_counter() - t0))
         sim = S.SPH(box, precision=args.precision, **cfg)
         sim.bind(t)
@@ -475,7 +487,7 @@ def main():
                                "h span %.0fx (0.1-99.9%%)" % (args.n_side, h_span),
                    "n_particles": n, "precision": prec, "exec": cfg["exec_mode"], "n_split": cfg["n_split"],
                    "persistent_wgs": cfg["persistent_wgs"], "prune": cfg["prune"], "graph": bool(cfg["use_graph"]),
-                   "rebuild_steps": cfg["rebuild_steps"],
+                   "rebuild_steps": cfg["rebuild_steps"], "h_drift": bool(cfg["h_drift"]),
                    "autotuned": bool(args.tune), "dt": dt},
         "builds": builds,
         "build_ms_per_step": sum(s["t_build_ms"] for s in per) / args.steps,
@@ -502,7 +514,8 @@ def main():
         sim.run()
     out["interpolation"] = interp_eval(sim, t, box)
     if not args.no_mlp:
-        out["h_predictor"] = mlp_eval(S, sim, t, dt, args.mlp_steps)
+        out["h_predictor"] = mlp_eval(S, sim, t, dt, args.mlp_steps,
+                                      lambda **kw: S.SPH(box, precision=args.precision, **dict(cfg, **kw)))
     sim.close()
     del t
     torch.cuda.empty_cache()

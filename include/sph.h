@@ -82,6 +82,13 @@ typedef struct {
                             every leaf's largest H plus twice the largest
                             displacement since the build stays inside its list
                             radius (rebuilding when not) */
+    int h_drift;         /* 1: sph_step starts each particle's H iteration from its
+                            previous H carried along the flow, H exp(-dt du/dt /
+                            (3 (gamma-1) u)) (d ln rho/dt = du/dt / ((gamma-1) u)
+                            for these equations; factor clamped to [1/2, 2]); 0:
+                            from the previous H.  Not applied while the learned
+                            predictor supplies the start.  Only the start changes:
+                            the converged H is set by the same FP64 test */
     const double* boxes; /* HOST pointer, n_domains x 3 box edge lengths; copied */
 } sph_params;
 

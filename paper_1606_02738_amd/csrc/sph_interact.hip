@@ -1326,6 +1326,21 @@ __global__ __launch_bounds__(256) void k_kick_drift(int64_t n, double* x, double
     }
 }
 
+// Start of the H iteration carried along the flow: with du/dt = (P/rho^2)
+// drho/dt (the energy equation of Sec. 2 against the density sum) and P =
+// (gamma-1) rho u, the fractional density change over dt is dt du/dt /
+// ((gamma-1) u); rho H^3 stays constant, so H scales by the cube root.
+__global__ __launch_bounds__(256) void k_h_drift(int64_t n, double* H, const double* __restrict__ u,
+                                                 const double* __restrict__ dudt, double gm1, double dt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double ui = u[i];
+    if (!(ui > 0.0)) return;
+    const double e = fmin(fmax(-dt * dudt[i] / (3.0 * gm1 * ui), -0.6931471805599453), 0.6931471805599453);
+    H[i] *= exp(e);
+}
+
 __global__ __launch_bounds__(256) void k_predict(int64_t n, const double* __restrict__ vx, const double* __restrict__ vy,
                                                  const double* __restrict__ vz, const double* __restrict__ u,
                                                  const double* __restrict__ ax, const double* __restrict__ ay,
@@ -2016,6 +2031,10 @@ sph_status step_all(sph_ctx* c, double dt)
     SPH_CHECK_LAUNCH();
     c->step_count++;
     SPH_TRY(mlp_pre_build(c, dt));
+    if (c->prm.h_drift && !(c->h_pred && c->mlp_ready)) {
+        k_h_drift<<<nb, 256, 0, c->stream>>>(c->n, c->P.H, c->P.u, c->P.dudt, c->prm.gamma - 1.0, dt);
+        SPH_CHECK_LAUNCH();
+    }
     double vmax = 0.0;
     SPH_CHECK_HIP(hipMemcpyAsync(&vmax, vmax_bits, 8, hipMemcpyDeviceToHost, c->stream));
     SPH_CHECK_HIP(hipStreamSynchronize(c->stream));

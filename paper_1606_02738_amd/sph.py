@@ -42,7 +42,7 @@ class Params(C.Structure):
                 ("h_tol", C.c_double), ("max_h_iter", C.c_int), ("n_split", C.c_int),
                 ("precision", C.c_int), ("exec_mode", C.c_int), ("n_domains", C.c_int),
                 ("persistent_wgs", C.c_int), ("use_graph", C.c_int), ("prune", C.c_int),
-                ("rebuild_steps", C.c_int),
+                ("rebuild_steps", C.c_int), ("h_drift", C.c_int),
                 ("boxes", C.POINTER(C.c_double))]
 
 
@@ -193,7 +193,7 @@ class SPH:
 
     def __init__(self, boxes, precision="fp32c", exec_mode="grid", gamma=5.0 / 3.0, eta=1.2348,
                  kernel_gamma=math.sqrt(10.0 / 3.0), h_tol=None, max_h_iter=40, n_split=64,
-                 persistent_wgs=0, prune="box", use_graph=False, rebuild_steps=0, stream=None):
+                 persistent_wgs=0, prune="box", use_graph=False, rebuild_steps=0, h_drift=True, stream=None):
         import torch
         self._torch = torch
         b = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(-1, 3))
@@ -209,6 +209,7 @@ class SPH:
         p.n_domains, p.persistent_wgs, p.use_graph = self.n_domains, persistent_wgs, int(bool(use_graph))
         p.prune = PRUNE_MODES[prune] if isinstance(prune, str) else int(prune)
         p.rebuild_steps = int(rebuild_steps)
+        p.h_drift = int(bool(h_drift))
         p.boxes = b.ctypes.data_as(C.POINTER(C.c_double))
         self.params = p
         s = stream if stream is not None else torch.cuda.current_stream()

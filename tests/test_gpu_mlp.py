@@ -163,13 +163,16 @@ def test_predictor_in_steps():
     """Record samples over plain steps, train with the library's kernels,
     then run the same steps from one state with and without the predictor:
     identical converged state within the convergence tolerance, fewer
-    particles left for a second sweep with the predictor."""
+    particles left for a second sweep with the predictor than with the
+    previous H as the start of the iteration (the method the predictor
+    replaces).  The start carried along the flow (h_drift) is run from the
+    same state as well and its fraction printed beside them."""
     import math
     import torch
     from paper_1606_02738_amd import sph as S
     log("case predictor clustered 40^3 fp32c")
     d = gen.clustered(40, n_halos=30, seed=2741)
-    sim = S.SPH(d["box"], precision="fp32c")
+    sim = S.SPH(d["box"], precision="fp32c", h_drift=False)
     t = S.to_device(d)
     sim.bind(t)
     sim.run()
@@ -189,28 +192,34 @@ def test_predictor_in_steps():
     n = t["x"].numel()
     state = _clone(t)
     res = {}
-    for mode in ("plain", "mlp"):
+    for mode in ("plain", "mlp", "drift"):
         for k in t:
             t[k].copy_(state[k])
-        sim.bind(t)
-        sim.build_cells()
-        sim.sort_cells()
-        sim.density()
-        sim.ghost()
-        sim.force()
-        sim.h_predict(mode == "mlp")
+        ss = S.SPH(d["box"], precision="fp32c", h_drift=True) if mode == "drift" else sim
+        ss.bind(t)
+        ss.build_cells()
+        ss.sort_cells()
+        ss.density()
+        ss.ghost()
+        ss.force()
+        if ss is sim:
+            sim.h_predict(mode == "mlp")
         fb, sw = [], []
         for _ in range(4):
-            sim.step(dt)
-            st = sim.stats()
+            ss.step(dt)
+            st = ss.stats()
             fb.append(st["unconv_after"][0] / n)
             sw.append(st["sweeps"])
         torch.cuda.synchronize()
         res[mode] = (S.to_host(t), np.mean(fb), np.mean(sw))
         log("%s: second-sweep fraction %.4g, mean sweeps %.2f" % (mode, res[mode][1], res[mode][2]))
+        if ss is not sim:
+            ss.close()
     sim.close()
-    a, b = res["plain"][0], res["mlp"][0]
-    # same physical state: H and rho agree to the FP32 convergence tolerance
-    assert np.max(np.abs(a["H"] - b["H"]) / a["H"]) < 1e-4
-    assert np.max(np.abs(a["rho"] - b["rho"]) / a["rho"]) < 3e-4
+    a = res["plain"][0]
+    for other in ("mlp", "drift"):
+        b = res[other][0]
+        # same physical state: H and rho agree to the FP32 convergence tolerance
+        assert np.max(np.abs(a["H"] - b["H"]) / a["H"]) < 1e-4
+        assert np.max(np.abs(a["rho"] - b["rho"]) / a["rho"]) < 3e-4
     assert res["mlp"][1] < res["plain"][1]
