@@ -341,6 +341,8 @@ def main():
                     help="run the configuration given by the flags instead of the autotuner's choice")
     ap.add_argument("--cpu-n-side", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--force", choices=("pairs", "gather"), default=None,
+                    help="force form (default: the autotuner's choice, else gather with box pruning)")
     ap.add_argument("--no-h-drift", action="store_true",
                     help="start the H iteration of a step from the previous H as is")
     ap.add_argument("--seed", type=int, default=2741)
@@ -380,7 +382,7 @@ def main():
     box = d["box"]
     cfg = dict(n_split=args.n_split, exec_mode=args.exec_mode, persistent_wgs=args.persistent_wgs,
                prune=args.prune, use_graph=args.graph, rebuild_steps=args.rebuild_steps,
-               h_drift=not args.no_h_drift)
+               h_drift=not args.no_h_drift, force=args.force or ("gather" if args.prune == "box" else "pairs"))
     sim = S.SPH(box, precision=args.precision, **cfg)
     t = S.to_device(d)
     del d
@@ -405,6 +407,8 @@ def main():
         t0 = time.perf_counter()
         cfg, tune_table = AT.autotune(box, t, args.precision, dt, cache=None, log=log)
         cfg = dict(cfg, h_drift=not args.no_h_drift)
+        if args.force:
+            cfg["force"] = args.force
         log("autotune: %s (%.1f s)" % (cfg, time.perf_counter() - t0))
         sim = S.SPH(box, precision=args.precision, **cfg)
         sim.bind(t)
@@ -488,6 +492,7 @@ def main():
                    "n_particles": n, "precision": prec, "exec": cfg["exec_mode"], "n_split": cfg["n_split"],
                    "persistent_wgs": cfg["persistent_wgs"], "prune": cfg["prune"], "graph": bool(cfg["use_graph"]),
                    "rebuild_steps": cfg["rebuild_steps"], "h_drift": bool(cfg["h_drift"]),
+                   "force": cfg["force"],
                    "autotuned": bool(args.tune), "dt": dt},
         "builds": builds,
         "build_ms_per_step": sum(s["t_build_ms"] for s in per) / args.steps,

@@ -55,6 +55,7 @@ typedef enum {
 enum { SPH_FP64 = 0, SPH_FP32C = 1, SPH_FP32 = 2 };      /* sph_params.precision */
 enum { SPH_EXEC_GRID = 0, SPH_EXEC_PERSISTENT = 1 };     /* sph_params.exec_mode */
 enum { SPH_PRUNE_BOX = 0, SPH_PRUNE_SORTED = 1 };        /* sph_params.prune */
+enum { SPH_FORCE_PAIRS = 0, SPH_FORCE_GATHER = 1 };      /* sph_params.force_mode */
 
 typedef struct {
     double gamma;        /* adiabatic index, 5/3 */
@@ -89,6 +90,12 @@ typedef struct {
                             from the previous H.  Not applied while the learned
                             predictor supplies the start.  Only the start changes:
                             the converged H is set by the same FP64 test */
+    int force_mode;      /* SPH_FORCE_PAIRS: each unordered pair of particles evaluated
+                            once and applied to both (Sec. 3.1 pair symmetry; atomic
+                            accumulation on the j side); SPH_FORCE_GATHER: each
+                            particle sums its own pairs r < max(H_i, H_j) (every pair
+                            evaluated from both sides, no atomics, symmetric
+                            neighbour-cell lists; box pruning only) */
     const double* boxes; /* HOST pointer, n_domains x 3 box edge lengths; copied */
 } sph_params;
 

@@ -5,9 +5,10 @@ configurations on the caller's particle set and returns the fastest.  The
 tunables are the leaf size (n_split: the tile of particles one wave holds),
 the execution form (one wave per leaf over a plain grid, or persistent
 workgroups draining a cost-ordered leaf queue, with the number of resident
-workgroups), the pair-pruning mode, hipGraph capture of the density, ghost
-and force stages, and how many steps the cells and lists are kept (the list
-skin).  Every candidate starts from the same saved state, so each is timed
+workgroups), the pair-pruning mode, the force form (each pair once with
+atomic j-side sums, or every particle gathering its own pairs), hipGraph
+capture of the density, ghost and force stages, and how many steps the
+cells and lists are kept (the list skin).  Every candidate starts from the same saved state, so each is timed
 on identical work; the particle tensors are restored afterwards.  Steps are
 averaged (not the median) so that the occasional rebuild of a candidate
 that keeps its lists is paid for.
@@ -41,27 +42,30 @@ def _key(t, n_domains, precision):
 def candidates(full=False):
     """Candidate configurations.  The default set is a coordinate sweep
     around the plain configuration; full=True is the whole product."""
-    base = dict(n_split=64, exec_mode="grid", persistent_wgs=0, prune="box", use_graph=False, rebuild_steps=0)
+    base = dict(n_split=64, exec_mode="grid", persistent_wgs=0, prune="box", use_graph=False, rebuild_steps=0,
+                force="gather")
     if full:
         out = []
         for ns in (32, 48, 64):
             for ex, wgs in (("grid", 0), ("persistent", 1024), ("persistent", 2048), ("persistent", 4096)):
-                for pr in ("box", "sorted"):
+                for pr, fo in (("box", "gather"), ("box", "pairs"), ("sorted", "pairs")):
                     for g in (False, True):
                         for rs in (0, 8):
                             out.append(dict(n_split=ns, exec_mode=ex, persistent_wgs=wgs, prune=pr, use_graph=g,
-                                            rebuild_steps=rs))
+                                            rebuild_steps=rs, force=fo))
         return out
     out = [dict(base)]
     for ns in (32, 40, 48, 56):
         out.append(dict(base, n_split=ns))
     for wgs in (1024, 2048, 4096):
         out.append(dict(base, exec_mode="persistent", persistent_wgs=wgs))
-    out.append(dict(base, prune="sorted"))
+    out.append(dict(base, force="pairs"))
+    out.append(dict(base, prune="sorted", force="pairs"))
     out.append(dict(base, use_graph=True))
     for rs in (4, 8, 16):
         out.append(dict(base, rebuild_steps=rs))
         out.append(dict(base, rebuild_steps=rs, use_graph=True))
+    out.append(dict(base, rebuild_steps=16, force="pairs"))
     return out
 
 

@@ -66,6 +66,8 @@ sph_status sph_create(const sph_params* params, void* hip_stream, sph_ctx** out)
     if (p.use_graph < 0 || p.use_graph > 1) return SPH_ERR_INVALID;
     if (p.rebuild_steps < 0 || p.rebuild_steps > 1000) return SPH_ERR_INVALID;
     if (p.h_drift != 0 && p.h_drift != 1) return SPH_ERR_INVALID;
+    if (p.force_mode != SPH_FORCE_PAIRS && p.force_mode != SPH_FORCE_GATHER) return SPH_ERR_INVALID;
+    if (p.force_mode == SPH_FORCE_GATHER && p.prune != SPH_PRUNE_BOX) return SPH_ERR_INVALID;
     for (int k = 0; k < 3 * p.n_domains; k++)
         if (!(p.boxes[k] > 0.0) || !isfinite(p.boxes[k])) return SPH_ERR_INVALID;
     sph_ctx* c = new (std::nothrow) sph_ctx();

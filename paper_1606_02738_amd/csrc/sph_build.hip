@@ -436,8 +436,12 @@ __global__ __launch_bounds__(256) void k_leaf_refresh(int n_leaves, const int* _
 // density sum of eq. (rho) over r < H_i needs.  The symmetric force range
 // r < max(H_i, H_j) of eq. (dvdt) is covered by the union of A's and B's
 // lists; each unordered pair of cells is evaluated once by a fixed owner
-// (see force_owner).  Found by descending the octree from the 27 top cells
-// around A's top cell, pruning cells whose box lies h_A or farther away.
+// (see force_owner).  With the gather-form force the lists are symmetric:
+// A's list also holds every B whose own radius h_B reaches A's box, so that
+// each particle finds all its pairs r < max(H_i, H_j) in its own cell's list.
+// Found by descending the octree from the 27 top cells around A's top cell,
+// pruning cells whose box lies farther away than h_A (and than the largest
+// list radius below them, for symmetric lists).
 // ---------------------------------------------------------------------------
 #define WALK_STACK 160
 
@@ -477,6 +481,8 @@ __global__ __launch_bounds__(256) void k_wnodes(const Node* __restrict__ nodes, 
     o.next = -1;
     o.count = nd.count;
     o.leaf = nd.leaf;
+    o.hl = 0.0f;  // set with the list radii (k_node_hmax)
+    o.pad = 0;
     w[k] = o;
 }
 
@@ -517,7 +523,7 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
                                               const int* __restrict__ l_dom, const int* __restrict__ l_top,
                                               const DomainInfo* __restrict__ di, const double* __restrict__ l_hlist,
                                               int* counts, const int* __restrict__ l_off, ListEntry* __restrict__ list,
-                                              int list_cap, int with_dir, int* flags)
+                                              int list_cap, int with_dir, int sym, int* flags)
 {
     const int A = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (A >= n_leaves) return;
@@ -527,7 +533,8 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
     const double hA = l_hlist[A];
     // conservative float pruning radius: the float boxes are rounded outward;
     // the absolute term covers the rounding of box + periodic shift in float
-    const float prune = (float)(hA * (1.0 + 1e-5) + 1e-6 * fmax(fmax(I.L[0], I.L[1]), I.L[2]));
+    const float slack = (float)(1e-6 * fmax(fmax(I.L[0], I.L[1]), I.L[2]));
+    const float prune = (float)(hA * (1.0 + 1e-5)) + slack;
     const WNode& WA = wn[leaf_node[A]];
     const double alo[3] = {l_lo[3 * A], l_lo[3 * A + 1], l_lo[3 * A + 2]};
     const double ahi[3] = {l_hi[3 * A], l_hi[3 * A + 1], l_hi[3 * A + 2]};
@@ -556,7 +563,9 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
         int k = I.top_offset + (nc[0] * I.n_top[1] + nc[1]) * I.n_top[2] + nc[2];
         while (k >= 0) {
             const WNode nd = wn[k];
-            if (nd.count == 0 || box_dist_f(WA.lo, WA.hi, nd.lo, nd.hi, svf) > prune) {
+            // symmetric lists also take every leaf whose own radius reaches A
+            if (nd.count == 0 ||
+                box_dist_f(WA.lo, WA.hi, nd.lo, nd.hi, svf) > (sym ? fmaxf(prune, nd.hl * 1.00001f + slack) : prune)) {
                 k = nd.next;
                 continue;
             }
@@ -577,7 +586,7 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
                     const double ms[3] = {-sv[0], -sv[1], -sv[2]};
                     d = box_dist(blo, bhi, alo, ahi, ms);
                 }
-                if (!(d < hA)) continue;
+                if (!(d < (sym ? fmax(hA, l_hlist[B]) : hA))) continue;
                 if (FILL) {
                     if (out < out_end && (MODE == 2 || out < list_cap)) {
                         int best = 0;
@@ -625,7 +634,7 @@ __global__ __launch_bounds__(256) void k_list_compact(int n_leaves, int cap, con
 // Largest H per cell, bottom-up over one level (leaves from particles,
 // internal cells from children).  One wave per cell.
 __global__ __launch_bounds__(256) void k_node_hmax(Node* nodes, int level_start, int n_level, const double* __restrict__ H,
-                                                   double* l_hlist, double skin_abs)
+                                                   double* l_hlist, double skin_abs, WNode* wn)
 {
     const int k = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (k >= n_level) return;
@@ -641,6 +650,8 @@ __global__ __launch_bounds__(256) void k_node_hmax(Node* nodes, int level_start,
     if (lane == 0) {
         nd.hmax = hm;
         if (nd.leaf >= 0 && l_hlist) l_hlist[nd.leaf] = hm * (1.0 + SPH_LIST_SKIN) + skin_abs;
+        // float bound of the subtree's list radii for the symmetric walk
+        if (wn) wn[level_start + k].hl = __double2float_ru((hm * (1.0 + SPH_LIST_SKIN) + skin_abs) * (1.0 + 1e-6));
     }
 }
 
@@ -826,7 +837,8 @@ sph_status node_hmax_all(sph_ctx* c, bool set_hlist)
         const int s = c->level_off[l], nl = c->level_off[l + 1] - s;
         if (nl <= 0) continue;
         k_node_hmax<<<blocks_for(nl, 4), 256, 0, c->stream>>>(
-            nodes, s, nl, c->P.H, set_hlist ? (double*)c->l_hlist.p : nullptr, c->skin_abs);
+            nodes, s, nl, c->P.H, set_hlist ? (double*)c->l_hlist.p : nullptr, c->skin_abs,
+            set_hlist ? (WNode*)c->wnodes.p : nullptr);
         SPH_CHECK_LAUNCH();
     }
     return SPH_OK;
@@ -840,6 +852,8 @@ sph_status relist(sph_ctx* c)
     int* flags = (int*)c->flags.p;
     SPH_CHECK_HIP(hipMemsetAsync(counts, 0, (size_t)(nL + 1) * sizeof(int), c->stream));
     const int with_dir = c->prm.prune == SPH_PRUNE_SORTED;
+    // the gather-form force needs every leaf within either radius in both lists
+    const int sym = c->prm.force_mode == SPH_FORCE_GATHER;
     // one pass into per-leaf slots of walk_cap entries, counting every entry
     const int cap = c->walk_cap;
     const bool one_pass = (size_t)nL * cap < ((size_t)1 << 31) - (size_t)cap;
@@ -849,12 +863,12 @@ sph_status relist(sph_ctx* c)
         k_walk<2><<<blocks_for(nL, 128), 128, 0, c->stream>>>(
             nL, (const int*)c->leaf_node.p, (const WNode*)c->wnodes.p, (const double*)c->l_lo.p,
             (const double*)c->l_hi.p, (const int*)c->l_dom.p, (const int*)c->l_cnt.p, (const DomainInfo*)c->dom_d.p,
-            (const double*)c->l_hlist.p, counts, nullptr, (ListEntry*)c->walk_scratch.p, cap, with_dir, flags);
+            (const double*)c->l_hlist.p, counts, nullptr, (ListEntry*)c->walk_scratch.p, cap, with_dir, sym, flags);
     } else {
         k_walk<0><<<blocks_for(nL, 128), 128, 0, c->stream>>>(
             nL, (const int*)c->leaf_node.p, (const WNode*)c->wnodes.p, (const double*)c->l_lo.p,
             (const double*)c->l_hi.p, (const int*)c->l_dom.p, (const int*)c->l_cnt.p, (const DomainInfo*)c->dom_d.p,
-            (const double*)c->l_hlist.p, counts, nullptr, nullptr, 0, with_dir, flags);
+            (const double*)c->l_hlist.p, counts, nullptr, nullptr, 0, with_dir, sym, flags);
     }
     SPH_CHECK_LAUNCH();
     SPH_TRY(scan_exclusive(c, counts, counts, nL + 1, flags + FI_NLIST));
@@ -879,7 +893,7 @@ sph_status relist(sph_ctx* c)
             nL, (const int*)c->leaf_node.p, (const WNode*)c->wnodes.p, (const double*)c->l_lo.p,
             (const double*)c->l_hi.p, (const int*)c->l_dom.p, (const int*)c->l_cnt.p, (const DomainInfo*)c->dom_d.p,
             (const double*)c->l_hlist.p, nullptr, (const int*)c->l_off.p, (ListEntry*)c->list.p, total, with_dir,
-            flags);
+            sym, flags);
     }
     SPH_CHECK_LAUNCH();
     c->n_list = total;

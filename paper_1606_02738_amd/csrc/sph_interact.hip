@@ -370,12 +370,13 @@ struct EBatchBox {
     int b[NE], n[NE];
     T ox[NE], oy[NE], oz[NE];
     T lo[3][NE], hi[3][NE];
+    T hl[NE];  // list radius of the cell (bounds its particles' H)
 };
 
 template <typename T, typename Keep, int NE>
 __device__ inline int load_batch_box(const ListEntry* list, int eb, int nbt, int lane, const int* l_begin,
                                      const int* l_count, const double* l_origin, const double* l_lo, const double* l_hi,
-                                     const double* oA, const DomainInfo& I, double grow, Keep keep,
+                                     const double* l_hlist, const double* oA, const DomainInfo& I, double grow, Keep keep,
                                      EBatchBox<T, NE>& E)
 {
     bool ok = false;
@@ -399,6 +400,7 @@ __device__ inline int load_batch_box(const ListEntry* list, int eb, int nbt, int
             E.lo[d][s] = (T)(l_lo[3 * B + d] + sv[d] - oA[d] - grow);
             E.hi[d][s] = (T)(l_hi[3 * B + d] + sv[d] - oA[d] + grow);
         }
+        E.hl[s] = (T)l_hlist[B];
     }
     wave_sync();
     return __popcll(mask);
@@ -508,7 +510,8 @@ __device__ void density_leaf_packed(const DensArgs& a, int A, PTile<T>& L, int l
     const double grow = 0.5 * mg + 1e-5 * fmax(hlA, hA);
     for (int eb = e0; eb < e1; eb += PD_ENTRIES) {
         const int nbt = min(PD_ENTRIES, e1 - eb);
-        const int nv = load_batch_box<T>(a.list, eb, nbt, lane, a.l_begin, a.l_count, a.l_origin, a.l_lo, a.l_hi, oA, I,
+        const int nv = load_batch_box<T>(a.list, eb, nbt, lane, a.l_begin, a.l_count, a.l_origin, a.l_lo, a.l_hi,
+                                         a.l_hlist, oA, I,
                                          grow, [&](const ListEntry& E) { return E.dist < hA + mg; }, L.e);
         V4 pf;  // prefetched first chunk of the next cell
         if (nv > 0 && lane < L.e.n[0]) pf = pos4[L.e.b[0] + lane];
@@ -841,6 +844,8 @@ struct ForceArgs {
     const int* l_count;
     const double* l_origin;
     const double* l_hlist;
+    const double* l_lo;
+    const double* l_hi;
     const int* l_dom;
     const int* l_off;
     const ListEntry* list;
@@ -1283,6 +1288,258 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPH_FORCE_W
 }
 
 // ---------------------------------------------------------------------------
+// Gather-form force: each particle of leaf A sums its own pairs r < max(H_i,
+// H_j) of eqs. (dvdt) and (dudt) over the cells of A's symmetric list.  Every
+// pair is evaluated from both sides (twice the pair arithmetic of the
+// pairs-once form) but nothing is accumulated on the j side, so there are no
+// atomics and each output is written once.  Same packing as the density:
+// candidates of all cells that pass the box test are packed 64 per tile;
+// phase 1 j-major (lane = candidate, one ballot per particle of A reaching
+// the tile), phase 2 i-major over the set bits.
+// ---------------------------------------------------------------------------
+#define FG_ENTRIES 32
+
+template <typename T>
+struct GTile {
+    typename vec4<T>::type cp[128];   // j in A's frame: x, y, z, m
+    typename vec4<T>::type cv[128];   // vx, vy, vz, k_j = A_j (8/pi) / H_j^4
+    typename vec2t<T>::type ch[128];  // H_j^2, 1/H_j
+    typename vec4<T>::type si[64];    // i of A: x, y, z (A frame), H_i^2 (negative: no particle)
+    EBatchBox<T, FG_ENTRIES> e;
+};
+
+template <typename T, bool COMP>
+__device__ void force_leaf_gather(const ForceArgs& a, int A, GTile<T>& L, int lane)
+{
+    typedef typename vec4<T>::type V4;
+    typedef typename vec2t<T>::type V2;
+    const V4* pos4 = (const V4*)a.pos4;
+    const V4* fv4 = (const V4*)a.fv4;
+    const T* hf = (const T*)a.hf;
+    const int bA = a.l_begin[A], nA = a.l_count[A];
+    const double oA[3] = {a.l_origin[3 * A], a.l_origin[3 * A + 1], a.l_origin[3 * A + 2]};
+    const DomainInfo& I = a.di[a.l_dom[A]];
+    const int e0 = a.l_off[A], e1 = a.l_off[A + 1];
+    const double mg = *a.margin;  // list margin (see density_leaf)
+    const T big = T(1e30);
+    unsigned long long npairs = 0, ndens_w = 0;
+    for (int c0 = 0; c0 < nA; c0 += 64) {
+        const int nc = min(64, nA - c0);
+        const bool vi = lane < nc;
+        const int i = bA + c0 + (vi ? lane : 0);
+        const unsigned long long vmask = __ballot(vi);
+        const V4 pi = pos4[i];
+        const V4 fi = fv4[i];
+        const T Hi = hf[i];
+        const T h2i = Hi * Hi, ihi = T(1) / Hi;
+        const T ki = fi.w * T(INV_PI_8) * ihi * ihi * ihi * ihi;
+        FAcc<T, COMP> ai;
+        int nni = 0, nmax = 0;  // pairs within H_i and within max(H_i, H_j), self included
+        const double hA = wave_max(vi ? (double)Hi : 0.0);
+        const T hAm = (T)(hA * (1.0 + 1e-5));
+        const T bxl = wave_min_t<T>(vi ? pi.x : big), bxh = wave_max_t<T>(vi ? pi.x : -big);
+        const T byl = wave_min_t<T>(vi ? pi.y : big), byh = wave_max_t<T>(vi ? pi.y : -big);
+        const T bzl = wave_min_t<T>(vi ? pi.z : big), bzh = wave_max_t<T>(vi ? pi.z : -big);
+        wave_sync();
+        {
+            V4 q = pi;
+            q.w = vi ? h2i : T(-1);
+            L.si[lane] = q;
+        }
+        // box of the buffered candidates (union of their cells' boxes) and
+        // the largest list radius of those cells (bounds their H)
+        T tlo[3] = {big, big, big}, thi[3] = {-big, -big, -big};
+        T thl = T(0);
+        auto run_tile = [&](int len) {
+            wave_sync();
+            const V4 pj = L.cp[lane];
+            const V2 hj = L.ch[lane];
+            const bool lv = lane < len;
+            const T R = fmax(Hi, thl) * T(1.00001);
+            const unsigned long long imask =
+                vmask & __ballot(box_d2<T>(pi.x, pi.y, pi.z, tlo[0], tlo[1], tlo[2], thi[0], thi[1], thi[2]) < R * R);
+            int mlo = 0, mhi = 0;
+            for (unsigned long long m = imask; m; m &= m - 1ull) {
+                const int ii = uniform(__ffsll((long long)m) - 1);
+                const V4 q = L.si[ii];
+                const T dx = pj.x - q.x, dy = pj.y - q.y, dz = pj.z - q.z;
+                const unsigned long long hm = __ballot(lv && dx * dx + dy * dy + dz * dz < fmax(q.w, hj.x));
+                mlo = amdgcn_writelane((int)(uint32_t)hm, ii, mlo);
+                mhi = amdgcn_writelane((int)(uint32_t)(hm >> 32), ii, mhi);
+            }
+            if (vi) {
+                unsigned long long m = ((unsigned long long)(uint32_t)mhi << 32) | (uint32_t)mlo;
+                while (m) {
+                    const int sl = __ffsll((long long)m) - 1;
+                    m &= m - 1ull;
+                    const V4 q = L.cp[sl];
+                    const V4 fj = L.cv[sl];
+                    const V2 hh = L.ch[sl];
+                    const T dx = pi.x - q.x, dy = pi.y - q.y, dz = pi.z - q.z;
+                    const T r2 = dx * dx + dy * dy + dz * dz;
+                    nmax++;
+                    if (r2 < h2i) nni++;
+                    if (r2 > T(0)) {  // the particle itself and coincident ones exert no force
+                        const T ir = fast_rsqrt(r2);
+                        const T r = r2 * ir;
+                        const T Fi = ki * spline_dw(r * ihi);    // A_i dW/dr(r, H_i)
+                        const T Fj = fj.w * spline_dw(r * hh.y);  // A_j dW/dr(r, H_j)
+                        const T F = (Fi + Fj) * ir;
+                        const T dvdr = ((fi.x - fj.x) * dx + (fi.y - fj.y) * dy + (fi.z - fj.z) * dz) * ir;
+                        const T mjF = q.w * F;
+                        ai.ax.add(-mjF * dx);
+                        ai.ay.add(-mjF * dy);
+                        ai.az.add(-mjF * dz);
+                        ai.du.add(q.w * Fi * dvdr);
+                    }
+                }
+            }
+            wave_sync();
+        };
+        int ncand = 0;
+        // cell boxes grow by the displacement since the build plus float rounding
+        const double grow = 0.5 * mg + 1e-5 * hA;
+        for (int eb = e0; eb < e1; eb += FG_ENTRIES) {
+            const int nbt = min(FG_ENTRIES, e1 - eb);
+            const double* hl = a.l_hlist;
+            const int nv = load_batch_box<T>(a.list, eb, nbt, lane, a.l_begin, a.l_count, a.l_origin, a.l_lo, a.l_hi,
+                                             hl, oA, I, grow,
+                                             [&](const ListEntry& E) { return E.dist < fmax(hA + mg, hl[E.B]); }, L.e);
+            // prefetched first chunk (positions, H) of the next cell
+            V4 pf;
+            T hp = T(1);
+            if (nv > 0 && lane < L.e.n[0]) {
+                const int p = L.e.b[0] + lane;
+                pf = pos4[p];
+                hp = hf[p];
+            }
+            for (int k = 0; k < nv; k++) {
+                const int bB = L.e.b[k], nB = L.e.n[k];
+                const T dox = L.e.ox[k], doy = L.e.oy[k], doz = L.e.oz[k];
+                const V4 cq = pf;
+                const T ch_ = hp;
+                if (k + 1 < nv && lane < L.e.n[k + 1]) {
+                    const int p = L.e.b[k + 1] + lane;
+                    pf = pos4[p];
+                    hp = hf[p];
+                }
+                for (int p0 = 0; p0 < nB; p0 += 64) {
+                    const int len = min(64, nB - p0);
+                    bool in = false;
+                    V4 q;
+                    T h = T(1);
+                    if (lane < len) {
+                        if (p0 == 0) {
+                            q = cq;
+                            h = ch_;
+                        } else {
+                            q = pos4[bB + p0 + lane];
+                            h = hf[bB + p0 + lane];
+                        }
+                        q.x += dox;
+                        q.y += doy;
+                        q.z += doz;
+                        const T Rj = fmax(hAm, h * T(1.00001));
+                        in = box_d2<T>(q.x, q.y, q.z, bxl, byl, bzl, bxh, byh, bzh) < Rj * Rj;
+                    }
+                    const unsigned long long mk = __ballot(in);
+                    if (in) {
+                        const V4 f = fv4[bB + p0 + lane];
+                        const int slot = ncand + mask_rank(mk, lane);
+                        const T ih = fast_rcp(h);
+                        V4 g = f;
+                        g.w = f.w * T(INV_PI_8) * ih * ih * ih * ih;
+                        V2 hh;
+                        hh.x = h * h;
+                        hh.y = ih;
+                        L.cp[slot] = q;
+                        L.cv[slot] = g;
+                        L.ch[slot] = hh;
+                    }
+                    ncand += __popcll(mk);
+                    if (mk) {
+                        for (int d = 0; d < 3; d++) {
+                            tlo[d] = fmin(tlo[d], L.e.lo[d][k]);
+                            thi[d] = fmax(thi[d], L.e.hi[d][k]);
+                        }
+                        thl = fmax(thl, L.e.hl[k]);
+                    }
+                    if (ncand >= 64) {
+                        run_tile(64);
+                        const int rest = ncand - 64;
+                        V4 t0, t1;
+                        V2 t2;
+                        if (lane < rest) {
+                            t0 = L.cp[64 + lane];
+                            t1 = L.cv[64 + lane];
+                            t2 = L.ch[64 + lane];
+                        }
+                        wave_sync();
+                        if (lane < rest) {
+                            L.cp[lane] = t0;
+                            L.cv[lane] = t1;
+                            L.ch[lane] = t2;
+                        }
+                        ncand = rest;
+                        // the carried candidates all come from this cell
+                        for (int d = 0; d < 3; d++) {
+                            tlo[d] = rest ? L.e.lo[d][k] : big;
+                            thi[d] = rest ? L.e.hi[d][k] : -big;
+                        }
+                        thl = rest ? L.e.hl[k] : T(0);
+                    }
+                }
+            }
+            wave_sync();
+        }
+        if (ncand > 0) run_tile(ncand);
+        if (vi) {
+            a.ax[i] = ai.ax.total();
+            a.ay[i] = ai.ay.total();
+            a.az[i] = ai.az.total();
+            a.dudt[i] = ai.du.total();
+            if (a.nngb) a.nngb[i] = nni;
+            npairs += (unsigned long long)max(nmax - 1, 0);  // ordered pairs, the particle itself excluded
+            ndens_w += (unsigned long long)nni;
+        }
+        wave_sync();
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        npairs += __shfl_xor(npairs, off);
+        ndens_w += __shfl_xor(ndens_w, off);
+    }
+    if (lane == 0 && npairs) atomicAdd(&a.counters[CNT_NFORCE], npairs);
+    if (lane == 0 && ndens_w) atomicAdd(&a.counters[CNT_NDENS_F], ndens_w);
+}
+
+#ifndef SPH_FORCEG_WAVES
+#define SPH_FORCEG_WAVES 5
+#endif
+
+template <typename T, bool COMP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPH_FORCEG_WAVES, 8))) void k_force_gather(
+    ForceArgs a)
+{
+    __shared__ GTile<T> tiles[WAVES_PER_WG];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (a.gate && uniform(*a.gate) != 1) return;
+    const int nL = a.nl_dev ? uniform(*a.nl_dev) : a.n_leaves;
+    if (!a.persistent) {
+        const int A = uniform(xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_WG + w);
+        if (A >= nL) return;
+        force_leaf_gather<T, COMP>(a, A, tiles[w], lane);
+        return;
+    }
+    for (int it = 0; it <= nL; it++) {
+        const int t = wave_pop(&a.counters[CNT_QUEUE2], lane);
+        if (t >= nL) break;
+        const int A = uniform(a.order ? a.order[t] : t);
+        if (A < 0 || A >= nL) break;
+        force_leaf_gather<T, COMP>(a, A, tiles[w], lane);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Integrator (kick-drift-kick) and FP64 conservation sums.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_kick_drift(int64_t n, double* x, double* y, double* z, double* vx, double* vy,
@@ -1689,6 +1946,8 @@ static void force_args(sph_ctx* c, const int* gate, bool graph, ForceArgs& a, in
     a.l_count = (const int*)c->l_count.p;
     a.l_origin = (const double*)c->l_origin.p;
     a.l_hlist = (const double*)c->l_hlist.p;
+    a.l_lo = (const double*)c->l_lo.p;
+    a.l_hi = (const double*)c->l_hi.p;
     a.l_dom = (const int*)c->l_dom.p;
     a.l_off = (const int*)c->l_off.p;
     a.list = (const ListEntry*)c->list.p;
@@ -1720,7 +1979,12 @@ static sph_status launch_force(sph_ctx* c, const int* gate, bool graph = false)
     ForceArgs a;
     int nb = 0;
     force_args(c, gate, graph, a, nb);
-    if (nb > 0) {
+    if (nb > 0 && c->prm.force_mode == SPH_FORCE_GATHER) {
+        if (c->prm.precision == SPH_FP64) k_force_gather<double, false><<<nb, 256, 0, c->stream>>>(a);
+        else if (c->prm.precision == SPH_FP32C) k_force_gather<float, true><<<nb, 256, 0, c->stream>>>(a);
+        else k_force_gather<float, false><<<nb, 256, 0, c->stream>>>(a);
+        SPH_CHECK_LAUNCH();
+    } else if (nb > 0) {
         const bool srt = c->prm.prune == SPH_PRUNE_SORTED;
         if (c->prm.precision == SPH_FP64) {
             if (srt) k_force<double, false, PRUNE_SORTED><<<nb, 256, 0, c->stream>>>(a);
@@ -1764,7 +2028,8 @@ sph_status force_all(sph_ctx* c)
         SPH_CHECK_HIP(hipEventElapsedTime(&ms, c->kev[2], c->kev[3]));
         c->st.t_force_kernel_ms = ms;
     }
-    c->st.n_force = (int64_t)nf;
+    // the gather form counts every pair from both sides
+    c->st.n_force = (int64_t)(c->prm.force_mode == SPH_FORCE_GATHER ? nf / 2 : nf);
     c->st.n_dens = (int64_t)ndf;  // exact at the final H
     c->force_done = true;
     return SPH_OK;
@@ -1967,7 +2232,7 @@ sph_status dgf_graph(sph_ctx* c)
     if (gate == 1) {
         c->st.sweeps = gsweeps;
         c->st.n_unconverged = 0;
-        c->st.n_force = (int64_t)hc[CNT_NFORCE];
+        c->st.n_force = (int64_t)(c->prm.force_mode == SPH_FORCE_GATHER ? hc[CNT_NFORCE] / 2 : hc[CNT_NFORCE]);
         c->st.n_dens = (int64_t)hc[CNT_NDENS_F];
         c->dens_done = c->ghost_done = c->force_done = true;
         // the whole graph is accounted as the density stage

@@ -56,6 +56,8 @@ struct WNode {
     int next;         // node after this subtree in depth-first order (-1: end of the top cell)
     int count;
     int leaf;
+    float hl;         // upper bound of the list radii of the leaves below (symmetric lists)
+    int pad;
 };
 
 // Neighbour-cell list entry of leaf A: leaf B, periodic image and the

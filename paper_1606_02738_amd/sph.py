@@ -22,6 +22,8 @@ PRECISIONS = {"fp64": SPH_FP64, "fp32c": SPH_FP32C, "fp32": SPH_FP32}
 EXEC_MODES = {"grid": SPH_EXEC_GRID, "persistent": SPH_EXEC_PERSISTENT}
 SPH_PRUNE_BOX, SPH_PRUNE_SORTED = 0, 1
 PRUNE_MODES = {"box": SPH_PRUNE_BOX, "sorted": SPH_PRUNE_SORTED}
+SPH_FORCE_PAIRS, SPH_FORCE_GATHER = 0, 1
+FORCE_MODES = {"pairs": SPH_FORCE_PAIRS, "gather": SPH_FORCE_GATHER}
 
 STATUS = {0: "SPH_OK", -1: "SPH_ERR_INVALID", -2: "SPH_ERR_HIP", -3: "SPH_ERR_NOT_CONVERGED",
           -4: "SPH_ERR_H_EXCEEDS_CELL", -5: "SPH_ERR_BOX_TOO_SMALL", -6: "SPH_ERR_ALLOC",
@@ -42,7 +44,7 @@ class Params(C.Structure):
                 ("h_tol", C.c_double), ("max_h_iter", C.c_int), ("n_split", C.c_int),
                 ("precision", C.c_int), ("exec_mode", C.c_int), ("n_domains", C.c_int),
                 ("persistent_wgs", C.c_int), ("use_graph", C.c_int), ("prune", C.c_int),
-                ("rebuild_steps", C.c_int), ("h_drift", C.c_int),
+                ("rebuild_steps", C.c_int), ("h_drift", C.c_int), ("force_mode", C.c_int),
                 ("boxes", C.POINTER(C.c_double))]
 
 
@@ -193,7 +195,7 @@ class SPH:
 
     def __init__(self, boxes, precision="fp32c", exec_mode="grid", gamma=5.0 / 3.0, eta=1.2348,
                  kernel_gamma=math.sqrt(10.0 / 3.0), h_tol=None, max_h_iter=40, n_split=64,
-                 persistent_wgs=0, prune="box", use_graph=False, rebuild_steps=0, h_drift=True, stream=None):
+                 persistent_wgs=0, prune="box", use_graph=False, rebuild_steps=0, h_drift=True, force=None, stream=None):
         import torch
         self._torch = torch
         b = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(-1, 3))
@@ -210,6 +212,9 @@ class SPH:
         p.prune = PRUNE_MODES[prune] if isinstance(prune, str) else int(prune)
         p.rebuild_steps = int(rebuild_steps)
         p.h_drift = int(bool(h_drift))
+        if force is None:  # the gather form where it is available (box pruning)
+            force = "gather" if p.prune == SPH_PRUNE_BOX else "pairs"
+        p.force_mode = FORCE_MODES[force] if isinstance(force, str) else int(force)
         p.boxes = b.ctypes.data_as(C.POINTER(C.c_double))
         self.params = p
         s = stream if stream is not None else torch.cuda.current_stream()

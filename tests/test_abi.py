@@ -57,7 +57,8 @@ def _params(**kw):
 
 @pytest.mark.parametrize("bad", [dict(gamma=1.0), dict(eta=0.0), dict(h_tol=0.0), dict(max_h_iter=0),
                                  dict(n_split=0), dict(n_split=65), dict(precision=7),
-                                 dict(exec_mode=3), dict(n_domains=0), dict(prune=2), dict(use_graph=2), dict(rebuild_steps=-1)])
+                                 dict(exec_mode=3), dict(n_domains=0), dict(prune=2), dict(use_graph=2), dict(rebuild_steps=-1),
+                                 dict(h_drift=2), dict(force_mode=2), dict(force_mode=1, prune=1)])
 def test_create_rejects_bad_params(L, bad):
     p, box = _params(**bad)
     h = C.c_void_p()

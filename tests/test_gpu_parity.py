@@ -68,6 +68,57 @@ def test_clustered_small(prec, mode, prune):
         assert_close(g, o, TOL_FP32, counts_exact=False)
 
 
+@pytest.mark.parametrize("prec,mode,case", [
+    ("fp64", "grid", "clustered"), ("fp32c", "grid", "clustered"), ("fp32", "grid", "clustered"),
+    ("fp32c", "persistent", "clustered"), ("fp64", "persistent", "lattice"), ("fp32c", "grid", "lattice"),
+    ("fp64", "grid", "ensemble"), ("fp32c", "grid", "ensemble")])
+def test_gather_force(prec, mode, case):
+    """The gather-form force (each particle sums its own pairs over symmetric
+    lists) against the oracle, with exact pair and neighbour counts in FP64."""
+    log("case gather force %s %s %s" % (case, prec, mode))
+    if case == "clustered":
+        d = gen.clustered(32, n_halos=20, seed=2741)
+    elif case == "lattice":
+        d = gen.lattice(32, vsigma=0.1, seed=2739)
+    else:
+        d = gen.ensemble(4, (12, 16), seed=11)
+    g, st = gpu_run(d, precision=prec, exec_mode=mode, force="gather")
+    o = oracle_run(d)
+    assert st["n_unconverged"] == 0
+    if prec == "fp64":
+        assert_close(g, o, TOL_FP64, stats=st)
+    else:
+        assert_close(g, o, TOL_FP32, counts_exact=False)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_gather_force_unsplittable_cell(prec):
+    """Gather force with a leaf of more than a wave (chunks of 64 particles
+    of A, each over the whole list)."""
+    log("case gather force unsplittable cell %s" % prec)
+    d = gen.lattice(16, vsigma=0.1, seed=21)
+    rng = np.random.default_rng(4)
+    k = 150
+    c = rng.uniform(-5e-8, 5e-8, (k, 3)) + 0.5
+    for a, key in enumerate(("x", "y", "z")):
+        d[key] = np.concatenate([d[key], c[:, a]])
+    for key in ("vx", "vy", "vz"):
+        d[key] = np.concatenate([d[key], rng.normal(0, 0.1, k)])
+    d["u"] = np.concatenate([d["u"], np.ones(k)])
+    d["m"] = np.concatenate([d["m"], np.full(k, d["m"][0])])
+    d["H"] = np.concatenate([d["H"], np.full(k, 1e-6)])
+    n = d["x"].size
+    d["id"] = np.arange(n, dtype=np.int64)
+    d["domain"] = np.zeros(n, dtype=np.int32)
+    g, st = gpu_run(d, precision=prec, force="gather")
+    assert st["n_unconverged"] == 0
+    o = oracle_run(d)
+    if prec == "fp64":
+        assert_close(g, o, TOL_FP64, stats=st)
+    else:
+        assert_close(g, o, TOL_FP32, counts_exact=False)
+
+
 @pytest.mark.parametrize("n_split", [8, 32])
 def test_small_leaves(n_split):
     log("case lattice16 n_split=%d" % n_split)
