@@ -33,6 +33,10 @@ sys.path.insert(0, ROOT)
 # accumulation.  Only pairs inside the range are counted.
 FLOPS_DENS = {"fp32c": 39, "fp32": 31, "fp64": 23}
 FLOPS_FORCE = {"fp32c": 64, "fp32": 52, "fp64": 52}
+# gather-form force: per ordered pair (each unordered pair is evaluated from
+# both sides), distance, both kernel gradients, the particle's own
+# acceleration and du/dt only
+FLOPS_FORCE_GATHER = {"fp32c": 59, "fp32": 47, "fp64": 47}
 # MI355X vector ALU peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x
 # 2 flop (FMA) x 2.4 GHz; FP64 vector runs at the same rate.
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
@@ -455,11 +459,15 @@ def main():
     force_ms = sum(s["t_force_kernel_ms"] for s in kper)
     prec = args.precision
     dens_flops = sum(s["n_dens_evals"] for s in kper) * FLOPS_DENS[prec]
-    force_flops = sum(s["n_force"] for s in kper) * FLOPS_FORCE[prec]
+    if cfg["force"] == "gather":
+        force_flops = sum(2 * s["n_force"] for s in kper) * FLOPS_FORCE_GATHER[prec]
+    else:
+        force_flops = sum(s["n_force"] for s in kper) * FLOPS_FORCE[prec]
     if dens_ms >= force_ms:
         kname, kflops, kms, klaunch = "k_density", dens_flops, dens_ms, dens_launch
     else:
-        kname, kflops, kms, klaunch = "k_force", force_flops, force_ms, len(kper)
+        kname = "k_force_gather" if cfg["force"] == "gather" else "k_force"
+        kflops, kms, klaunch = force_flops, force_ms, len(kper)
     achieved = kflops / (kms / 1e3) / 1e12
     traffic = measured_traffic(kname, "clustered%d_%s" % (args.n_side, prec), cfg)
     roof = {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
@@ -468,7 +476,7 @@ def main():
             "flop_per_launch": kflops / max(1, klaunch)}
     other = {"k_density": {"ms_total": dens_ms, "launches": dens_launch,
                            "tflops": dens_flops / max(dens_ms, 1e-9) / 1e9},
-             "k_force": {"ms_total": force_ms, "launches": len(kper),
+             ("k_force_gather" if cfg["force"] == "gather" else "k_force"): {"ms_total": force_ms, "launches": len(kper),
                          "tflops": force_flops / max(force_ms, 1e-9) / 1e9},
              "timed_without_graph": bool(cfg["use_graph"])}
 
