@@ -50,7 +50,7 @@ def candidates(full=False):
             for ex, wgs in (("grid", 0), ("persistent", 1024), ("persistent", 2048), ("persistent", 4096)):
                 for pr, fo in (("box", "gather"), ("box", "pairs"), ("sorted", "pairs")):
                     for g in (False, True):
-                        for rs in (0, 8):
+                        for rs in (0, 8, 32):
                             out.append(dict(n_split=ns, exec_mode=ex, persistent_wgs=wgs, prune=pr, use_graph=g,
                                             rebuild_steps=rs, force=fo))
         return out
@@ -62,14 +62,21 @@ def candidates(full=False):
     out.append(dict(base, force="pairs"))
     out.append(dict(base, prune="sorted", force="pairs"))
     out.append(dict(base, use_graph=True))
-    for rs in (4, 8, 16):
+    for rs in (4, 8, 16, 32, 64):
         out.append(dict(base, rebuild_steps=rs))
         out.append(dict(base, rebuild_steps=rs, use_graph=True))
-    out.append(dict(base, rebuild_steps=16, force="pairs"))
+    out.append(dict(base, rebuild_steps=32, force="pairs"))
     return out
 
 
 def _time_config(boxes, t, state, cfg, precision, dt, steps, warmup):
+    """Mean ms per step.  A candidate that keeps its cells and lists for
+    many steps may rebuild rarely or never inside the few timed steps, so
+    its builds are amortised: the timed steps without their builds, plus the
+    mean build time over the interval between builds (seen in the timed
+    steps when there are two or more, else half the candidate's
+    rebuild_steps: the displacement margin, twice the displacement since
+    the build, uses up the skin of rebuild_steps displacements by then)."""
     import torch
     for k in t:
         t[k].copy_(state[k])
@@ -77,14 +84,31 @@ def _time_config(boxes, t, state, cfg, precision, dt, steps, warmup):
     try:
         sim.bind(t)
         sim.run()
+        cold_build_ms = sim.stats()["t_build_ms"]
         for _ in range(warmup):
             sim.step(dt)
         torch.cuda.synchronize()
+        nb = sim.stats()["n_builds"]
+        per = []
         t0 = time.perf_counter()
         for _ in range(steps):
             sim.step(dt)
+            per.append(sim.stats())
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps * 1e3
+        wall_ms = (time.perf_counter() - t0) * 1e3
+        rs = cfg.get("rebuild_steps", 0)
+        if rs == 0:
+            return wall_ms / steps
+        built = []
+        for k, st in enumerate(per):
+            if st["n_builds"] > nb:
+                built.append(k)
+            nb = st["n_builds"]
+        build_ms = [per[k]["t_build_ms"] for k in built]
+        rest = (wall_ms - sum(build_ms)) / steps
+        mean_build = sum(build_ms) / len(build_ms) if build_ms else cold_build_ms
+        interval = (built[-1] - built[0]) / (len(built) - 1) if len(built) >= 2 else max(1.0, rs / 2.0)
+        return rest + mean_build / interval
     finally:
         sim.close()
 
