@@ -8,7 +8,7 @@ The predictor replaces the warm start of the smoothing-length iteration of
 the density loop (paper, section 2, the constraint between density and
 smoothing length solved per particle by Newton-Raphson): after the drift of
 a step it guesses the converged H of every particle; the plain iteration then
-runs from that guess and stays the judge of convergence.
+runs from that guess and alone decides convergence.
 
 Contents, all plain numpy in float64:
 
