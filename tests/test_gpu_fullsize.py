@@ -60,3 +60,45 @@ def test_clustered_256_sampled():
         assert abs(np.sum(m * g[k])) < 1e-6 * S_a
     pw = m * (g["vx"] * g["ax"] + g["vy"] * g["ay"] + g["vz"] * g["az"])
     assert abs(np.sum(pw) + np.sum(m * g["dudt"])) < 1e-4 * np.sum(np.abs(pw))
+
+
+def test_clustered_256_lazy_steps_properties():
+    """The benchmark's stepping configuration at full size (cells and lists
+    kept up to 64 steps, H started along the flow, gather force): three
+    steps agree with the same steps rebuilding every step (to the FP32
+    convergence tolerance), and the step's outputs keep the properties that
+    hold at any size (zero momentum sum of the forces)."""
+    import math
+    from paper_1606_02738_amd import sph as S
+    log("case clustered 256^3 fp32c three lazy steps: generating")
+    d = gen.clustered(256, seed=2742)
+    res = {}
+    for rs in (64, 0):
+        sim = S.SPH(d["box"], precision="fp32c", exec_mode="grid", prune="box", rebuild_steps=rs)
+        t = S.to_device(d)
+        sim.bind(t)
+        sim.run()
+        cs = math.sqrt(5.0 / 3.0 * (2.0 / 3.0) * float(t["u"].max()))
+        dt = 0.25 * float(t["H"].min()) / math.sqrt(10.0 / 3.0) / cs
+        for _ in range(3):
+            sim.step(dt)
+        torch.cuda.synchronize()
+        st = sim.stats()
+        res[rs] = (S.to_host(t), st)
+        sim.close()
+        del t
+        log("rebuild_steps=%d: builds %d, sweeps %d, n_force %d" % (rs, st["n_builds"], st["sweeps"], st["n_force"]))
+    a, b = res[64][0], res[0][0]
+    assert res[64][1]["n_builds"] < res[0][1]["n_builds"]
+    L = d["box"][0]
+    for k in ("x", "y", "z"):
+        dx = a[k] - b[k]
+        dx -= L * np.round(dx / L)
+        assert np.max(np.abs(dx)) < 1e-6 * L, k
+    for k in ("rho", "H"):
+        assert np.max(np.abs(a[k] - b[k]) / b[k]) < 1e-4, k
+    m = a["m"]
+    S_a = np.sum(m * np.sqrt(a["ax"] ** 2 + a["ay"] ** 2 + a["az"] ** 2))
+    for k in ("ax", "ay", "az"):
+        assert abs(np.sum(m * a[k])) < 1e-6 * S_a, k
+        assert np.max(np.abs(a[k] - b[k])) <= 1e-3 * np.max(np.abs(b[k])), k
