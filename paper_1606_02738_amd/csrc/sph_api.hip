@@ -106,7 +106,7 @@ sph_status sph_destroy(sph_ctx* c)
                      &c->nchild, &c->coff, &c->leafmark, &c->leafscan, &c->leaf_node, &c->l_begin, &c->l_count,
                      &c->l_origin, &c->l_lo, &c->l_hi, &c->l_hlist, &c->l_dom, &c->l_off, &c->l_active, &c->l_sorted,
                      &c->l_cnt, &c->l_cost, &c->l_order, &c->list, &c->pos4, &c->fv4, &c->hf, &c->skey, &c->sidx,
-                     &c->hlo, &c->hhi, &c->conv, &c->vpx, &c->vpy, &c->vpz, &c->upr, &c->flags, &c->counters,
+                     &c->hlo, &c->hhi, &c->conv, &c->flags, &c->counters,
                      &c->scan_tmp, &c->rs_hist, &c->sums, &c->dsum_part, &c->fgrid, &c->fcount, &c->mlp_X, &c->mlp_hprev, &c->mlp_params, &c->mlp_packed, &c->mlp_m, &c->mlp_v, &c->ds_X, &c->ds_y, &c->ds_count, &c->dparam, &c->walk_scratch};
     for (DevBuf* b : all) buf_free(*b);
     for (int k = 0; k < 8; k++)

@@ -388,7 +388,11 @@ __global__ __launch_bounds__(256) void k_leaf_pos(int n_leaves, const int* __res
 // Refresh of the cell-relative coordinates after a drift without a rebuild:
 // the nearest periodic image of each particle relative to its leaf's
 // origin, and the test that the leaf's largest H plus the displacement
-// margin still lies inside the radius its list was built for.
+// margin still lies inside the radius its list was built for.  In the FP32
+// modes (ext_ratio > 0) a leaf that could still be split and whose extent
+// plus the motion exceeds ext_ratio times its smallest H also asks for a
+// rebuild (the extent rule of the build, with the hysteresis of the check
+// after a density call).
 template <typename T>
 __global__ __launch_bounds__(256) void k_leaf_refresh(int n_leaves, const int* __restrict__ l_begin,
                                                       const int* __restrict__ l_count, const double* __restrict__ l_origin,
@@ -397,7 +401,9 @@ __global__ __launch_bounds__(256) void k_leaf_refresh(int n_leaves, const int* _
                                                       const double* __restrict__ y, const double* __restrict__ z,
                                                       const double* __restrict__ m, const double* __restrict__ H,
                                                       const double* __restrict__ margin, typename vec4<T>::type* pos4,
-                                                      T* hf, int* flags)
+                                                      T* hf, int* flags, const double* __restrict__ l_lo,
+                                                      const double* __restrict__ l_hi, const int* __restrict__ leaf_node,
+                                                      const Node* __restrict__ nodes, int max_level, double ext_ratio)
 {
     const int A = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6));
     if (A >= n_leaves) return;
@@ -405,7 +411,7 @@ __global__ __launch_bounds__(256) void k_leaf_refresh(int n_leaves, const int* _
     const int b = l_begin[A], c = l_count[A];
     const double o[3] = {l_origin[3 * A], l_origin[3 * A + 1], l_origin[3 * A + 2]};
     const DomainInfo& I = di[l_dom[A]];
-    double hm = 0.0;
+    double hm = 0.0, hn = INFINITY;
     for (int p = b + lane; p < b + c; p += 64) {
         const double q[3] = {x[p], y[p], z[p]};
         T r[3];
@@ -424,9 +430,19 @@ __global__ __launch_bounds__(256) void k_leaf_refresh(int n_leaves, const int* _
         const double h = H[p];
         hf[p] = (T)h;
         hm = fmax(hm, h);
+        hn = fmin(hn, h);
     }
-    for (int off = 32; off > 0; off >>= 1) hm = fmax(hm, __shfl_xor(hm, off));
-    if (lane == 0 && !(hm + *margin < l_hlist[A])) atomicOr(flags, FLAG_STALE);
+    for (int off = 32; off > 0; off >>= 1) {
+        hm = fmax(hm, __shfl_xor(hm, off));
+        hn = fmin(hn, __shfl_xor(hn, off));
+    }
+    bool stale = !(hm + *margin < l_hlist[A]);
+    if (ext_ratio > 0.0 && c >= 2 && nodes[leaf_node[A]].level < max_level) {
+        const double ext = fmax(fmax(l_hi[3 * A] - l_lo[3 * A], l_hi[3 * A + 1] - l_lo[3 * A + 1]),
+                                l_hi[3 * A + 2] - l_lo[3 * A + 2]) + *margin;
+        stale = stale || ext > ext_ratio * hn;
+    }
+    if (lane == 0 && stale) atomicOr(flags, FLAG_STALE);
 }
 
 // ---------------------------------------------------------------------------
@@ -1148,12 +1164,16 @@ sph_status refresh_leaves(sph_ctx* c, bool* fresh)
         k_leaf_refresh<double><<<blocks_for(nL, 4), 256, 0, c->stream>>>(
             nL, (const int*)c->l_begin.p, (const int*)c->l_count.p, (const double*)c->l_origin.p,
             (const double*)c->l_hlist.p, (const int*)c->l_dom.p, (const DomainInfo*)c->dom_d.p, c->P.x, c->P.y, c->P.z,
-            c->P.m, c->P.H, (const double*)c->dparam.p, (double4*)c->pos4.p, (double*)c->hf.p, flags);
+            c->P.m, c->P.H, (const double*)c->dparam.p, (double4*)c->pos4.p, (double*)c->hf.p, flags,
+            (const double*)c->l_lo.p, (const double*)c->l_hi.p, (const int*)c->leaf_node.p, (const Node*)c->nodes.p,
+            c->D, 0.0);
     else
         k_leaf_refresh<float><<<blocks_for(nL, 4), 256, 0, c->stream>>>(
             nL, (const int*)c->l_begin.p, (const int*)c->l_count.p, (const double*)c->l_origin.p,
             (const double*)c->l_hlist.p, (const int*)c->l_dom.p, (const DomainInfo*)c->dom_d.p, c->P.x, c->P.y, c->P.z,
-            c->P.m, c->P.H, (const double*)c->dparam.p, (float4*)c->pos4.p, (float*)c->hf.p, flags);
+            c->P.m, c->P.H, (const double*)c->dparam.p, (float4*)c->pos4.p, (float*)c->hf.p, flags,
+            (const double*)c->l_lo.p, (const double*)c->l_hi.p, (const int*)c->leaf_node.p, (const Node*)c->nodes.p,
+            c->D, 2.0 * SPH_FP32_EXTENT_RATIO);
     SPH_CHECK_LAUNCH();
     int fl = 0;
     SPH_TRY(read_int(c, flags, &fl));

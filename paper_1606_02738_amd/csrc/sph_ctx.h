@@ -36,7 +36,10 @@ struct sph_ctx {
 
     // stage state
     bool built = false, sorted = false, dens_done = false, ghost_done = false, force_done = false;
+    bool in_step = false;  // inside sph_step (the refresh of the next step checks the FP32 extent rule)
     bool predicted = false;      // ghost/force use the predicted v, u of a step
+    double hdt_h = 0.0;          // half the step in progress (the prediction's interval)
+    double hdt_up = 0.0;         // source of the upload of the prediction's half step
 
     // counters of the last calls
     sph_stats st{};
@@ -60,7 +63,6 @@ struct sph_ctx {
     DevBuf pos4, fv4, hf;         // kernel-side particle data (T = float or double)
     DevBuf skey, sidx;            // per-direction sorted projections
     DevBuf hlo, hhi, conv;        // Newton brackets and converged flags
-    DevBuf vpx, vpy, vpz, upr;    // predicted v, u of a step
     DevBuf flags, counters;       // device flags (int[64], see FI_*) and counters (int64)
     DevBuf scan_tmp;              // scan block sums
     DevBuf rs_hist;               // radix-sort digit histograms
@@ -74,7 +76,8 @@ struct sph_ctx {
     hipEvent_t kev[4] = {};     // per-launch kernel timing
 
     // lazy rebuild: displacement since the build and the list skin
-    DevBuf dparam;                      // double[8]: [0] list margin (2 x displacement), [1] max speed (bits)
+    DevBuf dparam;                      // double[8]: [0] list margin (2 x displacement), [1] max speed (bits),
+                                        // [2] half step of the ghost's prediction (0: none)
     double delta = 0.0;                 // largest displacement bound since the build
     double skin_abs = 0.0;              // absolute list skin of the last build
     double margin_h = 0.0;              // host copy of dparam[0] (source of its uploads)

@@ -809,21 +809,34 @@ __global__ __launch_bounds__(256) void k_ghost(int64_t n, const double* __restri
                                                const double* __restrict__ H, const double* __restrict__ u,
                                                const double* __restrict__ vx, const double* __restrict__ vy,
                                                const double* __restrict__ vz, double gamma, double* omega, double* P,
-                                               typename vec4<T>::type* fv4, T* hf, const int* gate)
+                                               typename vec4<T>::type* fv4, T* hf, const int* gate,
+                                               const double* __restrict__ ax, const double* __restrict__ ay,
+                                               const double* __restrict__ az, const double* __restrict__ dudt,
+                                               const double* __restrict__ hdt)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (gate && *gate != 1) return;
+    // inside a step the ghost and force use v and u predicted to the end of
+    // the step with the forces of its start: x + a dt/2 (hdt = dt/2; 0 outside)
+    const double hd = *hdt;
+    double ui = u[i], v0 = vx[i], v1 = vy[i], v2 = vz[i];
+    if (hd != 0.0) {
+        ui += dudt[i] * hd;
+        v0 += ax[i] * hd;
+        v1 += ay[i] * hd;
+        v2 += az[i] * hd;
+    }
     const double r = rho[i], h = H[i];
     const double om = 1.0 + h / (3.0 * r) * drho[i];
-    const double p = (gamma - 1.0) * r * u[i];
+    const double p = (gamma - 1.0) * r * ui;
     const double A = p / (om * r * r);
     if (omega) omega[i] = om;
     if (P) P[i] = p;
     typename vec4<T>::type f;
-    f.x = (T)vx[i];
-    f.y = (T)vy[i];
-    f.z = (T)vz[i];
+    f.x = (T)v0;
+    f.y = (T)v1;
+    f.z = (T)v2;
     f.w = (T)A;
     fv4[i] = f;
     hf[i] = (T)h;
@@ -1547,7 +1560,7 @@ __global__ __launch_bounds__(256) void k_kick_drift(int64_t n, double* x, double
                                                     const double* __restrict__ ay, const double* __restrict__ az,
                                                     const double* __restrict__ dudt, const int32_t* __restrict__ dom,
                                                     const DomainInfo* __restrict__ di, double dt,
-                                                    unsigned long long* vmax_bits)
+                                                    unsigned long long* vmax_bits, double* H, double gm1)
 {
     __shared__ double wmax[4];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1558,7 +1571,14 @@ __global__ __launch_bounds__(256) void k_kick_drift(int64_t n, double* x, double
         vx[i] = v[0];
         vy[i] = v[1];
         vz[i] = v[2];
-        u[i] += dudt[i] * h;
+        const double du = dudt[i];
+        const double ui = u[i] + du * h;
+        u[i] = ui;
+        if (H && ui > 0.0) {
+            // start of the H iteration carried along the flow (see k_h_drift)
+            const double e = fmin(fmax(-dt * du / (3.0 * gm1 * ui), -0.6931471805599453), 0.6931471805599453);
+            H[i] *= exp(e);
+        }
         sp = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
         const DomainInfo& I = di[dom ? dom[i] : 0];
         double* c[3] = {x, y, z};
@@ -1598,46 +1618,31 @@ __global__ __launch_bounds__(256) void k_h_drift(int64_t n, double* H, const dou
     H[i] *= exp(e);
 }
 
-__global__ __launch_bounds__(256) void k_predict(int64_t n, const double* __restrict__ vx, const double* __restrict__ vy,
-                                                 const double* __restrict__ vz, const double* __restrict__ u,
-                                                 const double* __restrict__ ax, const double* __restrict__ ay,
-                                                 const double* __restrict__ az, const double* __restrict__ dudt,
-                                                 double dt, double* vpx, double* vpy, double* vpz, double* upr)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double h = 0.5 * dt;
-    vpx[i] = vx[i] + ax[i] * h;
-    vpy[i] = vy[i] + ay[i] * h;
-    vpz[i] = vz[i] + az[i] * h;
-    upr[i] = u[i] + dudt[i] * h;
-}
-
-__global__ __launch_bounds__(256) void k_kick(int64_t n, double* vx, double* vy, double* vz, double* u,
-                                              const double* __restrict__ ax, const double* __restrict__ ay,
-                                              const double* __restrict__ az, const double* __restrict__ dudt, double dt)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double h = 0.5 * dt;
-    vx[i] += ax[i] * h;
-    vy[i] += ay[i] * h;
-    vz[i] += az[i] * h;
-    u[i] += dudt[i] * h;
-}
+struct KickArgs {
+    const double *ax, *ay, *az, *dudt;
+    double h;  // half the step
+};
 
 // partial[(d * chunks + chunk) * 5 + k]; chunks per box is chosen so that
 // the grid holds about 4096 workgroups (at least 64 per box)
+// With kick != nullptr the closing half kick of the step is applied first
+// (v += a dt/2, u += du/dt dt/2 with kick = {ax, ay, az, dudt}) and the
+// totals are those of the kicked state.
 __global__ __launch_bounds__(256) void k_sums_partial(const int* __restrict__ ranges, const double* __restrict__ m,
-                                                      const double* __restrict__ vx, const double* __restrict__ vy,
-                                                      const double* __restrict__ vz, const double* __restrict__ u,
-                                                      double* partial, int chunks)
+                                                      double* vx, double* vy, double* vz, double* u,
+                                                      double* partial, int chunks, KickArgs kick)
 {
     __shared__ double red[5][256];
     const int d = blockIdx.y, ch = blockIdx.x, tid = threadIdx.x;
     const int b = ranges[d], e = ranges[d + 1];
     double s[5] = {0, 0, 0, 0, 0};
     for (int64_t i = b + (int64_t)ch * 256 + tid; i < e; i += (int64_t)chunks * 256) {
+        if (kick.ax) {
+            vx[i] += kick.ax[i] * kick.h;
+            vy[i] += kick.ay[i] * kick.h;
+            vz[i] += kick.az[i] * kick.h;
+            u[i] += kick.dudt[i] * kick.h;
+        }
         const double mm = m[i], v0 = vx[i], v1 = vy[i], v2 = vz[i];
         s[0] += mm;
         s[1] += mm * v0;
@@ -1838,8 +1843,10 @@ static sph_status density_loop(sph_ctx* c, int done_sweeps, unsigned long long u
         unconv = hc[CNT_UNCONV];
         if (sweeps <= 8) c->st.unconv_after[sweeps - 1] = (int)std::min<unsigned long long>(unconv, INT32_MAX);
         if (fl & FLAG_BOX_SMALL) status = SPH_ERR_BOX_TOO_SMALL;
+        // (inside sph_step the refresh of the next step takes this test
+        // over: the lists are rebuilt then if the rule fails)
         if (unconv == 0 && c->prm.precision != SPH_FP64 && !prec_rebuilt && status == SPH_OK &&
-            sweeps < c->prm.max_h_iter) {
+            sweeps < c->prm.max_h_iter && !c->in_step) {
             SPH_CHECK_HIP(hipMemsetAsync(flags, 0, sizeof(int), c->stream));
             k_extent_check<<<blocks_for(c->n_leaves, 4), 256, 0, c->stream>>>(
                 c->n_leaves, (const int*)c->l_begin.p, (const int*)c->l_count.p, (const double*)c->l_lo.p,
@@ -1910,26 +1917,34 @@ sph_status density_all(sph_ctx* c)
 static sph_status launch_ghost(sph_ctx* c, const double* u, const double* vx, const double* vy, const double* vz,
                                const int* gate)
 {
+    const double* hdt = (const double*)c->dparam.p + 2;
     if (c->prm.precision == SPH_FP64)
-        k_ghost<double><<<blocks_for(c->n, 256), 256, 0, c->stream>>>(c->n, c->P.rho, c->P.drho_dH, c->P.H, u, vx, vy,
-                                                                     vz, c->prm.gamma, c->P.omega, c->P.P,
-                                                                     (double4*)c->fv4.p, (double*)c->hf.p, gate);
+        k_ghost<double><<<blocks_for(c->n, 256), 256, 0, c->stream>>>(
+            c->n, c->P.rho, c->P.drho_dH, c->P.H, u, vx, vy, vz, c->prm.gamma, c->P.omega, c->P.P, (double4*)c->fv4.p,
+            (double*)c->hf.p, gate, c->P.ax, c->P.ay, c->P.az, c->P.dudt, hdt);
     else
-        k_ghost<float><<<blocks_for(c->n, 256), 256, 0, c->stream>>>(c->n, c->P.rho, c->P.drho_dH, c->P.H, u, vx, vy,
-                                                                    vz, c->prm.gamma, c->P.omega, c->P.P,
-                                                                    (float4*)c->fv4.p, (float*)c->hf.p, gate);
+        k_ghost<float><<<blocks_for(c->n, 256), 256, 0, c->stream>>>(
+            c->n, c->P.rho, c->P.drho_dH, c->P.H, u, vx, vy, vz, c->prm.gamma, c->P.omega, c->P.P, (float4*)c->fv4.p,
+            (float*)c->hf.p, gate, c->P.ax, c->P.ay, c->P.az, c->P.dudt, hdt);
     SPH_CHECK_LAUNCH();
+    return SPH_OK;
+}
+
+// Half step of the velocity and energy prediction the ghost applies (a step
+// in progress) or 0, uploaded to the device slot the ghost reads.
+static sph_status set_prediction(sph_ctx* c)
+{
+    c->hdt_up = c->predicted ? c->hdt_h : 0.0;
+    SPH_CHECK_HIP(hipMemcpyAsync((double*)c->dparam.p + 2, &c->hdt_up, sizeof(double), hipMemcpyHostToDevice,
+                                 c->stream));
     return SPH_OK;
 }
 
 sph_status ghost_all(sph_ctx* c)
 {
     if (!c->dens_done) return SPH_ERR_STATE;
-    const bool pr = c->predicted;
-    const double* u = pr ? (const double*)c->upr.p : c->P.u;
-    const double* vx = pr ? (const double*)c->vpx.p : c->P.vx;
-    const double* vy = pr ? (const double*)c->vpy.p : c->P.vy;
-    const double* vz = pr ? (const double*)c->vpz.p : c->P.vz;
+    const double *u = c->P.u, *vx = c->P.vx, *vy = c->P.vy, *vz = c->P.vz;
+    SPH_TRY(set_prediction(c));
     SPH_CHECK_HIP(hipEventRecord(c->ev[2], c->stream));
     SPH_TRY(launch_ghost(c, u, vx, vy, vz, nullptr));
     SPH_CHECK_HIP(hipEventRecord(c->ev[3], c->stream));
@@ -2195,11 +2210,8 @@ static sph_status capture_dgf(sph_ctx* c, const double* u, const double* vx, con
 sph_status dgf_graph(sph_ctx* c)
 {
     if (!c->sorted) return SPH_ERR_STATE;
-    const bool pr = c->predicted;
-    const double* u = pr ? (const double*)c->upr.p : c->P.u;
-    const double* vx = pr ? (const double*)c->vpx.p : c->P.vx;
-    const double* vy = pr ? (const double*)c->vpy.p : c->P.vy;
-    const double* vz = pr ? (const double*)c->vpz.p : c->P.vz;
+    const double *u = c->P.u, *vx = c->P.vx, *vy = c->P.vy, *vz = c->P.vz;
+    SPH_TRY(set_prediction(c));
     SPH_TRY(buf_ensure(c->hlo, (size_t)c->n * 8));
     SPH_TRY(buf_ensure(c->hhi, (size_t)c->n * 8));
     SPH_TRY(buf_ensure(c->conv, (size_t)c->n));
@@ -2263,7 +2275,7 @@ sph_status dgf_graph(sph_ctx* c)
     return force_all(c);
 }
 
-sph_status domain_sums(sph_ctx* c, double* host_out)
+static sph_status sums_impl(sph_ctx* c, double* host_out, KickArgs kick)
 {
     const int nd = c->prm.n_domains;
     // one 256-thread workgroup per chunk of a box; at most one chunk per 1024
@@ -2275,7 +2287,7 @@ sph_status domain_sums(sph_ctx* c, double* host_out)
     double* part = (double*)c->dsum_part.p;
     double* out = part + (size_t)nd * chunks * 5;
     dim3 g(chunks, nd);
-    k_sums_partial<<<g, 256, 0, c->stream>>>(ranges, c->P.m, c->P.vx, c->P.vy, c->P.vz, c->P.u, part, chunks);
+    k_sums_partial<<<g, 256, 0, c->stream>>>(ranges, c->P.m, c->P.vx, c->P.vy, c->P.vz, c->P.u, part, chunks, kick);
     SPH_CHECK_LAUNCH();
     k_sums_final<<<nd, 256, 0, c->stream>>>(part, out, chunks);
     SPH_CHECK_LAUNCH();
@@ -2284,19 +2296,30 @@ sph_status domain_sums(sph_ctx* c, double* host_out)
     return SPH_OK;
 }
 
+sph_status domain_sums(sph_ctx* c, double* host_out)
+{
+    KickArgs none{};
+    return sums_impl(c, host_out, none);
+}
+
 sph_status step_all(sph_ctx* c, double dt)
 {
     if (!c->force_done) return SPH_ERR_STATE;
     const int nb = blocks_for(c->n, 256);
     unsigned long long* vmax_bits = (unsigned long long*)c->dparam.p + 1;
     SPH_CHECK_HIP(hipMemsetAsync(vmax_bits, 0, 8, c->stream));
+    // the start of the H iteration is carried along the flow unless the
+    // predictor supplies it; fused into the kick-drift unless the predictor
+    // records samples (its features read the H before the drift)
+    const bool drift = c->prm.h_drift && !(c->h_pred && c->mlp_ready);
+    const bool fuse = drift && !c->rec_on;
     k_kick_drift<<<nb, 256, 0, c->stream>>>(c->n, c->P.x, c->P.y, c->P.z, c->P.vx, c->P.vy, c->P.vz, c->P.u, c->P.ax,
                                             c->P.ay, c->P.az, c->P.dudt, c->P.domain, (const DomainInfo*)c->dom_d.p,
-                                            dt, vmax_bits);
+                                            dt, vmax_bits, fuse ? c->P.H : nullptr, c->prm.gamma - 1.0);
     SPH_CHECK_LAUNCH();
     c->step_count++;
     SPH_TRY(mlp_pre_build(c, dt));
-    if (c->prm.h_drift && !(c->h_pred && c->mlp_ready)) {
+    if (drift && !fuse) {
         k_h_drift<<<nb, 256, 0, c->stream>>>(c->n, c->P.H, c->P.u, c->P.dudt, c->prm.gamma - 1.0, dt);
         SPH_CHECK_LAUNCH();
     }
@@ -2321,17 +2344,10 @@ sph_status step_all(sph_ctx* c, double dt)
     }
     SPH_TRY(sort_all(c));
     SPH_CHECK_HIP(hipEventRecord(c->ev[7], c->stream));
-    const size_t nb8 = (size_t)c->n * 8;
-    SPH_TRY(buf_ensure(c->vpx, nb8));
-    SPH_TRY(buf_ensure(c->vpy, nb8));
-    SPH_TRY(buf_ensure(c->vpz, nb8));
-    SPH_TRY(buf_ensure(c->upr, nb8));
-    k_predict<<<nb, 256, 0, c->stream>>>(c->n, c->P.vx, c->P.vy, c->P.vz, c->P.u, c->P.ax, c->P.ay, c->P.az, c->P.dudt,
-                                         dt, (double*)c->vpx.p, (double*)c->vpy.p, (double*)c->vpz.p,
-                                         (double*)c->upr.p);
-    SPH_CHECK_LAUNCH();
     sph_status s;
+    c->hdt_h = 0.5 * dt;
     c->predicted = true;
+    c->in_step = true;
     if (c->prm.use_graph) {
         s = dgf_graph(c);
     } else {
@@ -2340,12 +2356,13 @@ sph_status step_all(sph_ctx* c, double dt)
         if (s == SPH_OK) s = force_all(c);
     }
     c->predicted = false;
+    c->in_step = false;
     if (s != SPH_OK) return s;
     SPH_TRY(mlp_post_step(c));
-    k_kick<<<nb, 256, 0, c->stream>>>(c->n, c->P.vx, c->P.vy, c->P.vz, c->P.u, c->P.ax, c->P.ay, c->P.az, c->P.dudt, dt);
-    SPH_CHECK_LAUNCH();
+    // closing half kick, fused with the FP64 totals of the kicked state
     std::vector<double> sums((size_t)c->prm.n_domains * 5);
-    SPH_TRY(domain_sums(c, sums.data()));
+    KickArgs kick{c->P.ax, c->P.ay, c->P.az, c->P.dudt, 0.5 * dt};
+    SPH_TRY(sums_impl(c, sums.data(), kick));
     for (int k = 0; k < 5; k++) {
         double t = 0.0;
         for (int d = 0; d < c->prm.n_domains; d++) t += sums[5 * d + k];
