@@ -245,6 +245,34 @@ def precision_eval(S, box, t, dt, cfg, steps=5):
     return res
 
 
+def rebuild_every_step_eval(S, box, t, dt, cfg, prec, steps=10):
+    """The same state and launch configuration with the cells and lists
+    rebuilt at every step (rebuild_steps = 0): the step time without the
+    amortisation of keeping them."""
+    import torch
+    state = {k: v.clone() for k, v in t.items()}
+    sim = S.SPH(box, precision=prec, **dict(cfg, rebuild_steps=0))
+    sim.bind(t)
+    sim.run()
+    sim.step(dt)
+    torch.cuda.synchronize()
+    per = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sim.step(dt)
+        per.append(sim.stats())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.close()
+    for k in t:
+        t[k].copy_(state[k])
+    inter = sum(q["n_dens"] + 2 * q["n_force"] for q in per)
+    out = {"ms_per_step": wall / steps * 1e3, "interactions_per_s": inter / wall, "steps": steps,
+           "build_ms_per_step": sum(q["t_build_ms"] for q in per) / steps}
+    log("rebuild every step: %.2f ms/step" % out["ms_per_step"])
+    return out
+
+
 def ensemble_eval(S, prec, steps=3, seed=2743, rebuild_steps=0):
     """64 independent periodic boxes (n_side ~ U{16..96}): every stage of a
     step as one launch over all boxes, against 64 contexts stepped one after
@@ -521,6 +549,7 @@ def main():
         out["autotune"] = [dict(c, ms_per_step=ms) for c, ms in tune_table]
     if not args.no_forms:
         sim.close()
+        out["rebuild_every_step"] = rebuild_every_step_eval(S, box, t, dt, cfg, prec)
         out["precision_forms"] = precision_eval(S, box, t, dt, cfg)
         sim = S.SPH(box, precision=args.precision, **cfg)
         sim.bind(t)
