@@ -1392,19 +1392,20 @@ __device__ void force_leaf_gather(const ForceArgs& a, int A, GTile<T>& L, int la
                     const T r2 = dx * dx + dy * dy + dz * dz;
                     nmax++;
                     if (r2 < h2i) nni++;
-                    if (r2 > T(0)) {  // the particle itself and coincident ones exert no force
-                        const T ir = fast_rsqrt(r2);
-                        const T r = r2 * ir;
-                        const T Fi = ki * spline_dw(r * ihi);    // A_i dW/dr(r, H_i)
-                        const T Fj = fj.w * spline_dw(r * hh.y);  // A_j dW/dr(r, H_j)
-                        const T F = (Fi + Fj) * ir;
-                        const T dvdr = ((fi.x - fj.x) * dx + (fi.y - fj.y) * dy + (fi.z - fj.z) * dz) * ir;
-                        const T mjF = q.w * F;
-                        ai.ax.add(-mjF * dx);
-                        ai.ay.add(-mjF * dy);
-                        ai.az.add(-mjF * dz);
-                        ai.du.add(q.w * Fi * dvdr);
-                    }
+                    // the particle itself and coincident ones exert no force:
+                    // at r2 = 0 the clamp gives r = 0, dW/dr(0) = 0 and d = 0,
+                    // so every term below is an exact zero (no branch)
+                    const T ir = fast_rsqrt(fmax(r2, T(1e-30)));
+                    const T r = r2 * ir;
+                    const T Fi = ki * spline_dw(r * ihi);    // A_i dW/dr(r, H_i)
+                    const T Fj = fj.w * spline_dw(r * hh.y);  // A_j dW/dr(r, H_j)
+                    const T F = (Fi + Fj) * ir;
+                    const T dvdr = ((fi.x - fj.x) * dx + (fi.y - fj.y) * dy + (fi.z - fj.z) * dz) * ir;
+                    const T mjF = q.w * F;
+                    ai.ax.add(-mjF * dx);
+                    ai.ay.add(-mjF * dy);
+                    ai.az.add(-mjF * dz);
+                    ai.du.add(q.w * Fi * dvdr);
                 }
             }
             wave_sync();
