@@ -96,21 +96,29 @@ def _time_config(boxes, t, state, cfg, precision, dt, steps, warmup):
             per.append(sim.stats())
         torch.cuda.synchronize()
         wall_ms = (time.perf_counter() - t0) * 1e3
-        rs = cfg.get("rebuild_steps", 0)
-        if rs == 0:
-            return wall_ms / steps
-        built = []
-        for k, st in enumerate(per):
-            if st["n_builds"] > nb:
-                built.append(k)
-            nb = st["n_builds"]
-        build_ms = [per[k]["t_build_ms"] for k in built]
-        rest = (wall_ms - sum(build_ms)) / steps
-        mean_build = sum(build_ms) / len(build_ms) if build_ms else cold_build_ms
-        interval = (built[-1] - built[0]) / (len(built) - 1) if len(built) >= 2 else max(1.0, rs / 2.0)
-        return rest + mean_build / interval
+        return amortised_ms(wall_ms, per, nb, cold_build_ms, cfg.get("rebuild_steps", 0))
     finally:
         sim.close()
+
+
+def amortised_ms(wall_ms, per, n_builds0, cold_build_ms, rebuild_steps):
+    """Mean ms per step of `len(per)` timed steps (per: each step's stats,
+    n_builds0: the build count before them) with the builds amortised over
+    their interval (see _time_config)."""
+    steps = len(per)
+    if rebuild_steps == 0:
+        return wall_ms / steps
+    built = []
+    nb = n_builds0
+    for k, st in enumerate(per):
+        if st["n_builds"] > nb:
+            built.append(k)
+        nb = st["n_builds"]
+    build_ms = [per[k]["t_build_ms"] for k in built]
+    rest = (wall_ms - sum(build_ms)) / steps
+    mean_build = sum(build_ms) / len(build_ms) if build_ms else cold_build_ms
+    interval = (built[-1] - built[0]) / (len(built) - 1) if len(built) >= 2 else max(1.0, rebuild_steps / 2.0)
+    return rest + mean_build / interval
 
 
 def autotune(boxes, t, precision, dt, steps=8, warmup=1, cands=None, cache=DEFAULT_CACHE, log=None, refresh=False):
