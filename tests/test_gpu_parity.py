@@ -187,6 +187,20 @@ def test_errors_and_state():
         sim.build_cells()
     assert ei.value.status == -5
     sim.close()
+    # an empty particle set is rejected before any GPU work
+    d = gen.lattice(8, seed=1)
+    e = gen.subset(d, np.arange(0))
+    e["id"] = np.zeros(0, dtype=np.int64)
+    e["domain"] = np.zeros(0, dtype=np.int32)
+    sim = S.SPH(d["box"], precision="fp32c")
+    sim.bind(S.to_device(e))
+    with pytest.raises(S.SPHError) as ei:
+        sim.build_cells()
+    assert ei.value.status == -1
+    with pytest.raises(S.SPHError) as ei:
+        sim.step(1e-3)
+    assert ei.value.status == -7
+    sim.close()
     torch.cuda.synchronize()
 
 
