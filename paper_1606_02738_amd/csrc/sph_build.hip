@@ -21,9 +21,14 @@ __device__ inline void flush_hrange(unsigned long long* dstat, int d, double hmx
     atomicMin(&dstat[2 * d + 1], (unsigned long long)__double_as_longlong(hmn));
 }
 
-// Grid-stride: each thread keeps the H range of its current box and flushes
-// it when the box changes; at the end a wave whose lanes share one box
-// reduces across lanes first (one atomic pair per wave).
+// Each workgroup takes one contiguous range of particles (coalesced within
+// it); each thread keeps the H range of its current box and flushes it when
+// the box changes, which happens only where a range crosses from one box
+// to the next when the particles are grouped by box (the generators' order
+// and the Morton order after a build); at the end a wave whose lanes share
+// one box reduces across lanes first (one atomic pair per wave).  (A
+// grid-stride loop would change box at almost every step for many boxes
+// and serialise on the per-box atomics.)
 __global__ __launch_bounds__(256) void k_validate(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
                                                   const double* __restrict__ z, const double* __restrict__ H,
                                                   const double* __restrict__ m, const int32_t* __restrict__ dom,
@@ -33,7 +38,9 @@ __global__ __launch_bounds__(256) void k_validate(int64_t n, const double* __res
     int dcur = -1;
     double hmx = 0.0, hmn = INFINITY;
     bool bad = false;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t b0 = (int64_t)blockIdx.x * per, b1 = min(n, b0 + per);
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
         const int d = dom ? dom[i] : 0;
         if (d < 0 || d >= ndom) {
             bad = true;
