@@ -82,7 +82,7 @@ sph_status sph_create(const sph_params* params, void* hip_stream, sph_ctx** out)
     if (s == SPH_OK) s = buf_ensure(c->dparam, 8 * sizeof(double));
     if (s == SPH_OK && hipMemsetAsync(c->dparam.p, 0, 8 * sizeof(double), c->stream) != hipSuccess) s = SPH_ERR_HIP;
     if (s == SPH_OK) s = buf_ensure(c->dom_d, (size_t)p.n_domains * sizeof(DomainInfo));
-    if (s == SPH_OK) s = buf_ensure(c->dstat, (size_t)p.n_domains * 16);
+    if (s == SPH_OK) s = buf_ensure(c->dstat, (size_t)p.n_domains * 24);
     for (int k = 0; k < 8 && s == SPH_OK; k++)
         if (hipEventCreate(&c->ev[k]) != hipSuccess) s = SPH_ERR_HIP;
     for (int k = 0; k < 4 && s == SPH_OK; k++)

@@ -15,10 +15,11 @@
 // Validation: finite inputs, positive m and H, positions inside [0,L) of the
 // particle's box; per-box largest and smallest H.
 // ---------------------------------------------------------------------------
-__device__ inline void flush_hrange(unsigned long long* dstat, int d, double hmx, double hmn)
+__device__ inline void flush_hrange(unsigned long long* dstat, int d, double hmx, double hmn, unsigned long long cnt)
 {
-    atomicMax(&dstat[2 * d], (unsigned long long)__double_as_longlong(hmx));
-    atomicMin(&dstat[2 * d + 1], (unsigned long long)__double_as_longlong(hmn));
+    atomicMax(&dstat[3 * d], (unsigned long long)__double_as_longlong(hmx));
+    atomicMin(&dstat[3 * d + 1], (unsigned long long)__double_as_longlong(hmn));
+    atomicAdd(&dstat[3 * d + 2], cnt);
 }
 
 // Each workgroup takes one contiguous range of particles (coalesced within
@@ -37,6 +38,7 @@ __global__ __launch_bounds__(256) void k_validate(int64_t n, const double* __res
 {
     int dcur = -1;
     double hmx = 0.0, hmn = INFINITY;
+    unsigned long long cnt = 0;
     bool bad = false;
     const int64_t per = (n + gridDim.x - 1) / gridDim.x;
     const int64_t b0 = (int64_t)blockIdx.x * per, b1 = min(n, b0 + per);
@@ -55,13 +57,15 @@ __global__ __launch_bounds__(256) void k_validate(int64_t n, const double* __res
             continue;
         }
         if (d != dcur) {
-            if (dcur >= 0) flush_hrange(dstat, dcur, hmx, hmn);
+            if (dcur >= 0) flush_hrange(dstat, dcur, hmx, hmn, cnt);
             dcur = d;
             hmx = 0.0;
             hmn = INFINITY;
+            cnt = 0;
         }
         hmx = fmax(hmx, h);
         hmn = fmin(hmn, h);
+        cnt++;
     }
     if (bad) atomicOr(flags, FLAG_INVALID);
     const int d0 = __shfl(dcur, 0);
@@ -70,10 +74,11 @@ __global__ __launch_bounds__(256) void k_validate(int64_t n, const double* __res
         for (int off = 32; off > 0; off >>= 1) {
             hmx = fmax(hmx, __shfl_xor(hmx, off));
             hmn = fmin(hmn, __shfl_xor(hmn, off));
+            cnt += __shfl_xor(cnt, off);
         }
-        if ((threadIdx.x & 63) == 0) flush_hrange(dstat, d0, hmx, hmn);
+        if ((threadIdx.x & 63) == 0) flush_hrange(dstat, d0, hmx, hmn, cnt);
     } else if (dcur >= 0) {
-        flush_hrange(dstat, dcur, hmx, hmn);
+        flush_hrange(dstat, dcur, hmx, hmn, cnt);
     }
 }
 
@@ -939,11 +944,12 @@ sph_status build_all(sph_ctx* c)
 
     // 1. validate, per-box H range
     SPH_CHECK_HIP(hipMemsetAsync(flags, 0, FI_NFLAGS * sizeof(int), c->stream));
-    std::vector<unsigned long long> dstat_h(2 * nd);
+    std::vector<unsigned long long> dstat_h(3 * nd);
     for (int d = 0; d < nd; d++) {
-        dstat_h[2 * d] = 0ull;
+        dstat_h[3 * d] = 0ull;
+        dstat_h[3 * d + 2] = 0ull;
         double inf = INFINITY;
-        memcpy(&dstat_h[2 * d + 1], &inf, 8);
+        memcpy(&dstat_h[3 * d + 1], &inf, 8);
     }
     // box extents are needed for validation before the grid is known
     c->dom_h.resize(nd);
@@ -953,26 +959,29 @@ sph_status build_all(sph_ctx* c)
         for (int a = 0; a < 3; a++) I.L[a] = c->boxes[3 * d + a];
     }
     SPH_CHECK_HIP(hipMemcpyAsync(c->dom_d.p, c->dom_h.data(), nd * sizeof(DomainInfo), hipMemcpyHostToDevice, c->stream));
-    SPH_CHECK_HIP(hipMemcpyAsync(c->dstat.p, dstat_h.data(), 2 * nd * 8, hipMemcpyHostToDevice, c->stream));
+    SPH_CHECK_HIP(hipMemcpyAsync(c->dstat.p, dstat_h.data(), 3 * nd * 8, hipMemcpyHostToDevice, c->stream));
     k_validate<<<std::min(blocks_for(n, 256), 2048), 256, 0, c->stream>>>(n, c->P.x, c->P.y, c->P.z, c->P.H, c->P.m, c->P.domain, nd,
                                                         (const DomainInfo*)c->dom_d.p,
                                                         (unsigned long long*)c->dstat.p, flags);
     SPH_CHECK_LAUNCH();
     int fl = 0;
-    SPH_CHECK_HIP(hipMemcpyAsync(dstat_h.data(), c->dstat.p, 2 * nd * 8, hipMemcpyDeviceToHost, c->stream));
+    SPH_CHECK_HIP(hipMemcpyAsync(dstat_h.data(), c->dstat.p, 3 * nd * 8, hipMemcpyDeviceToHost, c->stream));
     SPH_TRY(read_int(c, flags, &fl));
     if (fl & FLAG_INVALID) return SPH_ERR_INVALID;
 
-    // 2. top grids (edge >= largest H of the box, >= 3 cells per dimension)
+    // 2. top grids (edge >= largest H of the box, >= 3 cells per dimension;
+    // about twice as large where such cells would hold under 64 particles)
     int top = 0;
     double min_ratio = INFINITY;
     c->min_s0 = INFINITY;
     for (int d = 0; d < nd; d++) {
         double hmax, hmin;
-        memcpy(&hmax, &dstat_h[2 * d], 8);
-        memcpy(&hmin, &dstat_h[2 * d + 1], 8);
+        memcpy(&hmax, &dstat_h[3 * d], 8);
+        memcpy(&hmin, &dstat_h[3 * d + 1], 8);
+        const double nbox = (double)dstat_h[3 * d + 2];
         DomainInfo& I = c->dom_h[d];
-        if (dstat_h[2 * d] == 0ull) { hmax = 0.0; hmin = INFINITY; }  // empty box
+        if (dstat_h[3 * d] == 0ull) { hmax = 0.0; hmin = INFINITY; }  // empty box
+        int ntb[3];
         for (int a = 0; a < 3; a++) {
             // largest cell count with edge L/nt >= hmax
             int nt = 3;
@@ -983,7 +992,16 @@ sph_status build_all(sph_ctx* c)
                 while (I.L[a] / (nt + 1) >= hmax && nt < 1000000) nt++;
             }
             if (nt < 3) return SPH_ERR_BOX_TOO_SMALL;
-            nt = std::min(nt, 128);
+            ntb[a] = std::min(nt, 128);
+        }
+        // near-uniform boxes: top cells of edge ~H hold only ~10 particles
+        // each, so the leaves would stay far below a wave; there the cells
+        // are taken about twice as large per dimension where the box allows
+        if (nbox < 64.0 * (double)ntb[0] * ntb[1] * ntb[2])
+            for (int a = 0; a < 3; a++)
+                if (ntb[a] / 2 >= 3) ntb[a] /= 2;
+        for (int a = 0; a < 3; a++) {
+            const int nt = ntb[a];
             I.n_top[a] = nt;
             I.s0[a] = I.L[a] / nt;
             c->min_s0 = std::min(c->min_s0, I.s0[a]);

@@ -45,7 +45,7 @@ struct sph_ctx {
     sph_stats st{};
 
     // device buffers
-    DevBuf dom_d, dstat;          // DomainInfo[], per-domain (hmax, hmin) as u64 bits
+    DevBuf dom_d, dstat;          // DomainInfo[], per-domain (hmax, hmin) as u64 bits and particle count
     DevBuf keys[2], vals[2];      // radix sort ping-pong
     DevBuf okeys[2], ovals[2];    // task-order sort ping-pong
     DevBuf ikeys[2], ivals[2];    // interpolation point-order sort ping-pong
