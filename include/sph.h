@@ -166,8 +166,9 @@ sph_status sph_create(const sph_params* params, void* hip_stream, sph_ctx** out)
 sph_status sph_destroy(sph_ctx* ctx);
 
 /* Cell construction (Sec. 3.1: a grid of cells of edge >= the largest H per
- * box, recursively split while a cell holds more than n_split particles;
- * self and pair interactions between cells within range).  Binds `p` to the
+ * box -- about twice that where such cells would hold under 64 particles --
+ * recursively split while a cell holds more than n_split particles; self
+ * and pair interactions between cells within range).  Binds `p` to the
  * context, permutes every non-NULL particle array in place into Morton order
  * of the cells, and builds the neighbour-cell lists.  Particles must lie in
  * [0, L) of their box.  Errors: SPH_ERR_INVALID (NaN, non-positive H or m,
@@ -208,11 +209,12 @@ sph_status sph_force(sph_ctx* ctx);
 sph_status sph_density_ghost_force(sph_ctx* ctx);
 
 /* One kick-drift-kick step of length dt (integrator stage, Sec. 3.1):
- * half kick of v and u with the current forces, drift with periodic wrap,
- * cell rebuild and sort, density with H warm-started, ghost with the
- * predicted u, force with the predicted v, second half kick, FP64
- * conservation sums.  Requires a previous sph_force (forces of the current
- * positions). */
+ * half kick of v and u with the current forces, drift with periodic wrap
+ * (and, with h_drift, the start of each H iteration carried along the
+ * flow), cell rebuild and sort or, with rebuild_steps > 0, a refresh of the
+ * kept cells, density from that start, ghost with the predicted u, force
+ * with the predicted v, second half kick fused with the FP64 conservation
+ * sums.  Requires a previous sph_force (forces of the current positions). */
 sph_status sph_step(sph_ctx* ctx, double dt);
 
 /* SPH interpolation, Sec. 2, eq. (interp): out[k] = sum_i m_i Q_i / rho_i
