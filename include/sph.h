@@ -67,8 +67,10 @@ typedef struct {
     int precision;       /* SPH_FP64, SPH_FP32C (cell-relative FP32, compensated sums)
                             or SPH_FP32 (cell-relative FP32, plain sums) */
     int exec_mode;       /* SPH_EXEC_GRID: one workgroup slot per cell;
-                            SPH_EXEC_PERSISTENT: resident workgroups drain a
-                            cost-ordered device task queue */
+                            SPH_EXEC_PERSISTENT: resident workgroups drain
+                            device task queues, one per XCD over a contiguous
+                            Morton range of cells, and help the other XCDs'
+                            queues once their own is empty */
     int n_domains;       /* number of independent periodic boxes (>= 1) */
     int persistent_wgs;  /* resident workgroups for the persistent mode (0: auto) */
     int use_graph;       /* 1: density sweeps, ghost and force run as one captured
@@ -122,7 +124,7 @@ typedef struct {
     int64_t n_leaves;        /* leaf cells (self tasks) */
     int64_t n_nodes;         /* cells of all levels */
     int64_t n_list;          /* neighbour-cell entries (ordered pairs incl. self) */
-    int64_t n_pair_tasks;    /* unordered pair tasks (B > A) */
+    int64_t n_pair_tasks;    /* unordered pair tasks (B > A), persistent mode (else 0) */
     int64_t n_dens;          /* sum_i #{j : r_ij < H_i}, self included, at the final H
                                 (from the last force call; after density alone, at the
                                 last H the density stage evaluated) */

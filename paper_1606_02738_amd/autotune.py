@@ -4,7 +4,7 @@ Times whole kick-drift-kick steps through the C-ABI for a set of candidate
 configurations on the caller's particle set and returns the fastest.  The
 tunables are the leaf size (n_split: the tile of particles one wave holds),
 the execution form (one wave per leaf over a plain grid, or persistent
-workgroups draining a cost-ordered leaf queue, with the number of resident
+workgroups draining per-XCD leaf queues, with the number of resident
 workgroups), the pair-pruning mode, the force form (each pair once with
 atomic j-side sums, or every particle gathering its own pairs), hipGraph
 capture of the density, ghost and force stages, and how many steps the
@@ -65,6 +65,7 @@ def candidates(full=False):
     for rs in (4, 8, 16, 32, 64):
         out.append(dict(base, rebuild_steps=rs))
         out.append(dict(base, rebuild_steps=rs, use_graph=True))
+        out.append(dict(base, rebuild_steps=rs, exec_mode="persistent", persistent_wgs=2048))
     out.append(dict(base, rebuild_steps=32, force="pairs"))
     return out
 

@@ -78,7 +78,7 @@ sph_status sph_create(const sph_params* params, void* hip_stream, sph_ctx** out)
     c->stream = (hipStream_t)hip_stream;
     sph_status s = SPH_OK;
     if (s == SPH_OK) s = buf_ensure(c->flags, FI_NFLAGS * sizeof(int));
-    if (s == SPH_OK) s = buf_ensure(c->counters, CNT_N * 8);
+    if (s == SPH_OK) s = buf_ensure(c->counters, CNT_ALLOC * 8);
     if (s == SPH_OK) s = buf_ensure(c->dparam, 8 * sizeof(double));
     if (s == SPH_OK && hipMemsetAsync(c->dparam.p, 0, 8 * sizeof(double), c->stream) != hipSuccess) s = SPH_ERR_HIP;
     if (s == SPH_OK) s = buf_ensure(c->dom_d, (size_t)p.n_domains * sizeof(DomainInfo));
@@ -88,7 +88,7 @@ sph_status sph_create(const sph_params* params, void* hip_stream, sph_ctx** out)
     for (int k = 0; k < 4 && s == SPH_OK; k++)
         if (hipEventCreate(&c->kev[k]) != hipSuccess) s = SPH_ERR_HIP;
     if (s == SPH_OK && hipMemsetAsync(c->flags.p, 0, FI_NFLAGS * sizeof(int), c->stream) != hipSuccess) s = SPH_ERR_HIP;
-    if (s == SPH_OK && hipMemsetAsync(c->counters.p, 0, CNT_N * 8, c->stream) != hipSuccess) s = SPH_ERR_HIP;
+    if (s == SPH_OK && hipMemsetAsync(c->counters.p, 0, CNT_ALLOC * 8, c->stream) != hipSuccess) s = SPH_ERR_HIP;
     if (s != SPH_OK) {
         sph_destroy(c);
         return s;
@@ -102,10 +102,10 @@ sph_status sph_destroy(sph_ctx* c)
     if (!c) return SPH_OK;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
-    DevBuf* all[] = {&c->dom_d, &c->dstat, &c->keys[0], &c->keys[1], &c->vals[0], &c->vals[1], &c->okeys[0], &c->okeys[1], &c->ovals[0], &c->ovals[1], &c->ikeys[0], &c->ikeys[1], &c->ivals[0], &c->ivals[1], &c->dranges, &c->tmp, &c->nodes, &c->wnodes,
+    DevBuf* all[] = {&c->dom_d, &c->dstat, &c->keys[0], &c->keys[1], &c->vals[0], &c->vals[1], &c->ikeys[0], &c->ikeys[1], &c->ivals[0], &c->ivals[1], &c->dranges, &c->tmp, &c->nodes, &c->wnodes,
                      &c->nchild, &c->coff, &c->leafmark, &c->leafscan, &c->leaf_node, &c->l_begin, &c->l_count,
                      &c->l_origin, &c->l_lo, &c->l_hi, &c->l_hlist, &c->l_dom, &c->l_off, &c->l_active, &c->l_sorted,
-                     &c->l_cnt, &c->l_cost, &c->l_order, &c->list, &c->pos4, &c->fv4, &c->hf, &c->skey, &c->sidx,
+                     &c->l_cnt, &c->list, &c->pos4, &c->fv4, &c->hf, &c->skey, &c->sidx,
                      &c->hlo, &c->hhi, &c->conv, &c->flags, &c->counters,
                      &c->scan_tmp, &c->rs_hist, &c->sums, &c->dsum_part, &c->fgrid, &c->fcount, &c->mlp_X, &c->mlp_hprev, &c->mlp_params, &c->mlp_packed, &c->mlp_m, &c->mlp_v, &c->ds_X, &c->ds_y, &c->ds_count, &c->dparam, &c->walk_scratch};
     for (DevBuf* b : all) buf_free(*b);

@@ -782,47 +782,31 @@ static sph_status permute_all(sph_ctx* c, const uint32_t* perm)
     return SPH_OK;
 }
 
-// Task cost of a leaf (asymptotic model: particles of the cell times the
-// particles of every cell it interacts with) and the descending-cost order
-// in which the persistent kernels drain the leaves.
-__global__ __launch_bounds__(256) void k_leaf_cost(int n_leaves, const int* __restrict__ l_count,
-                                                   const int* __restrict__ l_off, const ListEntry* __restrict__ list,
-                                                   const double* __restrict__ l_hlist, uint64_t* keys, uint32_t* vals,
-                                                   unsigned long long* n_owned)
+// Unordered pair tasks (B > A) of the neighbour-cell lists: the entries a
+// leaf owns (persistent mode statistic).
+__global__ __launch_bounds__(256) void k_pair_tasks(int n_leaves, const int* __restrict__ l_off,
+                                                    const ListEntry* __restrict__ list,
+                                                    const double* __restrict__ l_hlist, unsigned long long* n_owned)
 {
     const int A = blockIdx.x * blockDim.x + threadIdx.x;
-    if (A >= n_leaves) return;
-    long long s = 0;
     unsigned long long own = 0;
-    for (int e = l_off[A]; e < l_off[A + 1]; e++) {
-        const ListEntry E = list[e];
-        s += l_count[E.B];
-        if (E.B != A && (E.B > A || !(E.dist < l_hlist[E.B]))) own++;
-    }
-    if (own) atomicAdd(n_owned, own);
-    long long cost = (long long)l_count[A] * s;
-    const long long cmax = (1ll << 40) - 1;
-    if (cost > cmax) cost = cmax;
-    keys[A] = (uint64_t)(cmax - cost);
-    vals[A] = (uint32_t)A;
+    if (A < n_leaves)
+        for (int e = l_off[A]; e < l_off[A + 1]; e++) {
+            const ListEntry E = list[e];
+            if (E.B != A && (E.B > A || !(E.dist < l_hlist[E.B]))) own++;
+        }
+    for (int off = 32; off > 0; off >>= 1) own += __shfl_xor(own, off);
+    if ((threadIdx.x & 63) == 0 && own) atomicAdd(n_owned, own);
 }
 
-static sph_status task_order(sph_ctx* c)
+static sph_status pair_tasks(sph_ctx* c)
 {
     const int nL = c->n_leaves;
-    for (int q = 0; q < 2; q++) {
-        SPH_TRY(buf_ensure(c->okeys[q], (size_t)(nL + 1) * 8));
-        SPH_TRY(buf_ensure(c->ovals[q], (size_t)(nL + 1) * 4));
-    }
     unsigned long long* npair = (unsigned long long*)c->counters.p + CNT_NPAIR;
     SPH_CHECK_HIP(hipMemsetAsync(npair, 0, 8, c->stream));
-    k_leaf_cost<<<blocks_for(nL, 256), 256, 0, c->stream>>>(nL, (const int*)c->l_count.p, (const int*)c->l_off.p,
-                                                          (const ListEntry*)c->list.p, (const double*)c->l_hlist.p,
-                                                          (uint64_t*)c->okeys[0].p, (uint32_t*)c->ovals[0].p, npair);
+    k_pair_tasks<<<blocks_for(nL, 256), 256, 0, c->stream>>>(nL, (const int*)c->l_off.p, (const ListEntry*)c->list.p,
+                                                           (const double*)c->l_hlist.p, npair);
     SPH_CHECK_LAUNCH();
-    int res = 0;
-    SPH_TRY(radix_sort(c, nL, 40, c->okeys, c->ovals, &res));
-    SPH_CHECK_HIP(hipMemcpyAsync(c->l_order.p, c->ovals[res].p, (size_t)nL * 4, hipMemcpyDeviceToDevice, c->stream));
     return SPH_OK;
 }
 
@@ -925,7 +909,7 @@ sph_status relist(sph_ctx* c)
     }
     SPH_CHECK_LAUNCH();
     c->n_list = total;
-    if (c->prm.exec_mode == SPH_EXEC_PERSISTENT) return task_order(c);
+    if (c->prm.exec_mode == SPH_EXEC_PERSISTENT) return pair_tasks(c);
     return SPH_OK;
 }
 
@@ -1107,8 +1091,6 @@ sph_status build_all(sph_ctx* c)
     SPH_TRY(buf_ensure(c->l_active, L1 * 4));
     SPH_TRY(buf_ensure(c->l_sorted, L1 * 4));
     SPH_TRY(buf_ensure(c->l_cnt, L1 * 4));
-    SPH_TRY(buf_ensure(c->l_cost, L1 * 8));
-    SPH_TRY(buf_ensure(c->l_order, L1 * 4));
     k_leaf_fill<<<blocks_for(n_nodes, 256), 256, 0, c->stream>>>(
         (Node*)c->nodes.p, n_nodes, (const int*)c->leafscan.p, (int*)c->leaf_node.p, (int*)c->l_begin.p,
         (int*)c->l_count.p, (double*)c->l_origin.p, (double*)c->l_lo.p, (double*)c->l_hi.p, (double*)c->l_hlist.p,

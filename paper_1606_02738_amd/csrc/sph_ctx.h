@@ -47,7 +47,6 @@ struct sph_ctx {
     // device buffers
     DevBuf dom_d, dstat;          // DomainInfo[], per-domain (hmax, hmin) as u64 bits and particle count
     DevBuf keys[2], vals[2];      // radix sort ping-pong
-    DevBuf okeys[2], ovals[2];    // task-order sort ping-pong
     DevBuf ikeys[2], ivals[2];    // interpolation point-order sort ping-pong
     DevBuf dranges;               // per-box particle ranges [n_domains + 1]
     const void* keys_sorted = nullptr;  // sorted Morton keys of the last build
@@ -56,7 +55,7 @@ struct sph_ctx {
     DevBuf wnodes;                // compact cells for the list walk
     DevBuf leafmark, leafscan;    // per particle
     DevBuf leaf_node;             // leaf -> node
-    DevBuf l_begin, l_count, l_origin, l_lo, l_hi, l_hlist, l_dom, l_off, l_active, l_sorted, l_cnt, l_cost, l_order;
+    DevBuf l_begin, l_count, l_origin, l_lo, l_hi, l_hlist, l_dom, l_off, l_active, l_sorted, l_cnt;
     DevBuf list;
     DevBuf walk_scratch;          // per-leaf slots of the one-pass list walk
     int walk_cap = 128;           // entries per slot (grows after an overflow)

@@ -112,6 +112,29 @@ __device__ inline int wave_pop(unsigned long long* counter, int lane)
 
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Task queue of the persistent kernels.  Task positions [0, nL) are cut into
+// XQ_N = 8 contiguous ranges, one per XCD (workgroup b runs on XCD b mod 8),
+// each drained through its own counter q[x * XQ_STRIDE].  A wave takes tasks
+// from the range of its own XCD first, so the waves running side by side on
+// one XCD work on neighbouring leaves and share its L2; once that range is
+// empty it helps the other ranges in ring order, which balances ranges of
+// unequal cost.  `k` (start at 0) is the number of ranges the wave has found
+// empty; returns -1 when all are.  Every successful pop takes a distinct
+// position, so a wave's loop over this ends after at most nL + 1 calls.
+static_assert(XQ_N == 8, "one task range per XCD");
+__device__ inline int xq_pop(unsigned long long* q, int nL, int& k, int lane)
+{
+    const int home = blockIdx.x & 7;
+    while (k < XQ_N) {
+        const int x = (home + k) & 7;
+        const int lo = (int)(((long long)nL * x) >> 3), hi = (int)(((long long)nL * (x + 1)) >> 3);
+        const long long t = (long long)lo + wave_pop(&q[x * XQ_STRIDE], lane);
+        if (t < hi) return (int)t;
+        k++;
+    }
+    return -1;
+}
+
 // v_writelane_b32: replace lane `lane` of `old` by the wave-uniform `src`
 __device__ int amdgcn_writelane(int src, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
 
@@ -229,7 +252,6 @@ struct DensArgs {
     double h_tol;
     int* flags;
     unsigned long long* counters;
-    const int* order;   // task order (persistent mode), may be NULL
     const double* margin;  // list margin: twice the largest displacement since the lists were built
     const int* gate;    // graph mode: skip the sweep unless *gate == 0 (NULL: always run)
     const int* nl_dev;  // graph mode: leaf count read from the device (NULL: n_leaves)
@@ -746,13 +768,11 @@ __global__ __launch_bounds__(256) void k_density(DensArgs a)
         density_leaf<T, COMP, PRUNE>(a, A, tiles[w], lane);
         return;
     }
-    // persistent: waves pop leaves from a cost-ordered queue; a wave pops at
-    // most n_leaves times
+    // persistent: waves pop leaves from the per-XCD queues
+    int k = 0;
     for (int it = 0; it <= nL; it++) {
-        const int t = wave_pop(&a.counters[CNT_QUEUE], lane);
-        if (t >= nL) break;
-        const int A = uniform(a.order ? a.order[t] : t);
-        if (A < 0 || A >= nL) break;
+        const int A = xq_pop(&a.counters[XQ_DENS], nL, k, lane);
+        if (A < 0) break;
         if (a.l_active[A]) density_leaf<T, COMP, PRUNE>(a, A, tiles[w], lane);
     }
 }
@@ -779,11 +799,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPH_DENS_WA
         density_leaf_packed<T, COMP>(a, A, tiles[w], lane);
         return;
     }
+    int k = 0;
     for (int it = 0; it <= nL; it++) {
-        const int t = wave_pop(&a.counters[CNT_QUEUE], lane);
-        if (t >= nL) break;
-        const int A = uniform(a.order ? a.order[t] : t);
-        if (A < 0 || A >= nL) break;
+        const int A = xq_pop(&a.counters[XQ_DENS], nL, k, lane);
+        if (A < 0) break;
         if (a.l_active[A] && a.l_count[A] <= 64) density_leaf_packed<T, COMP>(a, A, tiles[w], lane);
     }
 }
@@ -875,7 +894,6 @@ struct ForceArgs {
     double* dudt;
     int32_t* nngb;      // #{j : r_ij < H_i} incl. self at the final H (may be NULL)
     unsigned long long* counters;
-    const int* order;
     const double* margin;  // list margin: twice the largest displacement since the lists were built
     const int* gate;    // graph mode: run only if *gate == 1 (NULL: always run)
     const int* nl_dev;  // graph mode: leaf count read from the device (NULL: n_leaves)
@@ -1291,11 +1309,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPH_FORCE_W
         force_leaf<T, COMP, PRUNE>(a, A, tiles[w], lane);
         return;
     }
+    int k = 0;
     for (int it = 0; it <= nL; it++) {
-        const int t = wave_pop(&a.counters[CNT_QUEUE2], lane);
-        if (t >= nL) break;
-        const int A = uniform(a.order ? a.order[t] : t);
-        if (A < 0 || A >= nL) break;
+        const int A = xq_pop(&a.counters[XQ_FORCE], nL, k, lane);
+        if (A < 0) break;
         force_leaf<T, COMP, PRUNE>(a, A, tiles[w], lane);
     }
 }
@@ -1544,11 +1561,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPH_FORCEG_
         force_leaf_gather<T, COMP>(a, A, tiles[w], lane);
         return;
     }
+    int k = 0;
     for (int it = 0; it <= nL; it++) {
-        const int t = wave_pop(&a.counters[CNT_QUEUE2], lane);
-        if (t >= nL) break;
-        const int A = uniform(a.order ? a.order[t] : t);
-        if (A < 0 || A >= nL) break;
+        const int A = xq_pop(&a.counters[XQ_FORCE], nL, k, lane);
+        if (A < 0) break;
         force_leaf_gather<T, COMP>(a, A, tiles[w], lane);
     }
 }
@@ -1728,7 +1744,6 @@ static void dens_args(sph_ctx* c, const int* gate, bool graph, DensArgs& a, int&
     a.flags = (int*)c->flags.p;
     a.counters = (unsigned long long*)c->counters.p;
     a.persistent = c->prm.exec_mode == SPH_EXEC_PERSISTENT;
-    a.order = a.persistent ? (const int*)c->l_order.p : nullptr;
     a.gate = gate;
     a.margin = (const double*)c->dparam.p;
     a.nl_dev = graph ? (const int*)c->flags.p + FI_NLEAVES : nullptr;
@@ -1737,11 +1752,19 @@ static void dens_args(sph_ctx* c, const int* gate, bool graph, DensArgs& a, int&
     nb = a.persistent ? std::min(resident_wgs(c), blocks_for(nl, WAVES_PER_WG)) : blocks_for(nl, WAVES_PER_WG);
 }
 
-static sph_status launch_density(sph_ctx* c, const int* gate, bool graph = false)
+// `fresh`: every leaf is active (the first sweep of a density call or the
+// first after a rebuild).  Only such a sweep drains the persistent queues;
+// the later sweeps, with most leaves converged, run as a grid, whose
+// workgroups of inactive leaves exit at once (a queue would pop every leaf).
+static sph_status launch_density(sph_ctx* c, const int* gate, bool graph, bool fresh)
 {
     DensArgs a;
     int nb = 0;
     dens_args(c, gate, graph, a, nb);
+    if (a.persistent && !fresh) {
+        a.persistent = 0;
+        nb = blocks_for(graph ? leaf_capacity(c) : c->n_leaves, WAVES_PER_WG);
+    }
     if (nb <= 0) return SPH_OK;
     const bool srt = c->prm.prune == SPH_PRUNE_SORTED;
     if (!srt) {
@@ -1823,12 +1846,14 @@ static sph_status density_loop(sph_ctx* c, int done_sweeps, unsigned long long u
     int fl = 0;
     bool prec_rebuilt = false;
     sph_status status = SPH_OK;
+    bool fresh = done_sweeps == 0;
     for (sweeps = done_sweeps + 1; sweeps <= c->prm.max_h_iter; sweeps++) {
         SPH_CHECK_HIP(hipMemsetAsync(flags, 0, sizeof(int), c->stream));
         SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_UNCONV], 0, 8, c->stream));
-        SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_QUEUE], 0, 8, c->stream));
+        SPH_CHECK_HIP(hipMemsetAsync(&cnt[XQ_DENS], 0, XQ_N * XQ_STRIDE * 8, c->stream));
         SPH_CHECK_HIP(hipEventRecord(c->kev[0], c->stream));
-        SPH_TRY(launch_density(c, nullptr));
+        SPH_TRY(launch_density(c, nullptr, false, fresh));
+        fresh = false;
         SPH_CHECK_HIP(hipEventRecord(c->kev[1], c->stream));
         unsigned long long hc[CNT_N];
         SPH_CHECK_HIP(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, c->stream));
@@ -1870,6 +1895,7 @@ static sph_status density_loop(sph_ctx* c, int done_sweeps, unsigned long long u
                 SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_NDENS], 0, 8, c->stream));
                 c->st.rebuilds++;
                 c->st.precision_rebuilds++;
+                fresh = true;
                 continue;
             }
         }
@@ -1886,6 +1912,7 @@ static sph_status density_loop(sph_ctx* c, int done_sweeps, unsigned long long u
             SPH_CHECK_LAUNCH();
             SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_NDENS], 0, 8, c->stream));
             c->st.rebuilds++;
+            fresh = true;
         } else if (fl & FLAG_RELIST) {
             SPH_TRY(relist(c));
             c->st.relists++;
@@ -1981,7 +2008,6 @@ static void force_args(sph_ctx* c, const int* gate, bool graph, ForceArgs& a, in
     a.nngb = c->P.nngb;
     a.counters = (unsigned long long*)c->counters.p;
     a.persistent = c->prm.exec_mode == SPH_EXEC_PERSISTENT;
-    a.order = a.persistent ? (const int*)c->l_order.p : nullptr;
     a.gate = gate;
     a.margin = (const double*)c->dparam.p;
     a.nl_dev = graph ? (const int*)c->flags.p + FI_NLEAVES : nullptr;
@@ -2028,7 +2054,7 @@ sph_status force_all(sph_ctx* c)
     SPH_CHECK_HIP(hipMemsetAsync(c->P.az, 0, nb8, c->stream));
     SPH_CHECK_HIP(hipMemsetAsync(c->P.dudt, 0, nb8, c->stream));
     SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_NFORCE], 0, 8, c->stream));
-    SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_QUEUE2], 0, 8, c->stream));
+    SPH_CHECK_HIP(hipMemsetAsync(&cnt[XQ_FORCE], 0, XQ_N * XQ_STRIDE * 8, c->stream));
     SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_NDENS_F], 0, 8, c->stream));
     if (c->P.nngb) SPH_CHECK_HIP(hipMemsetAsync(c->P.nngb, 0, (size_t)c->n * 4, c->stream));
     SPH_CHECK_HIP(hipEventRecord(c->kev[2], c->stream));
@@ -2080,7 +2106,7 @@ __global__ void k_sweep_begin(unsigned long long* cnt, int* flags, const int* ga
 {
     if (threadIdx.x == 0 && blockIdx.x == 0 && *gate == 0) {
         cnt[CNT_UNCONV] = 0ull;
-        cnt[CNT_QUEUE] = 0ull;
+        for (int r = 0; r < XQ_N; r++) cnt[XQ_DENS + r * XQ_STRIDE] = 0ull;
         flags[FI_FLAGS] = 0;
         cnt[CNT_GSWEEPS] += 1ull;
     }
@@ -2106,7 +2132,7 @@ __global__ __launch_bounds__(256) void k_force_zero(int64_t n, double* ax, doubl
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) {
         cnt[CNT_NFORCE] = 0ull;
-        cnt[CNT_QUEUE2] = 0ull;
+        for (int r = 0; r < XQ_N; r++) cnt[XQ_FORCE + r * XQ_STRIDE] = 0ull;
         cnt[CNT_NDENS_F] = 0ull;
     }
     if (i < n) {
@@ -2181,7 +2207,7 @@ static sph_status capture_dgf(sph_ctx* c, const double* u, const double* vx, con
     k_graph_begin<<<1, 64, 0, c->stream>>>(cnt, flags, gate);
     for (int k = 0; k < sweeps && st == SPH_OK; k++) {
         k_sweep_begin<<<1, 64, 0, c->stream>>>(cnt, flags, gate);
-        st = launch_density(c, gate, true);
+        st = launch_density(c, gate, true, k == 0);
         k_sweep_end<<<1, 64, 0, c->stream>>>(cnt, flags, gate);
     }
     if (st == SPH_OK) st = launch_ghost(c, u, vx, vy, vz, gate);
