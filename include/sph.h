@@ -124,7 +124,7 @@ typedef struct {
     int64_t n_leaves;        /* leaf cells (self tasks) */
     int64_t n_nodes;         /* cells of all levels */
     int64_t n_list;          /* neighbour-cell entries (ordered pairs incl. self) */
-    int64_t n_pair_tasks;    /* unordered pair tasks (B > A), persistent mode (else 0) */
+    int64_t n_pair_tasks;    /* unordered pair tasks (B > A) of the current lists */
     int64_t n_dens;          /* sum_i #{j : r_ij < H_i}, self included, at the final H
                                 (from the last force call; after density alone, at the
                                 last H the density stage evaluated) */

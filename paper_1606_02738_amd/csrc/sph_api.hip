@@ -206,10 +206,16 @@ sph_status sph_get_stats(sph_ctx* c, sph_stats* out)
     c->st.n_leaves = c->n_leaves;
     c->st.n_nodes = c->n_nodes;
     c->st.n_list = c->n_list;
-    {
+    if (c->built && !c->pair_tasks_valid) {
+        SPH_TRY(count_pair_tasks(c));
         unsigned long long np = 0;
-        SPH_CHECK_HIP(hipMemcpy(&np, (unsigned long long*)c->counters.p + CNT_NPAIR, 8, hipMemcpyDeviceToHost));
+        SPH_CHECK_HIP(hipMemcpyAsync(&np, (unsigned long long*)c->counters.p + CNT_NPAIR, 8, hipMemcpyDeviceToHost,
+                                     c->stream));
+        SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
         c->st.n_pair_tasks = (int64_t)np;
+        c->pair_tasks_valid = true;
+    } else if (!c->built) {
+        c->st.n_pair_tasks = 0;
     }
     c->st.depth = c->depth;
     c->st.key_bits = c->key_bits;

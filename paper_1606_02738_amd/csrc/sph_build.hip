@@ -783,7 +783,7 @@ static sph_status permute_all(sph_ctx* c, const uint32_t* perm)
 }
 
 // Unordered pair tasks (B > A) of the neighbour-cell lists: the entries a
-// leaf owns (persistent mode statistic).
+// leaf owns.  A statistic only, counted when it is read.
 __global__ __launch_bounds__(256) void k_pair_tasks(int n_leaves, const int* __restrict__ l_off,
                                                     const ListEntry* __restrict__ list,
                                                     const double* __restrict__ l_hlist, unsigned long long* n_owned)
@@ -799,7 +799,7 @@ __global__ __launch_bounds__(256) void k_pair_tasks(int n_leaves, const int* __r
     if ((threadIdx.x & 63) == 0 && own) atomicAdd(n_owned, own);
 }
 
-static sph_status pair_tasks(sph_ctx* c)
+sph_status count_pair_tasks(sph_ctx* c)
 {
     const int nL = c->n_leaves;
     unsigned long long* npair = (unsigned long long*)c->counters.p + CNT_NPAIR;
@@ -909,7 +909,7 @@ sph_status relist(sph_ctx* c)
     }
     SPH_CHECK_LAUNCH();
     c->n_list = total;
-    if (c->prm.exec_mode == SPH_EXEC_PERSISTENT) return pair_tasks(c);
+    c->pair_tasks_valid = false;
     return SPH_OK;
 }
 

@@ -31,7 +31,8 @@ struct sph_ctx {
     // octree / leaves / lists
     int n_nodes = 0, n_leaves = 0, depth = 0;
     int max_leaf = 0;            // particles in the fullest leaf
-    int64_t n_list = 0, n_pair_tasks = 0;
+    int64_t n_list = 0;
+    bool pair_tasks_valid = false;  // the device count of pair tasks belongs to the current lists
     std::vector<int> level_off;  // node index of the first node of each level
 
     // stage state
@@ -129,6 +130,7 @@ sph_status radix_sort(sph_ctx* c, int n, int bits, DevBuf* kb, DevBuf* vb, int* 
 sph_status build_all(sph_ctx* c);
 sph_status sort_all(sph_ctx* c);
 sph_status relist(sph_ctx* c);
+sph_status count_pair_tasks(sph_ctx* c);
 sph_status node_hmax_all(sph_ctx* c, bool set_hlist);
 sph_status refresh_leaves(sph_ctx* c, bool* fresh);
 sph_status domain_ranges(sph_ctx* c);
