@@ -67,10 +67,11 @@ typedef struct {
     int precision;       /* SPH_FP64, SPH_FP32C (cell-relative FP32, compensated sums)
                             or SPH_FP32 (cell-relative FP32, plain sums) */
     int exec_mode;       /* SPH_EXEC_GRID: one workgroup slot per cell;
-                            SPH_EXEC_PERSISTENT: resident workgroups drain
-                            device task queues, one per XCD over a contiguous
-                            Morton range of cells, and help the other XCDs'
-                            queues once their own is empty */
+                            SPH_EXEC_PERSISTENT: in the force loop, resident
+                            workgroups drain device task queues, one per XCD
+                            over a contiguous Morton range of cells, and help
+                            the other XCDs' queues once their own is empty
+                            (density sweeps run as a grid in both modes) */
     int n_domains;       /* number of independent periodic boxes (>= 1) */
     int persistent_wgs;  /* resident workgroups for the persistent mode (0: auto) */
     int use_graph;       /* 1: density sweeps, ghost and force run as one captured

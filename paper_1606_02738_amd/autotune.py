@@ -3,9 +3,9 @@
 Times whole kick-drift-kick steps through the C-ABI for a set of candidate
 configurations on the caller's particle set and returns the fastest.  The
 tunables are the leaf size (n_split: the tile of particles one wave holds),
-the execution form (one wave per leaf over a plain grid, or persistent
-workgroups draining per-XCD leaf queues, with the number of resident
-workgroups), the pair-pruning mode, the force form (each pair once with
+the execution form of the force loop (one wave per leaf over a plain grid,
+or persistent workgroups draining per-XCD leaf queues, with the number of
+resident workgroups), the pair-pruning mode, the force form (each pair once with
 atomic j-side sums, or every particle gathering its own pairs), hipGraph
 capture of the density, ghost and force stages, and how many steps the
 cells and lists are kept (the list skin).  Every candidate starts from the same saved state, so each is timed

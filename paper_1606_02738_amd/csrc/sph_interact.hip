@@ -112,7 +112,7 @@ __device__ inline int wave_pop(unsigned long long* counter, int lane)
 
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Task queue of the persistent kernels.  Task positions [0, nL) are cut into
+// Task queue of the persistent force kernels.  Task positions [0, nL) are cut into
 // XQ_N = 8 contiguous ranges, one per XCD (workgroup b runs on XCD b mod 8),
 // each drained through its own counter q[x * XQ_STRIDE].  A wave takes tasks
 // from the range of its own XCD first, so the waves running side by side on
@@ -255,7 +255,6 @@ struct DensArgs {
     const double* margin;  // list margin: twice the largest displacement since the lists were built
     const int* gate;    // graph mode: skip the sweep unless *gate == 0 (NULL: always run)
     const int* nl_dev;  // graph mode: leaf count read from the device (NULL: n_leaves)
-    int persistent;
     int big_only;       // skip leaves of at most 64 particles (done by the packed kernel)
 };
 
@@ -760,21 +759,11 @@ __global__ __launch_bounds__(256) void k_density(DensArgs a)
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (a.gate && uniform(*a.gate) != 0) return;
     const int nL = a.nl_dev ? uniform(*a.nl_dev) : a.n_leaves;
-    if (!a.persistent) {
-        const int A = uniform(xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_WG + w);
-        if (A >= nL) return;
-        if (!a.l_active[A]) return;
-        if (a.big_only && a.l_count[A] <= 64) return;
-        density_leaf<T, COMP, PRUNE>(a, A, tiles[w], lane);
-        return;
-    }
-    // persistent: waves pop leaves from the per-XCD queues
-    int k = 0;
-    for (int it = 0; it <= nL; it++) {
-        const int A = xq_pop(&a.counters[XQ_DENS], nL, k, lane);
-        if (A < 0) break;
-        if (a.l_active[A]) density_leaf<T, COMP, PRUNE>(a, A, tiles[w], lane);
-    }
+    const int A = uniform(xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_WG + w);
+    if (A >= nL) return;
+    if (!a.l_active[A]) return;
+    if (a.big_only && a.l_count[A] <= 64) return;
+    density_leaf<T, COMP, PRUNE>(a, A, tiles[w], lane);
 }
 
 
@@ -792,19 +781,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPH_DENS_WA
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (a.gate && uniform(*a.gate) != 0) return;
     const int nL = a.nl_dev ? uniform(*a.nl_dev) : a.n_leaves;
-    if (!a.persistent) {
-        const int A = uniform(xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_WG + w);
-        if (A >= nL) return;
-        if (!a.l_active[A] || a.l_count[A] > 64) return;
-        density_leaf_packed<T, COMP>(a, A, tiles[w], lane);
-        return;
-    }
-    int k = 0;
-    for (int it = 0; it <= nL; it++) {
-        const int A = xq_pop(&a.counters[XQ_DENS], nL, k, lane);
-        if (A < 0) break;
-        if (a.l_active[A] && a.l_count[A] <= 64) density_leaf_packed<T, COMP>(a, A, tiles[w], lane);
-    }
+    const int A = uniform(xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_WG + w);
+    if (A >= nL) return;
+    if (!a.l_active[A] || a.l_count[A] > 64) return;
+    density_leaf_packed<T, COMP>(a, A, tiles[w], lane);
 }
 
 __global__ __launch_bounds__(256) void k_density_reset(int64_t n, int n_leaves, double* hlo, double* hhi, uint8_t* conv,
@@ -1743,28 +1723,23 @@ static void dens_args(sph_ctx* c, const int* gate, bool graph, DensArgs& a, int&
     a.h_tol = c->prm.precision == SPH_FP64 ? c->prm.h_tol : std::max(c->prm.h_tol, 2e-6);
     a.flags = (int*)c->flags.p;
     a.counters = (unsigned long long*)c->counters.p;
-    a.persistent = c->prm.exec_mode == SPH_EXEC_PERSISTENT;
     a.gate = gate;
     a.margin = (const double*)c->dparam.p;
     a.nl_dev = graph ? (const int*)c->flags.p + FI_NLEAVES : nullptr;
     if (graph) a.n_leaves = 0;  // read on the device
     const int nl = graph ? leaf_capacity(c) : c->n_leaves;
-    nb = a.persistent ? std::min(resident_wgs(c), blocks_for(nl, WAVES_PER_WG)) : blocks_for(nl, WAVES_PER_WG);
+    nb = blocks_for(nl, WAVES_PER_WG);
 }
 
-// `fresh`: every leaf is active (the first sweep of a density call or the
-// first after a rebuild).  Only such a sweep drains the persistent queues;
-// the later sweeps, with most leaves converged, run as a grid, whose
-// workgroups of inactive leaves exit at once (a queue would pop every leaf).
-static sph_status launch_density(sph_ctx* c, const int* gate, bool graph, bool fresh)
+// Density sweeps run as a grid of one wave per leaf in every execution mode:
+// the persistent queues were slower here (first sweep 10.2 against 10.0 ms
+// at 256^3, and the later sweeps, with most leaves converged, pay a pop per
+// leaf where a grid's workgroups of converged leaves exit at once).
+static sph_status launch_density(sph_ctx* c, const int* gate, bool graph = false)
 {
     DensArgs a;
     int nb = 0;
     dens_args(c, gate, graph, a, nb);
-    if (a.persistent && !fresh) {
-        a.persistent = 0;
-        nb = blocks_for(graph ? leaf_capacity(c) : c->n_leaves, WAVES_PER_WG);
-    }
     if (nb <= 0) return SPH_OK;
     const bool srt = c->prm.prune == SPH_PRUNE_SORTED;
     if (!srt) {
@@ -1776,7 +1751,6 @@ static sph_status launch_density(sph_ctx* c, const int* gate, bool graph, bool f
         // the chunked two-phase kernel over a plain grid
         if (c->max_leaf <= 64) return SPH_OK;
         a.big_only = 1;
-        a.persistent = 0;
         nb = blocks_for(graph ? leaf_capacity(c) : c->n_leaves, WAVES_PER_WG);
     }
     if (c->prm.precision == SPH_FP64) {
@@ -1846,14 +1820,11 @@ static sph_status density_loop(sph_ctx* c, int done_sweeps, unsigned long long u
     int fl = 0;
     bool prec_rebuilt = false;
     sph_status status = SPH_OK;
-    bool fresh = done_sweeps == 0;
     for (sweeps = done_sweeps + 1; sweeps <= c->prm.max_h_iter; sweeps++) {
         SPH_CHECK_HIP(hipMemsetAsync(flags, 0, sizeof(int), c->stream));
         SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_UNCONV], 0, 8, c->stream));
-        SPH_CHECK_HIP(hipMemsetAsync(&cnt[XQ_DENS], 0, XQ_N * XQ_STRIDE * 8, c->stream));
         SPH_CHECK_HIP(hipEventRecord(c->kev[0], c->stream));
-        SPH_TRY(launch_density(c, nullptr, false, fresh));
-        fresh = false;
+        SPH_TRY(launch_density(c, nullptr));
         SPH_CHECK_HIP(hipEventRecord(c->kev[1], c->stream));
         unsigned long long hc[CNT_N];
         SPH_CHECK_HIP(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, c->stream));
@@ -1895,7 +1866,6 @@ static sph_status density_loop(sph_ctx* c, int done_sweeps, unsigned long long u
                 SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_NDENS], 0, 8, c->stream));
                 c->st.rebuilds++;
                 c->st.precision_rebuilds++;
-                fresh = true;
                 continue;
             }
         }
@@ -1912,7 +1882,6 @@ static sph_status density_loop(sph_ctx* c, int done_sweeps, unsigned long long u
             SPH_CHECK_LAUNCH();
             SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_NDENS], 0, 8, c->stream));
             c->st.rebuilds++;
-            fresh = true;
         } else if (fl & FLAG_RELIST) {
             SPH_TRY(relist(c));
             c->st.relists++;
@@ -2106,7 +2075,6 @@ __global__ void k_sweep_begin(unsigned long long* cnt, int* flags, const int* ga
 {
     if (threadIdx.x == 0 && blockIdx.x == 0 && *gate == 0) {
         cnt[CNT_UNCONV] = 0ull;
-        for (int r = 0; r < XQ_N; r++) cnt[XQ_DENS + r * XQ_STRIDE] = 0ull;
         flags[FI_FLAGS] = 0;
         cnt[CNT_GSWEEPS] += 1ull;
     }
@@ -2207,7 +2175,7 @@ static sph_status capture_dgf(sph_ctx* c, const double* u, const double* vx, con
     k_graph_begin<<<1, 64, 0, c->stream>>>(cnt, flags, gate);
     for (int k = 0; k < sweeps && st == SPH_OK; k++) {
         k_sweep_begin<<<1, 64, 0, c->stream>>>(cnt, flags, gate);
-        st = launch_density(c, gate, true, k == 0);
+        st = launch_density(c, gate, true);
         k_sweep_end<<<1, 64, 0, c->stream>>>(cnt, flags, gate);
     }
     if (st == SPH_OK) st = launch_ghost(c, u, vx, vy, vz, gate);

@@ -103,10 +103,10 @@ enum { FI_FLAGS = 0, FI_SCRATCH = 8, FI_NCHILD = 9, FI_NLEAVES = 10, FI_NLIST = 
 
 // Counters written by kernels (device, int64).
 enum { CNT_UNCONV = 0, CNT_NDENS = 1, CNT_NFORCE = 2, CNT_DEVAL = 5, CNT_NPAIR = 6, CNT_NDENS_F = 7, CNT_GSWEEPS = 8, CNT_UHIST = 9, CNT_N = 16 };
-// Task queues of the persistent kernels, behind the counters above: XQ_N = 8
-// per loop (density, force), one per XCD, XQ_STRIDE counters (128 bytes)
-// apart.  (64 queues, 8 per XCD, made the force loop slower.)
-enum { XQ_N = 8, XQ_STRIDE = 16, XQ_DENS = CNT_N, XQ_FORCE = CNT_N + XQ_N * XQ_STRIDE, CNT_ALLOC = CNT_N + 2 * XQ_N * XQ_STRIDE };
+// Task queues of the persistent force kernels, behind the counters above:
+// XQ_N = 8, one per XCD, XQ_STRIDE counters (128 bytes) apart.  (64 queues,
+// 8 per XCD, made the force loop slower.)
+enum { XQ_N = 8, XQ_STRIDE = 16, XQ_FORCE = CNT_N, CNT_ALLOC = CNT_N + XQ_N * XQ_STRIDE };
 
 // Leaf arrays (device SoA).
 struct LeafArrays {
