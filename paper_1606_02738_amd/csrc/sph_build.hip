@@ -782,18 +782,22 @@ static sph_status permute_all(sph_ctx* c, const uint32_t* perm)
     return SPH_OK;
 }
 
-// Unordered pair tasks (B > A) of the neighbour-cell lists: the entries a
-// leaf owns.  A statistic only, counted when it is read.
+// Unordered pair tasks of the neighbour-cell lists: the entries a leaf owns.
+// Symmetric lists (gather-form force) hold every pair in both leaves' lists,
+// so the entry with B > A owns it; one-sided lists (pairs form) hold B in A's
+// list when B is within A's radius, so A also owns the entries whose B does
+// not reach back to A.  A statistic only, counted when it is read.
 __global__ __launch_bounds__(256) void k_pair_tasks(int n_leaves, const int* __restrict__ l_off,
                                                     const ListEntry* __restrict__ list,
-                                                    const double* __restrict__ l_hlist, unsigned long long* n_owned)
+                                                    const double* __restrict__ l_hlist, int sym,
+                                                    unsigned long long* n_owned)
 {
     const int A = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long own = 0;
     if (A < n_leaves)
         for (int e = l_off[A]; e < l_off[A + 1]; e++) {
             const ListEntry E = list[e];
-            if (E.B != A && (E.B > A || !(E.dist < l_hlist[E.B]))) own++;
+            if (E.B != A && (E.B > A || (!sym && !(E.dist < l_hlist[E.B])))) own++;
         }
     for (int off = 32; off > 0; off >>= 1) own += __shfl_xor(own, off);
     if ((threadIdx.x & 63) == 0 && own) atomicAdd(n_owned, own);
@@ -804,8 +808,10 @@ sph_status count_pair_tasks(sph_ctx* c)
     const int nL = c->n_leaves;
     unsigned long long* npair = (unsigned long long*)c->counters.p + CNT_NPAIR;
     SPH_CHECK_HIP(hipMemsetAsync(npair, 0, 8, c->stream));
+    if (nL <= 0) return SPH_OK;
     k_pair_tasks<<<blocks_for(nL, 256), 256, 0, c->stream>>>(nL, (const int*)c->l_off.p, (const ListEntry*)c->list.p,
-                                                           (const double*)c->l_hlist.p, npair);
+                                                           (const double*)c->l_hlist.p,
+                                                           c->prm.force_mode == SPH_FORCE_GATHER ? 1 : 0, npair);
     SPH_CHECK_LAUNCH();
     return SPH_OK;
 }

@@ -256,6 +256,32 @@ def test_ensemble_boxes_equal_standalone_runs(prec, mode):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_persistent_force_bit_identical_to_grid(prec):
+    """Gather-form force: a particle's sums run over its own leaf's list in
+    list order whichever wave takes the leaf, so the per-XCD queues of the
+    persistent mode (waves that empty their own XCD's range take leaves from
+    the others) must reproduce the grid launch bit for bit; a leaf lost or
+    taken twice would show here.  The density sweeps are a grid launch in
+    both modes.  The lists of the gather force are symmetric: every
+    unordered pair of neighbouring leaves sits in both lists, so the
+    pair-task count is half the entries besides the leaves' own (no leaf
+    reaches its periodic image in this box)."""
+    log("case persistent vs grid gather force, clustered 40^3 %s" % prec)
+    d = gen.clustered(40, seed=5, n_halos=8)
+    g, sg = gpu_run(d, precision=prec, exec_mode="grid", force="gather")
+    p, sp = gpu_run(d, precision=prec, exec_mode="persistent", force="gather")
+    assert sg["n_unconverged"] == 0 and sp["n_unconverged"] == 0
+    for k in ("rho", "H", "ax", "ay", "az", "dudt"):
+        assert np.array_equal(g[k], p[k]), k
+    assert np.array_equal(g["nngb"], p["nngb"])
+    assert sg["n_force"] == sp["n_force"] and sg["n_dens"] == sp["n_dens"]
+    assert sg["n_list"] == sp["n_list"] and sg["n_leaves"] == sp["n_leaves"]
+    assert sg["n_pair_tasks"] == sp["n_pair_tasks"]
+    assert 2 * sp["n_pair_tasks"] == sp["n_list"] - sp["n_leaves"]
+    log("leaves %d, list entries %d, pair tasks %d" % (sp["n_leaves"], sp["n_list"], sp["n_pair_tasks"]))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
 def test_wide_h_range_stress(prec):
     """A more extreme clustered box (log-density sigma 3, half the particles
     in concentrated halos over 4 decades of mass): smoothing lengths span
