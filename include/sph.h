@@ -329,7 +329,9 @@ sph_status sph_h_get_params(sph_ctx* ctx, float* params);
  * H (the plain method). */
 sph_status sph_h_predict(sph_ctx* ctx, int on);
 
-/* Copy counters and timings to *out (synchronises the stream). */
+/* Copy counters and timings to *out (synchronises the stream).  The first
+ * call after the cells or lists changed also counts the pair tasks with one
+ * small kernel on the library's stream. */
 sph_status sph_get_stats(sph_ctx* ctx, sph_stats* out);
 
 /* FP64 per-box totals of the bound particles (synchronises the stream):
