@@ -61,7 +61,9 @@ typedef struct {
     double gamma;        /* adiabatic index, 5/3 */
     double eta;          /* resolution parameter (Dehnen-Aly), 1.2348 ~ 48 neighbours */
     double kernel_gamma; /* H / h_DA for the cubic spline, sqrt(10/3) */
-    double h_tol;        /* converged when |rho H^3 - C| <= h_tol * C (FP64 test) */
+    double h_tol;        /* converged when |rho H^3 - C| <= h_tol * C (FP64 test); the FP32
+                            modes use at least 2.5e-7 (SPH_FP32C) or 2e-6 (SPH_FP32), the
+                            resolution of their sums */
     int max_h_iter;      /* smoothing-length sweeps per density call */
     int n_split;         /* split cells holding more than this many particles (<= 64) */
     int precision;       /* SPH_FP64, SPH_FP32C (cell-relative FP32, compensated sums)

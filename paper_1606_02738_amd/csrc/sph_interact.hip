@@ -1720,7 +1720,10 @@ static void dens_args(sph_ctx* c, const int* gate, bool graph, DensArgs& a, int&
     a.conv = (uint8_t*)c->conv.p;
     a.nngb = c->P.nngb;
     a.C_fac = pow(c->prm.kernel_gamma * c->prm.eta, 3.0);
-    a.h_tol = c->prm.precision == SPH_FP64 ? c->prm.h_tol : std::max(c->prm.h_tol, 2e-6);
+    // FP32 sums resolve rho H^3 to about 1e-7 with compensation and a few
+    // 1e-7 without; the residual test is not asked for more than that
+    a.h_tol = c->prm.precision == SPH_FP64 ? c->prm.h_tol
+              : std::max(c->prm.h_tol, c->prm.precision == SPH_FP32C ? SPH_FP32C_TOL_MIN : SPH_FP32_TOL_MIN);
     a.flags = (int*)c->flags.p;
     a.counters = (unsigned long long*)c->counters.p;
     a.gate = gate;

@@ -75,6 +75,13 @@ struct ListEntry {
 // that small growth of H during the iteration needs no new list.
 #define SPH_LIST_SKIN 0.05
 
+// Smallest residual tolerance |rho H^3 - C| / C of the FP32 modes (the
+// sums' own resolution).  The converged H then differs from the exact root by
+// about tol / (3 Omega), and rho by tol |1 - 1/Omega| (Omega reaches ~0.15 in
+// the clustered box), so the compensated mode keeps rho within a few 1e-6.
+#define SPH_FP32C_TOL_MIN 2.5e-7
+#define SPH_FP32_TOL_MIN 2e-6
+
 // Largest leaf extent / smallest H of the leaf in the FP32 modes.
 #define SPH_FP32_EXTENT_RATIO 16.0
 
