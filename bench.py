@@ -434,6 +434,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--force", choices=("pairs", "gather"), default=None,
                     help="force form (default: the autotuner's choice, else gather with box pruning)")
+    ap.add_argument("--lists", choices=("cell", "particle"), default="cell",
+                    help="neighbour lists of the density and force kernels (default: the autotuner's choice)")
+    ap.add_argument("--tile", type=int, default=0, help="LDS segment of the particle-list kernels")
     ap.add_argument("--no-h-drift", action="store_true",
                     help="start the H iteration of a step from the previous H as is")
     ap.add_argument("--seed", type=int, default=2741)
@@ -475,7 +478,8 @@ def main():
     box = d["box"]
     cfg = dict(n_split=args.n_split, exec_mode=args.exec_mode, persistent_wgs=args.persistent_wgs,
                prune=args.prune, use_graph=args.graph, rebuild_steps=args.rebuild_steps,
-               h_drift=not args.no_h_drift, force=args.force or ("gather" if args.prune == "box" else "pairs"))
+               h_drift=not args.no_h_drift, force=args.force or ("gather" if args.prune == "box" else "pairs"),
+               lists=args.lists, tile=args.tile)
     sim = S.SPH(box, precision=args.precision, **cfg)
     t = S.to_device(d)
     del d
@@ -602,7 +606,7 @@ def main():
                    "n_particles": n, "precision": prec, "exec": cfg["exec_mode"], "n_split": cfg["n_split"],
                    "persistent_wgs": cfg["persistent_wgs"], "prune": cfg["prune"], "graph": bool(cfg["use_graph"]),
                    "rebuild_steps": cfg["rebuild_steps"], "h_drift": bool(cfg["h_drift"]),
-                   "force": cfg["force"],
+                   "force": cfg["force"], "lists": cfg.get("lists", "cell"), "tile": cfg.get("tile", 0),
                    "autotuned": bool(args.tune), "dt": dt},
         "builds": builds,
         "build_ms_per_step": sum(s["t_build_ms"] for s in per) / args.steps,

@@ -56,6 +56,7 @@ enum { SPH_FP64 = 0, SPH_FP32C = 1, SPH_FP32 = 2 };      /* sph_params.precision
 enum { SPH_EXEC_GRID = 0, SPH_EXEC_PERSISTENT = 1 };     /* sph_params.exec_mode */
 enum { SPH_PRUNE_BOX = 0, SPH_PRUNE_SORTED = 1 };        /* sph_params.prune */
 enum { SPH_FORCE_PAIRS = 0, SPH_FORCE_GATHER = 1 };      /* sph_params.force_mode */
+enum { SPH_LISTS_CELL = 0, SPH_LISTS_PARTICLE = 1 };     /* sph_params.lists */
 
 typedef struct {
     double gamma;        /* adiabatic index, 5/3 */
@@ -101,6 +102,19 @@ typedef struct {
                             particle sums its own pairs r < max(H_i, H_j) (every pair
                             evaluated from both sides, no atomics, symmetric
                             neighbour-cell lists; box pruning only) */
+    int lists;           /* SPH_LISTS_CELL: the density and force kernels stage the
+                            candidates of each leaf's neighbour cells in LDS and test
+                            them; SPH_LISTS_PARTICLE: at every cell build the cell lists
+                            are turned into one list per particle of the j with
+                            r_ij < max(R_i, R_j), R = 1.02 H plus the kept cells' skin;
+                            a chunk (up to 64 particles of one leaf, one wave) stages the
+                            union of its particles' lists in LDS and every lane loops over
+                            its own list only (positions as fixed-point integers per box
+                            axis, converted to the chunk's frame in the compute
+                            precision).  Requires SPH_FORCE_GATHER and SPH_PRUNE_BOX */
+    int tile;            /* particle lists: candidates staged in LDS per segment, 256, 512
+                            or 1024 (0: 1024 for the density and 512 for the force; FP64
+                            at most 512 / 256) */
     const double* boxes; /* HOST pointer, n_domains x 3 box edge lengths; copied */
 } sph_params;
 
@@ -159,6 +173,13 @@ typedef struct {
     int64_t steps_since_build;  /* sph_step calls since cells and lists were built */
     int64_t n_builds;           /* cell and list builds since sph_create */
     double list_margin;         /* twice the largest displacement since the build */
+    int64_t n_chunks;           /* particle lists: chunks (up to 64 particles of one leaf) */
+    int64_t n_plist;            /* particle lists: entries over all particles (pairs listed from
+                                   both sides, the particle itself not listed) */
+    int64_t n_union;            /* particle lists: members of the chunks' unions */
+    int64_t stale_moved;        /* particle lists, last drift: particles beyond their skin */
+    int64_t stale_grown;        /* particle lists, last drift: particles whose H passed their
+                                   list radius */
 } sph_stats;
 
 typedef struct sph_ctx sph_ctx;

@@ -68,6 +68,9 @@ sph_status sph_create(const sph_params* params, void* hip_stream, sph_ctx** out)
     if (p.h_drift != 0 && p.h_drift != 1) return SPH_ERR_INVALID;
     if (p.force_mode != SPH_FORCE_PAIRS && p.force_mode != SPH_FORCE_GATHER) return SPH_ERR_INVALID;
     if (p.force_mode == SPH_FORCE_GATHER && p.prune != SPH_PRUNE_BOX) return SPH_ERR_INVALID;
+    if (p.lists != SPH_LISTS_CELL && p.lists != SPH_LISTS_PARTICLE) return SPH_ERR_INVALID;
+    if (p.lists == SPH_LISTS_PARTICLE && p.force_mode != SPH_FORCE_GATHER) return SPH_ERR_INVALID;
+    if (p.tile != 0 && p.tile != 256 && p.tile != 512 && p.tile != 1024) return SPH_ERR_INVALID;
     for (int k = 0; k < 3 * p.n_domains; k++)
         if (!(p.boxes[k] > 0.0) || !isfinite(p.boxes[k])) return SPH_ERR_INVALID;
     sph_ctx* c = new (std::nothrow) sph_ctx();
@@ -107,7 +110,9 @@ sph_status sph_destroy(sph_ctx* c)
                      &c->l_origin, &c->l_lo, &c->l_hi, &c->l_hlist, &c->l_dom, &c->l_off, &c->l_active, &c->l_sorted,
                      &c->l_cnt, &c->list, &c->pos4, &c->fv4, &c->hf, &c->skey, &c->sidx,
                      &c->hlo, &c->hhi, &c->conv, &c->flags, &c->counters,
-                     &c->scan_tmp, &c->rs_hist, &c->sums, &c->dsum_part, &c->fgrid, &c->fcount, &c->mlp_X, &c->mlp_hprev, &c->mlp_params, &c->mlp_packed, &c->mlp_m, &c->mlp_v, &c->ds_X, &c->ds_y, &c->ds_count, &c->dparam, &c->walk_scratch};
+                     &c->scan_tmp, &c->rs_hist, &c->sums, &c->dsum_part, &c->fgrid, &c->fcount, &c->mlp_X, &c->mlp_hprev, &c->mlp_params, &c->mlp_packed, &c->mlp_m, &c->mlp_v, &c->ds_X, &c->ds_y, &c->ds_count, &c->dparam, &c->walk_scratch,
+                     &c->pq, &c->pR, &c->plist, &c->prem, &c->plen, &c->pskin, &c->pq0, &c->pext, &c->pbox,
+                     &c->ch_base, &c->ch_p0, &c->ch_n, &c->ch_uo, &c->ch_ro, &c->ch_U};
     for (DevBuf* b : all) buf_free(*b);
     for (int k = 0; k < 8; k++)
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
@@ -227,6 +232,9 @@ sph_status sph_get_stats(sph_ctx* c, sph_stats* out)
     c->st.steps_since_build = c->steps_since_build;
     c->st.n_builds = c->n_builds;
     c->st.list_margin = c->margin_h;
+    c->st.n_chunks = c->n_chunks;
+    c->st.n_plist = c->n_plist;
+    c->st.n_union = c->n_union;
     *out = c->st;
     return SPH_OK;
 }

@@ -847,15 +847,18 @@ sph_status domain_ranges(sph_ctx* c)
 }
 
 // Largest H per cell from the current H, deepest level first; with
-// set_hlist the leaves' list radii become it plus the skins.
+// set_hlist the leaves' list radii become it plus the skins.  With particle
+// lists the cell maxima are those of the particles' list extents R + s
+// instead, so the cell lists hold every pair the particle lists need.
 sph_status node_hmax_all(sph_ctx* c, bool set_hlist)
 {
     Node* nodes = (Node*)c->nodes.p;
+    const double* h = c->prm.lists == SPH_LISTS_PARTICLE && set_hlist ? (const double*)c->pext.p : c->P.H;
     for (int l = (int)c->level_off.size() - 2; l >= 0; l--) {
         const int s = c->level_off[l], nl = c->level_off[l + 1] - s;
         if (nl <= 0) continue;
         k_node_hmax<<<blocks_for(nl, 4), 256, 0, c->stream>>>(
-            nodes, s, nl, c->P.H, set_hlist ? (double*)c->l_hlist.p : nullptr, c->skin_abs,
+            nodes, s, nl, h, set_hlist ? (double*)c->l_hlist.p : nullptr, c->skin_abs,
             set_hlist ? (WNode*)c->wnodes.p : nullptr);
         SPH_CHECK_LAUNCH();
     }
@@ -864,6 +867,8 @@ sph_status node_hmax_all(sph_ctx* c, bool set_hlist)
 
 sph_status relist(sph_ctx* c)
 {
+    // particle lists: radii and skins from the current H
+    if (c->prm.lists == SPH_LISTS_PARTICLE) SPH_TRY(plist_ext(c, true, nullptr));
     SPH_TRY(node_hmax_all(c, true));
     const int nL = c->n_leaves;
     int* counts = (int*)c->l_off.p;
@@ -916,6 +921,8 @@ sph_status relist(sph_ctx* c)
     SPH_CHECK_LAUNCH();
     c->n_list = total;
     c->pair_tasks_valid = false;
+    // particle lists follow every new set of cell lists
+    if (c->prm.lists == SPH_LISTS_PARTICLE) SPH_TRY(plist_build(c));
     return SPH_OK;
 }
 
@@ -958,6 +965,13 @@ sph_status build_all(sph_ctx* c)
     SPH_CHECK_HIP(hipMemcpyAsync(dstat_h.data(), c->dstat.p, 3 * nd * 8, hipMemcpyDeviceToHost, c->stream));
     SPH_TRY(read_int(c, flags, &fl));
     if (fl & FLAG_INVALID) return SPH_ERR_INVALID;
+    // particle lists: the largest list radius and skin of each box
+    std::vector<double> pbox;
+    if (c->prm.lists == SPH_LISTS_PARTICLE) {
+        pbox.assign(2 * (size_t)nd, 0.0);
+        SPH_TRY(plist_ext(c, false, pbox.data()));
+    }
+    c->skin_max = 0.0;
 
     // 2. top grids (edge >= largest H of the box, >= 3 cells per dimension;
     // about twice as large where such cells would hold under 64 particles)
@@ -971,6 +985,23 @@ sph_status build_all(sph_ctx* c)
         const double nbox = (double)dstat_h[3 * d + 2];
         DomainInfo& I = c->dom_h[d];
         if (dstat_h[3 * d] == 0ull) { hmax = 0.0; hmin = INFINITY; }  // empty box
+        // particle lists: top cells cover the largest list radius plus twice
+        // the largest skin; where three such cells per dimension do not fit
+        // the box, the allowances are scaled down by alpha until they do
+        I.pl_alpha = 0.0;
+        I.pl_smax = 0.0;
+        if (!pbox.empty() && dstat_h[3 * d] != 0ull) {
+            const double need = pbox[2 * d] + 2.0 * pbox[2 * d + 1];
+            const double base = hmax * (1.0 + SPH_PLIST_SKIN);
+            const double lim = std::min(I.L[0], std::min(I.L[1], I.L[2])) / 3.0;
+            double alpha = 1.0;
+            if (need > lim) alpha = need > base ? std::max(0.0, (lim - base) / (need - base)) : 0.0;
+            alpha = std::min(alpha, 1.0);
+            I.pl_alpha = alpha;
+            I.pl_smax = alpha * pbox[2 * d + 1];
+            hmax = std::max(hmax, std::min(lim, base + alpha * std::max(0.0, need - base)));
+            c->skin_max = std::max(c->skin_max, I.pl_smax);
+        }
         int ntb[3];
         for (int a = 0; a < 3; a++) {
             // largest cell count with edge L/nt >= hmax
@@ -1119,7 +1150,9 @@ sph_status build_all(sph_ctx* c)
             c->P.z, c->P.m, c->P.H, (float4*)c->pos4.p, (float*)c->hf.p);
     SPH_CHECK_LAUNCH();
 
-    // 7. neighbour-cell lists
+    // 7. neighbour-cell lists (particle lists: the cell lists' radii are the
+    // list extents plus the largest skin)
+    if (c->prm.lists == SPH_LISTS_PARTICLE) c->skin_abs = c->skin_max;
     SPH_TRY(buf_ensure(c->wnodes, (size_t)n_nodes * sizeof(WNode)));
     k_wnodes<<<blocks_for(n_nodes, 256), 256, 0, c->stream>>>((const Node*)c->nodes.p, n_nodes, (WNode*)c->wnodes.p);
     SPH_CHECK_LAUNCH();

@@ -61,6 +61,20 @@ struct sph_ctx {
     DevBuf walk_scratch;          // per-leaf slots of the one-pass list walk
     int walk_cap = 128;           // entries per slot (grows after an overflow)
     DevBuf pos4, fv4, hf;         // kernel-side particle data (T = float or double)
+    // per-particle lists (lists = SPH_LISTS_PARTICLE)
+    DevBuf pq, pR, plen, plist;   // fixed-point positions + mass, list radii, list lengths, entries
+    DevBuf prem;                  // FP32 modes: remainders of the fixed-point coordinates
+    DevBuf pskin, pq0, pext, pbox;  // skins, fixed-point positions at the build, extents R + s,
+                                    // per-box largest R and s
+    double list_dt = 0.0;         // step length of the build's step (0: a build outside a step)
+    double skin_max = 0.0;        // largest skin of the last build
+    DevBuf ch_base, ch_p0, ch_n;  // chunks: first chunk of each leaf; first particle, count
+    DevBuf ch_uo, ch_ro, ch_U;    // union offsets, row offsets, union members
+    int n_chunks = 0;
+    int plist_rows = 0;           // rows of the current particle lists
+    int64_t n_union = 0;          // union members over all chunks
+    bool plist_valid = false;
+    int64_t n_plist = 0;          // entries of the current particle lists
     DevBuf skey, sidx;            // per-direction sorted projections
     DevBuf hlo, hhi, conv;        // Newton brackets and converged flags
     DevBuf flags, counters;       // device flags (int[64], see FI_*) and counters (int64)
@@ -134,6 +148,14 @@ sph_status count_pair_tasks(sph_ctx* c);
 sph_status node_hmax_all(sph_ctx* c, bool set_hlist);
 sph_status refresh_leaves(sph_ctx* c, bool* fresh);
 sph_status domain_ranges(sph_ctx* c);
+
+// per-particle lists (sph_plist.hip)
+struct DensArgs;
+sph_status plist_build(sph_ctx* c);
+sph_status plist_ext(sph_ctx* c, bool final, double* boxmax_host);
+sph_status plist_refresh(sph_ctx* c, bool* fresh);
+sph_status launch_density_plist(sph_ctx* c, const DensArgs& d);
+sph_status launch_force_plist(sph_ctx* c, const int* gate);
 
 // interaction stages (sph_interact.hip)
 sph_status density_all(sph_ctx* c);

@@ -17,6 +17,10 @@ struct DomainInfo {
     double s0[3];     // top-cell edges (>= largest H of the box)
     int n_top[3];     // top cells per dimension (>= 3)
     int top_offset;   // global index of the box's first top cell
+    double pl_smax;   // particle lists: largest skin in the box (the top cells cover the
+                      // largest list radius plus twice this)
+    double pl_alpha;  // particle lists: fraction of the skins and growth allowances the
+                      // box's top cells can hold (1 unless the box is small against them)
 };
 
 // Feature grid of one box for the learned H predictor: G cells per axis,
@@ -74,6 +78,12 @@ struct ListEntry {
 // Relative margin added to a cell's largest H when its list is built, so
 // that small growth of H during the iteration needs no new list.
 #define SPH_LIST_SKIN 0.05
+// The same margin of a particle's own list radius (particle lists); below
+// SPH_LIST_SKIN, so the cell lists hold every pair the particle lists need.
+#define SPH_PLIST_SKIN 0.02
+// Largest growth factor of a particle's list radius (the growth of its H
+// predicted over the lists' lifetime, see k_plist_ext).
+#define SPH_PLIST_GROWTH_MAX 1.5
 
 // Smallest residual tolerance |rho H^3 - C| / C of the FP32 modes (the
 // sums' own resolution).  The converged H then differs from the exact root by
@@ -106,14 +116,17 @@ enum {
 };
 
 // Slots of the int[64] flags buffer.
-enum { FI_FLAGS = 0, FI_SCRATCH = 8, FI_NCHILD = 9, FI_NLEAVES = 10, FI_NLIST = 11, FI_GATE = 12, FI_MAXLEAF = 13, FI_MAXLIST = 14, FI_NFLAGS = 64 };
+enum { FI_FLAGS = 0, FI_SCRATCH = 8, FI_NCHILD = 9, FI_NLEAVES = 10, FI_NLIST = 11, FI_GATE = 12, FI_MAXLEAF = 13, FI_MAXLIST = 14, FI_PLROWS = 15, FI_NFLAGS = 64 };
 
 // Counters written by kernels (device, int64).
-enum { CNT_UNCONV = 0, CNT_NDENS = 1, CNT_NFORCE = 2, CNT_DEVAL = 5, CNT_NPAIR = 6, CNT_NDENS_F = 7, CNT_GSWEEPS = 8, CNT_UHIST = 9, CNT_N = 16 };
+enum { CNT_UNCONV = 0, CNT_NDENS = 1, CNT_NFORCE = 2, CNT_NPLIST = 3, CNT_DEVAL = 5, CNT_NPAIR = 6, CNT_NDENS_F = 7, CNT_GSWEEPS = 8, CNT_UHIST = 9, CNT_N = 16 };
 // Task queues of the persistent force kernels, behind the counters above:
 // XQ_N = 8, one per XCD, XQ_STRIDE counters (128 bytes) apart.  (64 queues,
 // 8 per XCD, made the force loop slower.)
-enum { XQ_N = 8, XQ_STRIDE = 16, XQ_FORCE = CNT_N, CNT_ALLOC = CNT_N + XQ_N * XQ_STRIDE };
+enum { XQ_N = 8, XQ_STRIDE = 16, XQ_FORCE = CNT_N };
+// Particle lists: particles whose list failed the validity test of the last
+// drift, by reason (moved beyond the skin, H beyond the list radius).
+enum { CNT_STALE_MOVED = CNT_N + XQ_N * XQ_STRIDE, CNT_STALE_GROWN, CNT_ALLOC };
 
 // Leaf arrays (device SoA).
 struct LeafArrays {

@@ -24,6 +24,8 @@ SPH_PRUNE_BOX, SPH_PRUNE_SORTED = 0, 1
 PRUNE_MODES = {"box": SPH_PRUNE_BOX, "sorted": SPH_PRUNE_SORTED}
 SPH_FORCE_PAIRS, SPH_FORCE_GATHER = 0, 1
 FORCE_MODES = {"pairs": SPH_FORCE_PAIRS, "gather": SPH_FORCE_GATHER}
+SPH_LISTS_CELL, SPH_LISTS_PARTICLE = 0, 1
+LIST_MODES = {"cell": SPH_LISTS_CELL, "particle": SPH_LISTS_PARTICLE}
 
 STATUS = {0: "SPH_OK", -1: "SPH_ERR_INVALID", -2: "SPH_ERR_HIP", -3: "SPH_ERR_NOT_CONVERGED",
           -4: "SPH_ERR_H_EXCEEDS_CELL", -5: "SPH_ERR_BOX_TOO_SMALL", -6: "SPH_ERR_ALLOC",
@@ -45,7 +47,7 @@ class Params(C.Structure):
                 ("precision", C.c_int), ("exec_mode", C.c_int), ("n_domains", C.c_int),
                 ("persistent_wgs", C.c_int), ("use_graph", C.c_int), ("prune", C.c_int),
                 ("rebuild_steps", C.c_int), ("h_drift", C.c_int), ("force_mode", C.c_int),
-                ("boxes", C.POINTER(C.c_double))]
+                ("lists", C.c_int), ("tile", C.c_int), ("boxes", C.POINTER(C.c_double))]
 
 
 class Particles(C.Structure):
@@ -65,7 +67,9 @@ class Stats(C.Structure):
                 ("n_dens_evals", C.c_int64), ("n_density_launches", C.c_int32),
                 ("graph_captures", C.c_int32), ("graph_fallbacks", C.c_int32), ("precision_rebuilds", C.c_int32),
                 ("unconv_after", C.c_int32 * 8), ("t_predict_ms", C.c_double),
-                ("steps_since_build", C.c_int64), ("n_builds", C.c_int64), ("list_margin", C.c_double)]
+                ("steps_since_build", C.c_int64), ("n_builds", C.c_int64), ("list_margin", C.c_double),
+                ("n_chunks", C.c_int64), ("n_plist", C.c_int64), ("n_union", C.c_int64),
+                ("stale_moved", C.c_int64), ("stale_grown", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -195,7 +199,8 @@ class SPH:
 
     def __init__(self, boxes, precision="fp32c", exec_mode="grid", gamma=5.0 / 3.0, eta=1.2348,
                  kernel_gamma=math.sqrt(10.0 / 3.0), h_tol=None, max_h_iter=40, n_split=64,
-                 persistent_wgs=0, prune="box", use_graph=False, rebuild_steps=0, h_drift=True, force=None, stream=None):
+                 persistent_wgs=0, prune="box", use_graph=False, rebuild_steps=0, h_drift=True, force=None,
+                 lists="cell", tile=0, stream=None):
         import torch
         self._torch = torch
         b = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(-1, 3))
@@ -215,6 +220,8 @@ class SPH:
         if force is None:  # the gather form where it is available (box pruning)
             force = "gather" if p.prune == SPH_PRUNE_BOX else "pairs"
         p.force_mode = FORCE_MODES[force] if isinstance(force, str) else int(force)
+        p.lists = LIST_MODES[lists] if isinstance(lists, str) else int(lists)
+        p.tile = int(tile)
         p.boxes = b.ctypes.data_as(C.POINTER(C.c_double))
         self.params = p
         s = stream if stream is not None else torch.cuda.current_stream()
