@@ -515,19 +515,31 @@ def main():
         sim.step(dt)
         log("warmup step %d done" % k)
     torch.cuda.synchronize()
-    per = []
-    builds0 = sim.stats()["n_builds"]
+    # the timed region: steps only (a step reads the device twice on its own;
+    # the interaction counts are running totals on the device, read after)
+    st0 = sim.stats()
     tstep = []
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         sim.step(dt)
-        per.append(sim.stats())  # synchronises the stream
         tstep.append(time.perf_counter())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    st1 = sim.stats()
     dts = np.diff([t0] + tstep) * 1e3
-    builds = per[-1]["n_builds"] - builds0
+    builds = st1["n_builds"] - st0["n_builds"]
+    assert st1["force_calls"] - st0["force_calls"] == args.steps
+    inter = (st1["n_dens_total"] - st0["n_dens_total"]) + 2 * (st1["n_force_total"] - st0["n_force_total"])
+    force_pairs = st1["n_force_total"] - st0["n_force_total"]
+    dens_total = st1["n_dens_total"] - st0["n_dens_total"]
     log("timed %d steps in %.3f s (%d cell builds)" % (args.steps, wall, builds))
+    # phase breakdown and kernel durations: further steps, each followed by a
+    # stats read, after the timed region
+    per = []
+    for k in range(min(args.steps, 10)):
+        sim.step(dt)
+        per.append(sim.stats())
     kper = per
     if cfg["use_graph"]:
         # kernels inside the graph are not timed one by one: time the same
@@ -543,9 +555,8 @@ def main():
         sim.bind(t)
         sim.run()
 
-    inter = sum(s["n_dens"] + 2 * s["n_force"] for s in per)
     t_dgf = sum(s["t_density_ms"] + s["t_ghost_ms"] + s["t_force_ms"] for s in per) / 1e3
-    force_pairs = sum(s["n_force"] for s in per)
+    inter_phase = sum(s["n_dens"] + 2 * s["n_force"] for s in per)
     # per-kernel durations and the work of those launches
     dens_ms = sum(s["t_density_kernels_ms"] for s in kper)
     dens_launch = sum(s["n_density_launches"] for s in kper)
@@ -609,17 +620,18 @@ def main():
                    "force": cfg["force"], "lists": cfg.get("lists", "cell"), "tile": cfg.get("tile", 0),
                    "autotuned": bool(args.tune), "dt": dt},
         "builds": builds,
-        "build_ms_per_step": sum(s["t_build_ms"] for s in per) / args.steps,
         "interactions_per_step": inter / args.steps,
-        "n_dens_per_step": sum(s["n_dens"] for s in per) / args.steps,
+        "n_dens_per_step": dens_total / args.steps,
         "n_force_per_step": force_pairs / args.steps,
-        "interactions_per_s_density_ghost_force": inter / t_dgf,
-        "mean_sweeps": sum(s["sweeps"] for s in per) / args.steps,
+        "phase_steps": len(per),
+        "build_ms_per_step": sum(s["t_build_ms"] for s in per) / len(per),
+        "interactions_per_s_density_ghost_force": inter_phase / t_dgf,
+        "mean_sweeps": sum(s["sweeps"] for s in per) / len(per),
         "unconverged_after_sweep": [s["unconv_after"][:s["sweeps"]] for s in per],
         "density_evals_per_neighbour": sum(s["n_dens_evals"] for s in per) / max(1, sum(s["n_dens"] for s in per)),
-        "phase_ms_per_step": {"density": sum(s["t_density_ms"] for s in per) / args.steps,
-                              "ghost": sum(s["t_ghost_ms"] for s in per) / args.steps,
-                              "force": sum(s["t_force_ms"] for s in per) / args.steps},
+        "phase_ms_per_step": {"density": sum(s["t_density_ms"] for s in per) / len(per),
+                              "ghost": sum(s["t_ghost_ms"] for s in per) / len(per),
+                              "force": sum(s["t_force_ms"] for s in per) / len(per)},
         "kernels": other,
         "roofline": roof,
     }

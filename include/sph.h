@@ -21,13 +21,24 @@
  *   - Returns sph_status; never throws, never aborts.  Argument errors and
  *     HIP launch errors are reported synchronously.  Conditions found on the
  *     device (non-convergence, H too large for the box) are reported by the
- *     call that observes them (the density call synchronises its stream once
- *     per smoothing-length sweep).
+ *     call that observes them: the density stage runs its first sweeps as a
+ *     device-gated sequence and reads the device once at its end (more
+ *     sweeps, relists and rebuilds continue from there on the host); a step
+ *     reads it once more before its density stage (largest speed, validity
+ *     of the kept cells and lists); ghost and force do not wait on the
+ *     device, and the force stage's counts and a step's totals are read by
+ *     sph_get_stats.
  *   - All particle arrays are DEVICE pointers owned by the caller, length n,
  *     structure-of-arrays, float64 unless stated.  The library never frees
- *     them.  It keeps its own scratch buffers (device memory allocated with
- *     hipMalloc inside sph_build_cells when they need to grow) and frees them
- *     in sph_destroy.
+ *     them.
+ *   - The library never allocates device memory: every buffer it keeps
+ *     (keys, octree, cell and particle lists, kernel-side particle data,
+ *     predictor samples, interpolation order) is carved from the workspace
+ *     the caller gives to sph_create (sph_workspace_size estimates it).  A
+ *     call whose buffers do not fit returns SPH_ERR_WORKSPACE and
+ *     sph_get_stats reports the bytes it needed; the context stays usable
+ *     for smaller work, or is replaced by one with a larger workspace.  The
+ *     context-free predictor calls take their own workspace argument.
  *   - Work is enqueued on the HIP stream given to sph_create.
  *   - A context is not thread-safe; use one context per host thread.
  */
@@ -48,7 +59,7 @@ typedef enum {
     SPH_ERR_NOT_CONVERGED = -3,  /* smoothing lengths not converged in max_h_iter sweeps */
     SPH_ERR_H_EXCEEDS_CELL = -4, /* a smoothing length outgrew the cell grid (rebuild) */
     SPH_ERR_BOX_TOO_SMALL = -5,  /* a smoothing length exceeds 1/3 of its box edge */
-    SPH_ERR_ALLOC = -6,          /* device allocation failed */
+    SPH_ERR_WORKSPACE = -6,      /* the caller's workspace is too small for the call */
     SPH_ERR_STATE = -7           /* call out of order (e.g. force before ghost) */
 } sph_status;
 
@@ -180,15 +191,34 @@ typedef struct {
     int64_t stale_moved;        /* particle lists, last drift: particles beyond their skin */
     int64_t stale_grown;        /* particle lists, last drift: particles whose H passed their
                                    list radius */
+    int64_t workspace_bytes;    /* usable bytes of the workspace */
+    int64_t workspace_in_use;   /* bytes the context's buffers hold now */
+    int64_t workspace_high;     /* most bytes held at once */
+    int64_t workspace_needed;   /* after SPH_ERR_WORKSPACE: bytes that call needed (0: none failed) */
+    int64_t n_force_total;      /* sum of n_force over every force stage since sph_create */
+    int64_t n_dens_total;       /* sum of n_dens (force stage's count) since sph_create */
+    int64_t force_calls;        /* force stages since sph_create */
 } sph_stats;
 
 typedef struct sph_ctx sph_ctx;
 
-/* Create a context.  `params` is copied (including the boxes array).
- * hip_stream: a hipStream_t (NULL = default stream). */
-sph_status sph_create(const sph_params* params, void* hip_stream, sph_ctx** out);
+/* Smallest workspace sph_create accepts. */
+#define SPH_WORKSPACE_MIN ((size_t)1 << 20)
 
-/* Release every buffer the context owns.  Safe on NULL. */
+/* Workspace bytes for n particles with these parameters (HOST *bytes): an
+ * estimate covering the stages' buffers for the clustered and lattice
+ * workloads, interpolation at up to n points and predictor samples of up to
+ * n / 8 particles.  SPH_ERR_INVALID on n < 1 or n >= 2^31. */
+sph_status sph_workspace_size(const sph_params* params, int64_t n, size_t* bytes);
+
+/* Create a context.  `params` is copied (including the boxes array).
+ * workspace: DEVICE memory of `bytes` bytes owned by the caller (e.g. a torch
+ * uint8 tensor), at least SPH_WORKSPACE_MIN; the context carves all its
+ * device buffers from it and the caller must keep it until sph_destroy.
+ * hip_stream: a hipStream_t (NULL = default stream). */
+sph_status sph_create(const sph_params* params, void* workspace, size_t bytes, void* hip_stream, sph_ctx** out);
+
+/* Release the context (its workspace returns to the caller).  Safe on NULL. */
 sph_status sph_destroy(sph_ctx* ctx);
 
 /* Cell construction (Sec. 3.1: a grid of cells of edge >= the largest H per
@@ -301,20 +331,29 @@ sph_status sph_interpolate(sph_ctx* ctx, const double* Q, const double* px, cons
 #define SPH_MLP_NT 9473
 #define SPH_MLP_NP 9507
 
+/* Workspace bytes (HOST *bytes) of sph_mlp_forward and sph_mlp_loss_grad over
+ * n rows. */
+sph_status sph_mlp_workspace_size(int64_t n, size_t* bytes);
+
 /* Network output for n feature rows: y[i] = predicted log(H_new/H_prev).
  * params: SPH_MLP_NP floats, X: n x SPH_MLP_XSTRIDE floats, y: n floats; all
- * DEVICE pointers.  Matrix products on the MFMA units (bfloat16 weights,
- * activations split into two bfloat16 terms, float32 accumulation).
- * hip_stream: hipStream_t (NULL = default).  SPH_ERR_INVALID on n < 0 or a
- * NULL pointer with n > 0. */
-sph_status sph_mlp_forward(const float* params, const float* X, int64_t n, float* y, void* hip_stream);
+ * DEVICE pointers.  workspace: DEVICE scratch of `bytes` bytes (packed
+ * weights; sph_mlp_workspace_size).  Matrix products on the MFMA units
+ * (bfloat16 weights, activations split into two bfloat16 terms, float32
+ * accumulation).  hip_stream: hipStream_t (NULL = default); asynchronous.
+ * SPH_ERR_INVALID on n < 0 or a NULL pointer with n > 0,
+ * SPH_ERR_WORKSPACE if the workspace is too small. */
+sph_status sph_mlp_forward(const float* params, const float* X, int64_t n, float* y, void* workspace, size_t bytes,
+                           void* hip_stream);
 
 /* Mean loss (HOST *loss, may be NULL) and its gradient with respect to the
  * SPH_MLP_NT trained parameters (DEVICE grad) over n rows (X as above, y:
  * n target values of log(H_new/H_prev)); float32 arithmetic with the
- * bfloat16-rounded weights.  Synchronises the stream. */
+ * bfloat16-rounded weights.  workspace: DEVICE scratch of `bytes` bytes
+ * (per-workgroup partial gradients; sph_mlp_workspace_size).  Synchronises
+ * the stream (for *loss). */
 sph_status sph_mlp_loss_grad(const float* params, const float* X, const float* y, int64_t n, float* grad,
-                             double* loss, void* hip_stream);
+                             double* loss, void* workspace, size_t bytes, void* hip_stream);
 
 /* One Adam step (step number t >= 1) on the SPH_MLP_NT trained values of
  * params with moment buffers m, v (SPH_MLP_NT floats each, DEVICE):
@@ -331,9 +370,14 @@ sph_status sph_h_features(sph_ctx* ctx, double dt, float* X);
 /* Record training samples during the following sph_step calls: each step
  * keeps about rate * n particles (chosen by a hash of seed, step count and
  * index) as (features, log(H_converged / H_prev)) until `capacity` samples
- * are held on the device.  capacity = 0 stops recording and frees the
- * samples.  Returns the number held so far through *held (HOST, may be NULL). */
-sph_status sph_h_record(sph_ctx* ctx, int64_t capacity, double rate, uint64_t seed, int64_t* held);
+ * are held, in the caller's DEVICE buffers X (capacity x SPH_MLP_XSTRIDE
+ * floats) and y (capacity floats), which must stay valid until recording
+ * stops and sph_h_train has read them.  Calling again with the same buffers
+ * and capacity only reports the count; other buffers restart the count.
+ * capacity = 0 stops recording (X, y may be NULL).  Returns the number held
+ * so far through *held (HOST, may be NULL). */
+sph_status sph_h_record(sph_ctx* ctx, float* X, float* y, int64_t capacity, double rate, uint64_t seed,
+                        int64_t* held);
 
 /* Train the context's network on the recorded samples with the library's
  * forward, backward and Adam kernels: `epochs` passes in minibatches of
@@ -352,9 +396,10 @@ sph_status sph_h_get_params(sph_ctx* ctx, float* params);
  * H (the plain method). */
 sph_status sph_h_predict(sph_ctx* ctx, int on);
 
-/* Copy counters and timings to *out (synchronises the stream).  The first
- * call after the cells or lists changed also counts the pair tasks with one
- * small kernel on the library's stream. */
+/* Copy counters and timings to *out (synchronises the stream: the force
+ * stage's counts and kernel time and a step's FP64 totals are read from the
+ * device here).  The first call after the cells or lists changed also counts
+ * the pair tasks with one small kernel on the library's stream. */
 sph_status sph_get_stats(sph_ctx* ctx, sph_stats* out);
 
 /* FP64 per-box totals of the bound particles (synchronises the stream):

@@ -543,8 +543,9 @@ __device__ inline float box_dist_f(const float* alo, const float* ahi, const flo
 }
 
 // MODE 0: count the entries of each leaf; 1: write them at the scanned
-// offsets l_off; 2: write up to list_cap entries of leaf A at A * list_cap
-// and count them all (one pass when no leaf exceeds the capacity).
+// offsets l_off (with list_cap > 0, only the leaves of more than list_cap
+// entries: the others come from their slots); 2: write up to list_cap
+// entries of leaf A at A * list_cap and count them all.
 template <int MODE>
 __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restrict__ leaf_node, const WNode* __restrict__ wn,
                                               const double* __restrict__ l_lo, const double* __restrict__ l_hi,
@@ -558,6 +559,7 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
     const DomainInfo& I = di[l_dom[A]];
     const int loc = l_top[A] - I.top_offset;
     const int tc[3] = {loc / (I.n_top[2] * I.n_top[1]), (loc / I.n_top[2]) % I.n_top[1], loc % I.n_top[2]};
+    if (MODE == 1 && list_cap > 0 && l_off[A + 1] - l_off[A] <= list_cap) return;
     const double hA = l_hlist[A];
     // conservative float pruning radius: the float boxes are rounded outward;
     // the absolute term covers the rounding of box + periodic shift in float
@@ -568,8 +570,9 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
     const double ahi[3] = {l_hi[3 * A], l_hi[3 * A + 1], l_hi[3 * A + 2]};
     constexpr bool FILL = MODE != 0;
     int cnt = 0;
-    int out = MODE == 1 ? l_off[A] : (MODE == 2 ? A * list_cap : 0);
-    const int out_end = MODE == 1 ? l_off[A + 1] : (MODE == 2 ? A * list_cap + list_cap : 0);
+    const size_t out_base = MODE == 1 ? (size_t)l_off[A] : (MODE == 2 ? (size_t)A * list_cap : 0);
+    const int out_len = MODE == 1 ? l_off[A + 1] - l_off[A] : (MODE == 2 ? list_cap : 0);
+    int out = 0;
     for (int sx = -1; sx <= 1; sx++)
     for (int sy = -1; sy <= 1; sy++)
     for (int sz = -1; sz <= 1; sz++) {
@@ -616,7 +619,7 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
                 }
                 if (!(d < (sym ? fmax(hA, l_hlist[B]) : hA))) continue;
                 if (FILL) {
-                    if (out < out_end && (MODE == 2 || out < list_cap)) {
+                    if (out < out_len) {
                         int best = 0;
                         if (with_dir) {
                             // sort direction: the one of 13 most aligned with the centre offset
@@ -633,7 +636,7 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
                         e.B = B;
                         e.code = code_shift | (best << 8);
                         e.dist = d;
-                        list[out] = e;
+                        list[out_base + out] = e;
                     } else if (MODE == 1) {
                         atomicOr(flags, FLAG_INVALID);
                     }
@@ -648,7 +651,8 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
 }
 
 // Move the entries of the one-pass walk from the per-leaf slots to the
-// scanned offsets.  One wave per leaf.
+// scanned offsets (leaves of more than cap entries are walked again).  One
+// wave per leaf.
 __global__ __launch_bounds__(256) void k_list_compact(int n_leaves, int cap, const ListEntry* __restrict__ scratch,
                                                       const int* __restrict__ l_off, ListEntry* __restrict__ list)
 {
@@ -656,6 +660,7 @@ __global__ __launch_bounds__(256) void k_list_compact(int n_leaves, int cap, con
     if (A >= n_leaves) return;
     const int lane = threadIdx.x & 63;
     const int o = l_off[A], n = l_off[A + 1] - o;
+    if (n > cap) return;
     for (int e = lane; e < n; e += 64) list[o + e] = scratch[(size_t)A * cap + e];
 }
 
@@ -877,9 +882,12 @@ sph_status relist(sph_ctx* c)
     const int with_dir = c->prm.prune == SPH_PRUNE_SORTED;
     // the gather-form force needs every leaf within either radius in both lists
     const int sym = c->prm.force_mode == SPH_FORCE_GATHER;
-    // one pass into per-leaf slots of walk_cap entries, counting every entry
-    const int cap = c->walk_cap;
-    const bool one_pass = (size_t)nL * cap < ((size_t)1 << 31) - (size_t)cap;
+    // one pass into per-leaf slots, counting every entry; a slot holds about
+    // twice the previous build's mean entries per leaf, and all slots together
+    // at most SPH_WALK_SLOT_BYTES per particle
+    int cap = c->walk_cap;
+    while (cap > 16 && (size_t)nL * cap * sizeof(ListEntry) > (size_t)c->n * SPH_WALK_SLOT_BYTES) cap /= 2;
+    const bool one_pass = (size_t)nL * cap * sizeof(ListEntry) <= (size_t)c->n * SPH_WALK_SLOT_BYTES + ((size_t)1 << 20);
     if (one_pass) {
         SPH_TRY(buf_ensure(c->walk_scratch, (size_t)nL * cap * sizeof(ListEntry)));
         SPH_CHECK_HIP(hipMemsetAsync(flags + FI_MAXLIST, 0, sizeof(int), c->stream));
@@ -899,26 +907,30 @@ sph_status relist(sph_ctx* c)
     SPH_CHECK_HIP(hipMemcpyAsync(hf, flags + FI_NLIST, sizeof(hf), hipMemcpyDeviceToHost, c->stream));
     SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
     const int total = hf[0], over = hf[FI_MAXLIST - FI_NLIST];
-    if (total < 0) return SPH_ERR_ALLOC;
+    if (total < 0) return SPH_ERR_WORKSPACE;
     SPH_TRY(buf_ensure(c->list, (size_t)std::max(total, 1) * sizeof(ListEntry)));
-    if (one_pass && over == 0) {
+    if (one_pass) {
         k_list_compact<<<blocks_for(nL, 4), 256, 0, c->stream>>>(nL, cap, (const ListEntry*)c->walk_scratch.p,
                                                                  (const int*)c->l_off.p, (ListEntry*)c->list.p);
-    } else {
-        // some leaf had more entries than its slot: second walk at the offsets,
-        // and a larger slot for the next builds
-        if (over > 0) {
-            int nc = cap;
-            while (nc < over && nc < 4096) nc *= 2;
-            c->walk_cap = nc;
-        }
+        SPH_CHECK_LAUNCH();
+    }
+    if (!one_pass || over > 0) {
+        // leaves with more entries than their slot (all leaves without the
+        // one pass): walked again, writing at the scanned offsets
         k_walk<1><<<blocks_for(nL, 128), 128, 0, c->stream>>>(
             nL, (const int*)c->leaf_node.p, (const WNode*)c->wnodes.p, (const double*)c->l_lo.p,
             (const double*)c->l_hi.p, (const int*)c->l_dom.p, (const int*)c->l_cnt.p, (const DomainInfo*)c->dom_d.p,
-            (const double*)c->l_hlist.p, nullptr, (const int*)c->l_off.p, (ListEntry*)c->list.p, total, with_dir,
-            sym, flags);
+            (const double*)c->l_hlist.p, nullptr, (const int*)c->l_off.p, (ListEntry*)c->list.p,
+            one_pass ? cap : 0, with_dir, sym, flags);
+        SPH_CHECK_LAUNCH();
     }
-    SPH_CHECK_LAUNCH();
+    // slot for the next build: the power of two at or above twice the mean
+    {
+        const int64_t mean2 = 2 * ((int64_t)total + nL - 1) / std::max(nL, 1);
+        int nc = 16;
+        while (nc < mean2 && nc < 4096) nc *= 2;
+        c->walk_cap = nc;
+    }
     c->n_list = total;
     c->pair_tasks_valid = false;
     // particle lists follow every new set of cell lists
@@ -1200,11 +1212,14 @@ sph_status sort_all(sph_ctx* c)
 // Keep the cells and lists of the last build for a step: refresh the
 // cell-relative coordinates and check every leaf against the displacement
 // margin.  *fresh = false when a rebuild is needed.
+// With fresh = NULL the test's flag is left on the device (the caller reads
+// it together with other values) and the margin is the one on the device.
 sph_status refresh_leaves(sph_ctx* c, bool* fresh)
 {
     int* flags = (int*)c->flags.p;
     SPH_CHECK_HIP(hipMemsetAsync(flags, 0, sizeof(int), c->stream));
-    SPH_CHECK_HIP(hipMemcpyAsync(c->dparam.p, &c->margin_h, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if (fresh)
+        SPH_CHECK_HIP(hipMemcpyAsync(c->dparam.p, &c->margin_h, sizeof(double), hipMemcpyHostToDevice, c->stream));
     const int nL = c->n_leaves;
     if (c->prm.precision == SPH_FP64)
         k_leaf_refresh<double><<<blocks_for(nL, 4), 256, 0, c->stream>>>(
@@ -1221,6 +1236,7 @@ sph_status refresh_leaves(sph_ctx* c, bool* fresh)
             (const double*)c->l_lo.p, (const double*)c->l_hi.p, (const int*)c->leaf_node.p, (const Node*)c->nodes.p,
             c->D, 2.0 * SPH_FP32_EXTENT_RATIO);
     SPH_CHECK_LAUNCH();
+    if (!fresh) return SPH_OK;
     int fl = 0;
     SPH_TRY(read_int(c, flags, &fl));
     *fresh = !(fl & FLAG_STALE);

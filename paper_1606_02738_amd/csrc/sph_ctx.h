@@ -2,17 +2,44 @@
 // translation units.  Not part of the C-ABI.
 #pragma once
 
+#include <map>
 #include <vector>
 
 #include "sph_internal.h"
 
+// Device memory of the library: blocks carved from a caller-owned workspace
+// (first fit over a free list, neighbours merged on release).  The library
+// itself never allocates device memory.
+struct Pool {
+    char* base = nullptr;
+    size_t size = 0;
+    std::map<size_t, size_t> free_blocks;  // offset -> bytes
+    size_t in_use = 0, high = 0;
+    size_t needed = 0;  // in-use bytes plus the request that did not fit (0: none failed)
+    void init(void* mem, size_t bytes);
+    void* take(size_t bytes);
+    void give(void* p, size_t bytes);
+};
+
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
+    Pool* pool = nullptr;
+};
+
+// The pool the calls on this host thread carve from: set by every C-ABI entry
+// point for its duration (the context's pool, or one over the workspace a
+// context-free call is given).
+extern thread_local Pool* g_pool;
+struct PoolScope {
+    Pool* prev;
+    explicit PoolScope(Pool* p) : prev(g_pool) { g_pool = p; }
+    ~PoolScope() { g_pool = prev; }
 };
 
 struct sph_ctx {
     sph_params prm;
+    Pool pool;                   // over the caller's workspace
     std::vector<double> boxes;   // n_domains x 3
     hipStream_t stream = nullptr;
 
@@ -44,6 +71,10 @@ struct sph_ctx {
 
     // counters of the last calls
     sph_stats st{};
+    bool force_pending = false;   // the last force call's counts are still on the device
+    bool sums_pending = false;    // the last step's FP64 totals are still on the device
+    const double* sums_dev = nullptr;
+    unsigned long long stale_h[2] = {0, 0};
 
     // device buffers
     DevBuf dom_d, dstat;          // DomainInfo[], per-domain (hmax, hmin) as u64 bits and particle count
@@ -103,7 +134,9 @@ struct sph_ctx {
     DevBuf fgrid, fcount;               // FeatGrid[], per-cell counts
     DevBuf mlp_X, mlp_hprev;            // features and previous H of the current step (particle order)
     DevBuf mlp_params, mlp_packed, mlp_m, mlp_v;
-    DevBuf ds_X, ds_y, ds_count;        // recorded samples
+    float* ds_X = nullptr;              // recorded samples (the caller's buffers)
+    float* ds_y = nullptr;
+    DevBuf ds_count;
     bool rec_on = false, h_pred = false, mlp_ready = false, mlp_have = false, mlp_pending = false;
     int64_t rec_cap = 0;
     double rec_rate = 0.0;

@@ -1492,15 +1492,89 @@ static sph_status density_loop(sph_ctx* c, int done_sweeps, unsigned long long u
     return unconv ? SPH_ERR_NOT_CONVERGED : SPH_OK;
 }
 
+// Density stage: the first sweeps run as a gated sequence on the device (the
+// same gate the graph mode uses: after each sweep a one-thread kernel turns
+// the gate to "converged" or "the host must take over"), so the common case
+// costs one readback for the whole stage; the host loop continues from there
+// when more sweeps, a relist or a rebuild are needed.
+#define SPH_GATED_SWEEPS 3
+
+__global__ void k_graph_begin(unsigned long long* cnt, int* flags, int* gate);
+__global__ void k_sweep_begin(unsigned long long* cnt, int* flags, const int* gate);
+__global__ void k_sweep_end(unsigned long long* cnt, const int* flags, int* gate);
+
 sph_status density_all(sph_ctx* c)
 {
     if (!c->sorted) return SPH_ERR_STATE;
     SPH_CHECK_HIP(hipEventRecord(c->ev[0], c->stream));
     SPH_TRY(density_reset(c));
-    SPH_CHECK_HIP(hipMemsetAsync(c->counters.p, 0, CNT_NPAIR * 8, c->stream));
-    const sph_status s = density_loop(c, 0, 1ull);
+    int* gate = (int*)c->flags.p + FI_GATE;
+    unsigned long long* cnt = (unsigned long long*)c->counters.p;
+    int* flags = (int*)c->flags.p;
+    const int sweeps = std::min(SPH_GATED_SWEEPS, c->prm.max_h_iter);
+    k_graph_begin<<<1, 64, 0, c->stream>>>(cnt, flags, gate);
+    SPH_CHECK_LAUNCH();
+    SPH_CHECK_HIP(hipEventRecord(c->kev[0], c->stream));
+    for (int k = 0; k < sweeps; k++) {
+        k_sweep_begin<<<1, 64, 0, c->stream>>>(cnt, flags, gate);
+        SPH_TRY(launch_density(c, gate));
+        k_sweep_end<<<1, 64, 0, c->stream>>>(cnt, flags, gate);
+        SPH_CHECK_LAUNCH();
+    }
+    SPH_CHECK_HIP(hipEventRecord(c->kev[1], c->stream));
+    int hfl[FI_GATE + 1];
+    unsigned long long hc[CNT_N];
+    SPH_CHECK_HIP(hipMemcpyAsync(hfl, c->flags.p, sizeof(hfl), hipMemcpyDeviceToHost, c->stream));
+    SPH_CHECK_HIP(hipMemcpyAsync(hc, c->counters.p, sizeof(hc), hipMemcpyDeviceToHost, c->stream));
+    SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
+    const int g = hfl[FI_GATE], fl = hfl[FI_FLAGS];
+    const int done = (int)hc[CNT_GSWEEPS];
+    {
+        float ms = 0.f;
+        SPH_CHECK_HIP(hipEventElapsedTime(&ms, c->kev[0], c->kev[1]));
+        c->st.t_density_kernels_ms = ms;
+    }
+    c->st.n_density_launches = done;
+    c->st.n_dens_evals = (int64_t)hc[CNT_DEVAL];
+    for (int k = 0; k < 8; k++)
+        c->st.unconv_after[k] = k < done && k < CNT_N - CNT_UHIST
+                                    ? (int)std::min<unsigned long long>(hc[CNT_UHIST + k], INT32_MAX)
+                                    : -1;
+    sph_status st = SPH_OK;
+    if (g == 1 && (c->prm.precision == SPH_FP64 || c->in_step)) {
+        // converged (the FP32 extent check after a cold start runs in the host loop)
+        c->st.sweeps = done;
+        c->st.n_unconverged = 0;
+        c->st.n_dens = (int64_t)hc[CNT_NDENS];
+        c->dens_done = true;
+        c->ghost_done = false;
+        c->force_done = false;
+    } else if (g == 1) {
+        st = density_loop(c, done - 1, 1ull);
+    } else {
+        if (fl & FLAG_BOX_SMALL) {
+            c->st.sweeps = done;
+            c->st.n_unconverged = (int)std::min<unsigned long long>(hc[CNT_UNCONV], INT32_MAX);
+            st = SPH_ERR_BOX_TOO_SMALL;
+        } else {
+            if ((fl & FLAG_REBUILD) || ((fl & FLAG_RELIST) && c->delta > 0.0)) {
+                SPH_TRY(build_all(c));
+                SPH_TRY(sort_all(c));
+                k_density_reset<<<blocks_for(std::max<int64_t>(c->n, c->n_leaves), 256), 256, 0, c->stream>>>(
+                    c->n, c->n_leaves, (double*)c->hlo.p, (double*)c->hhi.p, (uint8_t*)c->conv.p,
+                    (int*)c->l_active.p, nullptr);
+                SPH_CHECK_LAUNCH();
+                SPH_CHECK_HIP(hipMemsetAsync(&cnt[CNT_NDENS], 0, 8, c->stream));
+                c->st.rebuilds++;
+            } else if (fl & FLAG_RELIST) {
+                SPH_TRY(relist(c));
+                c->st.relists++;
+            }
+            st = density_loop(c, done, hc[CNT_UNCONV]);
+        }
+    }
     SPH_CHECK_HIP(hipEventRecord(c->ev[1], c->stream));
-    return s;
+    return st;
 }
 
 static sph_status launch_ghost(sph_ctx* c, const double* u, const double* vx, const double* vy, const double* vz,
@@ -1605,6 +1679,21 @@ static sph_status launch_force(sph_ctx* c, const int* gate, bool graph = false)
     return SPH_OK;
 }
 
+// Running totals of the interaction counters (device, no host round trip):
+// the force stage's N_force (ordered, as counted) and N_dens are added to
+// CNT_NFORCE_SUM / CNT_NDENS_SUM after every force launch.
+__global__ void k_count_totals(unsigned long long* cnt, const int* gate)
+{
+    if (gate && *gate != 1) return;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        cnt[CNT_NFORCE_SUM] += cnt[CNT_NFORCE];
+        cnt[CNT_NDENS_SUM] += cnt[CNT_NDENS_F];
+        cnt[CNT_FORCE_CALLS] += 1ull;
+    }
+}
+
+// Force stage, asynchronous: the counts and the kernel's duration are read by
+// sph_get_stats (force_pending).
 sph_status force_all(sph_ctx* c)
 {
     if (!c->ghost_done) return SPH_ERR_STATE;
@@ -1622,19 +1711,10 @@ sph_status force_all(sph_ctx* c)
     SPH_CHECK_HIP(hipEventRecord(c->kev[2], c->stream));
     SPH_TRY(launch_force(c, nullptr));
     SPH_CHECK_HIP(hipEventRecord(c->kev[3], c->stream));
+    k_count_totals<<<1, 64, 0, c->stream>>>(cnt, nullptr);
+    SPH_CHECK_LAUNCH();
     SPH_CHECK_HIP(hipEventRecord(c->ev[5], c->stream));
-    unsigned long long nf = 0, ndf = 0;
-    SPH_CHECK_HIP(hipMemcpyAsync(&nf, &cnt[CNT_NFORCE], 8, hipMemcpyDeviceToHost, c->stream));
-    SPH_CHECK_HIP(hipMemcpyAsync(&ndf, &cnt[CNT_NDENS_F], 8, hipMemcpyDeviceToHost, c->stream));
-    SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
-    {
-        float ms = 0.f;
-        SPH_CHECK_HIP(hipEventElapsedTime(&ms, c->kev[2], c->kev[3]));
-        c->st.t_force_kernel_ms = ms;
-    }
-    // the gather form counts every pair from both sides
-    c->st.n_force = (int64_t)(c->prm.force_mode == SPH_FORCE_GATHER ? nf / 2 : nf);
-    c->st.n_dens = (int64_t)ndf;  // exact at the final H
+    c->force_pending = true;
     c->force_done = true;
     return SPH_OK;
 }
@@ -1655,8 +1735,11 @@ sph_status force_all(sph_ctx* c)
 __global__ void k_graph_begin(unsigned long long* cnt, int* flags, int* gate)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        for (int k = 0; k < CNT_NPAIR; k++) cnt[k] = 0ull;
-        cnt[CNT_NDENS_F] = 0ull;
+        // the force stage's counters are left to the force stage (they may
+        // still be unread by the host)
+        cnt[CNT_UNCONV] = 0ull;
+        cnt[CNT_NDENS] = 0ull;
+        cnt[CNT_DEVAL] = 0ull;
         cnt[CNT_GSWEEPS] = 0ull;
         for (int k = CNT_UHIST; k < CNT_N; k++) cnt[k] = 0ull;
         flags[FI_FLAGS] = 0;
@@ -1781,6 +1864,7 @@ static sph_status capture_dgf(sph_ctx* c, const double* u, const double* vx, con
     k_force_zero<<<blocks_for(c->n, 256), 256, 0, c->stream>>>(c->n, c->P.ax, c->P.ay, c->P.az, c->P.dudt, c->P.nngb,
                                                               cnt, gate);
     if (st == SPH_OK) st = launch_force(c, gate, true);
+    k_count_totals<<<1, 64, 0, c->stream>>>(cnt, gate);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(c->stream, &g);
     c->stream = user;
@@ -1885,6 +1969,11 @@ static sph_status sums_impl(sph_ctx* c, double* host_out, KickArgs kick)
     SPH_CHECK_LAUNCH();
     k_sums_final<<<nd, 256, 0, c->stream>>>(part, out, chunks);
     SPH_CHECK_LAUNCH();
+    c->sums_dev = out;
+    if (!host_out) {
+        c->sums_pending = true;  // read by sph_get_stats
+        return SPH_OK;
+    }
     SPH_CHECK_HIP(hipMemcpyAsync(host_out, out, (size_t)nd * 5 * 8, hipMemcpyDeviceToHost, c->stream));
     SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
     return SPH_OK;
@@ -1908,6 +1997,22 @@ sph_status step_all(sph_ctx* c, double dt)
     return s;
 }
 
+// Displacement bound of the kept lists, on the device: margin += 2 vmax dt.
+__global__ void k_margin(double* dparam, double dt)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double v;
+        const unsigned long long b = ((const unsigned long long*)dparam)[1];
+        memcpy(&v, &b, 8);
+        dparam[0] += 2.0 * v * dt;
+    }
+}
+
+// One step.  The host reads the device once before the density stage (the
+// step's largest speed and whether the kept cells and lists are still valid:
+// the cell build is host-driven) and once inside the density stage; the
+// force, the closing kick and the FP64 totals are enqueued without waiting
+// (the totals are read by sph_get_stats).
 static sph_status step_impl(sph_ctx* c, double dt)
 {
     if (!c->force_done) return SPH_ERR_STATE;
@@ -1929,17 +2034,38 @@ static sph_status step_impl(sph_ctx* c, double dt)
         k_h_drift<<<nb, 256, 0, c->stream>>>(c->n, c->P.H, c->P.u, c->P.dudt, c->prm.gamma - 1.0, dt);
         SPH_CHECK_LAUNCH();
     }
-    double vmax = 0.0;
-    SPH_CHECK_HIP(hipMemcpyAsync(&vmax, vmax_bits, 8, hipMemcpyDeviceToHost, c->stream));
-    SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
     SPH_CHECK_HIP(hipEventRecord(c->ev[6], c->stream));
-    bool fresh = false;
-    if (c->prm.rebuild_steps > 0 && c->built) {
+    const bool keep = c->prm.rebuild_steps > 0 && c->built;
+    if (keep) {
         // keep the cells and lists while the displacement margin allows
-        c->delta += vmax * dt;
-        c->margin_h = 2.0 * c->delta;
-        if (c->prm.lists == SPH_LISTS_PARTICLE) SPH_TRY(plist_refresh(c, &fresh));
-        else SPH_TRY(refresh_leaves(c, &fresh));
+        k_margin<<<1, 64, 0, c->stream>>>((double*)c->dparam.p, dt);
+        SPH_CHECK_LAUNCH();
+        if (c->prm.lists == SPH_LISTS_PARTICLE) SPH_TRY(plist_refresh(c, nullptr));
+        else SPH_TRY(refresh_leaves(c, nullptr));
+    }
+    double dp[2] = {0.0, 0.0};
+    int fl = 0;
+    SPH_CHECK_HIP(hipMemcpyAsync(dp, c->dparam.p, 16, hipMemcpyDeviceToHost, c->stream));
+    SPH_CHECK_HIP(hipMemcpyAsync(&fl, c->flags.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    if (keep && c->prm.lists == SPH_LISTS_PARTICLE)
+        SPH_CHECK_HIP(hipMemcpyAsync(c->stale_h, (unsigned long long*)c->counters.p + CNT_STALE_MOVED, 16,
+                                     hipMemcpyDeviceToHost, c->stream));
+    SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
+    double vmax;
+    {
+        unsigned long long b;
+        memcpy(&b, &dp[1], 8);
+        memcpy(&vmax, &b, 8);
+    }
+    bool fresh = false;
+    if (keep) {
+        c->margin_h = dp[0];
+        c->delta = 0.5 * dp[0];
+        fresh = !(fl & FLAG_STALE);
+        if (c->prm.lists == SPH_LISTS_PARTICLE) {
+            c->st.stale_moved = (int64_t)c->stale_h[0];
+            c->st.stale_grown = (int64_t)c->stale_h[1];
+        }
     }
     if (fresh) {
         c->steps_since_build++;
@@ -1967,13 +2093,7 @@ static sph_status step_impl(sph_ctx* c, double dt)
     if (s != SPH_OK) return s;
     SPH_TRY(mlp_post_step(c));
     // closing half kick, fused with the FP64 totals of the kicked state
-    std::vector<double> sums((size_t)c->prm.n_domains * 5);
     KickArgs kick{c->P.ax, c->P.ay, c->P.az, c->P.dudt, 0.5 * dt};
-    SPH_TRY(sums_impl(c, sums.data(), kick));
-    for (int k = 0; k < 5; k++) {
-        double t = 0.0;
-        for (int d = 0; d < c->prm.n_domains; d++) t += sums[5 * d + k];
-        c->st.conserved[k] = t;
-    }
+    SPH_TRY(sums_impl(c, nullptr, kick));
     return SPH_OK;
 }

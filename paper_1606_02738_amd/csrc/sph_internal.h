@@ -68,6 +68,10 @@ struct WNode {
 // sort direction to use for the pair.  A's list holds every leaf B whose
 // bounding box (image) lies closer than h_A (the radius the list was built
 // for), i.e. the cells the density gather of A needs.
+// Bytes per particle the one-pass list walk may hold in per-leaf slots
+// (leaves with more entries than their slot are walked a second time).
+#define SPH_WALK_SLOT_BYTES 64
+
 struct ListEntry {
     int B;
     int code;         // shift index (0..26) | dir << 8
@@ -126,7 +130,9 @@ enum { CNT_UNCONV = 0, CNT_NDENS = 1, CNT_NFORCE = 2, CNT_NPLIST = 3, CNT_DEVAL 
 enum { XQ_N = 8, XQ_STRIDE = 16, XQ_FORCE = CNT_N };
 // Particle lists: particles whose list failed the validity test of the last
 // drift, by reason (moved beyond the skin, H beyond the list radius).
-enum { CNT_STALE_MOVED = CNT_N + XQ_N * XQ_STRIDE, CNT_STALE_GROWN, CNT_ALLOC };
+enum { CNT_STALE_MOVED = CNT_N + XQ_N * XQ_STRIDE, CNT_STALE_GROWN,
+       // running totals of the force stage's counts since sph_create
+       CNT_NFORCE_SUM, CNT_NDENS_SUM, CNT_FORCE_CALLS, CNT_ALLOC };
 
 // Leaf arrays (device SoA).
 struct LeafArrays {

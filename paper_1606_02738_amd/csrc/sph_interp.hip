@@ -279,6 +279,7 @@ extern "C" sph_status sph_interpolate(sph_ctx* c, const double* Q, const double*
 {
     if (!c || m_pts < 0 || ((!Q || !px || !py || !pz || !out) && m_pts > 0)) return SPH_ERR_INVALID;
     if (c->prm.n_domains > 1 && !pdom && m_pts > 0) return SPH_ERR_INVALID;
+    PoolScope ps(&c->pool);
     if (!c->dens_done) return SPH_ERR_STATE;
     if (m_pts == 0) return SPH_OK;
     if (m_pts > INT32_MAX) return SPH_ERR_INVALID;

@@ -749,7 +749,7 @@ sph_status mlp_post_step(sph_ctx* c)
     if (c->mlp_pending && c->rec_on && c->rec_cap > 0) {
         k_record<<<nblocks(c->n, 256), 256, 0, c->stream>>>(
             c->n, (const float*)c->mlp_X.p, c->P.H, (const double*)c->mlp_hprev.p, c->P.id, c->rec_seed,
-            (uint64_t)c->step_count, c->rec_rate, (float*)c->ds_X.p, (float*)c->ds_y.p, (unsigned int)c->rec_cap,
+            (uint64_t)c->step_count, c->rec_rate, c->ds_X, c->ds_y, (unsigned int)c->rec_cap,
             (unsigned int*)c->ds_count.p);
         SPH_CHECK_LAUNCH();
     }
@@ -768,42 +768,59 @@ static sph_status ensure_params(sph_ctx* c)
 
 extern "C" {
 
-sph_status sph_mlp_forward(const float* params, const float* X, int64_t n, float* y, void* hip_stream)
+// Scratch of the context-free calls over n rows: packed weights, partial
+// gradients of each workgroup (k_mlp_fb, MB rows each) and the loss slot.
+static size_t mlp_scratch_bytes(int64_t n)
+{
+    const size_t nwg = (size_t)std::max<int64_t>(1, nblocks(std::max<int64_t>(n, 1), MB));
+    const size_t r = 256;
+    auto up = [&](size_t b) { return (b + r - 1) / r * r + r; };
+    return up(sizeof(MlpPacked)) + up(nwg * NT * sizeof(float)) + up(nwg * sizeof(float)) + up(sizeof(float)) +
+           ((size_t)4 << 10);
+}
+
+sph_status sph_mlp_workspace_size(int64_t n, size_t* bytes)
+{
+    if (n < 0 || !bytes) return SPH_ERR_INVALID;
+    *bytes = mlp_scratch_bytes(n);
+    return SPH_OK;
+}
+
+sph_status sph_mlp_forward(const float* params, const float* X, int64_t n, float* y, void* workspace, size_t bytes,
+                           void* hip_stream)
 {
     if (n < 0 || ((!params || !X || !y) && n > 0)) return SPH_ERR_INVALID;
     if (n == 0) return SPH_OK;
+    if (!workspace) return SPH_ERR_INVALID;
     const hipStream_t s = (hipStream_t)hip_stream;
-    MlpPacked* w = nullptr;
-    SPH_CHECK_HIP(hipMalloc(&w, sizeof(MlpPacked)));
-    sph_status st = pack(params, w, s);
-    if (st == SPH_OK) {
-        k_mlp_infer<<<infer_grid(n), 256, 0, s>>>(w, X, n, y, nullptr, 0.f);
-        if (hipGetLastError() != hipSuccess) st = SPH_ERR_HIP;
-    }
-    if (hipStreamSynchronize(s) != hipSuccess) st = SPH_ERR_HIP;
-    (void)hipFree(w);
-    return st;
+    Pool pool;
+    pool.init(workspace, bytes);
+    PoolScope ps(&pool);
+    DevBuf w;
+    SPH_TRY(buf_ensure(w, sizeof(MlpPacked)));
+    SPH_TRY(pack(params, (MlpPacked*)w.p, s));
+    k_mlp_infer<<<infer_grid(n), 256, 0, s>>>((const MlpPacked*)w.p, X, n, y, nullptr, 0.f);
+    SPH_CHECK_LAUNCH();
+    return SPH_OK;
 }
 
 sph_status sph_mlp_loss_grad(const float* params, const float* X, const float* y, int64_t n, float* grad,
-                             double* loss, void* hip_stream)
+                             double* loss, void* workspace, size_t bytes, void* hip_stream)
 {
-    if (n <= 0 || !params || !X || !y || !grad) return SPH_ERR_INVALID;
+    if (n <= 0 || !params || !X || !y || !grad || !workspace) return SPH_ERR_INVALID;
     const hipStream_t s = (hipStream_t)hip_stream;
+    Pool pool;
+    pool.init(workspace, bytes);
+    PoolScope ps(&pool);
     TrainScratch S;
-    sph_status st = buf_ensure(S.loss, sizeof(float));
-    if (st == SPH_OK)
-        st = minibatch(S, params, X, y, n, 0, n, 1, 0, grad, nullptr, nullptr, nullptr, false, 0.f, 0.f, 0.f, 0.f, 0,
-                       (float*)S.loss.p, s);
+    SPH_TRY(buf_ensure(S.loss, sizeof(float)));
+    SPH_TRY(minibatch(S, params, X, y, n, 0, n, 1, 0, grad, nullptr, nullptr, nullptr, false, 0.f, 0.f, 0.f, 0.f, 0,
+                      (float*)S.loss.p, s));
     float L = 0.f;
-    if (st == SPH_OK && hipMemcpyAsync(&L, S.loss.p, sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess)
-        st = SPH_ERR_HIP;
-    if (hipStreamSynchronize(s) != hipSuccess) st = SPH_ERR_HIP;
+    SPH_CHECK_HIP(hipMemcpyAsync(&L, S.loss.p, sizeof(float), hipMemcpyDeviceToHost, s));
+    SPH_CHECK_HIP(hipStreamSynchronize(s));
     if (loss) *loss = L;
-    buf_free(S.part);
-    buf_free(S.part_loss);
-    buf_free(S.loss);
-    return st;
+    return SPH_OK;
 }
 
 sph_status sph_mlp_adam(float* params, float* m, float* v, const float* grad, int t, float lr, float beta1,
@@ -820,27 +837,31 @@ sph_status sph_mlp_adam(float* params, float* m, float* v, const float* grad, in
 sph_status sph_h_features(sph_ctx* c, double dt, float* X)
 {
     if (!c || !X) return SPH_ERR_INVALID;
+    PoolScope ps(&c->pool);
     if (!c->built) return SPH_ERR_STATE;
     return mlp_features(c, dt, X, nullptr);
 }
 
-sph_status sph_h_record(sph_ctx* c, int64_t capacity, double rate, uint64_t seed, int64_t* held)
+sph_status sph_h_record(sph_ctx* c, float* X, float* y, int64_t capacity, double rate, uint64_t seed,
+                        int64_t* held)
 {
     if (!c || capacity < 0 || capacity > INT32_MAX || !(rate >= 0.0 && rate <= 1.0)) return SPH_ERR_INVALID;
+    if (capacity > 0 && (!X || !y)) return SPH_ERR_INVALID;
+    PoolScope ps(&c->pool);
     if (capacity == 0) {
         c->rec_on = false;
         c->rec_cap = 0;
-        buf_free(c->ds_X);
-        buf_free(c->ds_y);
+        c->ds_X = nullptr;
+        c->ds_y = nullptr;
         if (held) *held = 0;
         return SPH_OK;
     }
-    if (!c->rec_on || capacity != c->rec_cap) {
-        SPH_TRY(buf_ensure(c->ds_X, (size_t)capacity * XS * sizeof(float)));
-        SPH_TRY(buf_ensure(c->ds_y, (size_t)capacity * sizeof(float)));
+    if (!c->rec_on || capacity != c->rec_cap || X != c->ds_X || y != c->ds_y) {
         SPH_TRY(buf_ensure(c->ds_count, sizeof(unsigned int)));
         SPH_CHECK_HIP(hipMemsetAsync(c->ds_count.p, 0, sizeof(unsigned int), c->stream));
     }
+    c->ds_X = X;
+    c->ds_y = y;
     c->rec_on = true;
     c->rec_cap = capacity;
     c->rec_rate = rate;
@@ -857,6 +878,7 @@ sph_status sph_h_record(sph_ctx* c, int64_t capacity, double rate, uint64_t seed
 sph_status sph_h_train(sph_ctx* c, int epochs, int batch, double lr, uint64_t seed, int init, double* loss)
 {
     if (!c || epochs < 0 || batch < 1 || !(lr > 0.0)) return SPH_ERR_INVALID;
+    PoolScope ps(&c->pool);
     if (!c->ds_count.p || c->rec_cap <= 0) return SPH_ERR_STATE;
     unsigned int h = 0;
     SPH_CHECK_HIP(hipMemcpyAsync(&h, c->ds_count.p, sizeof(h), hipMemcpyDeviceToHost, c->stream));
@@ -865,8 +887,8 @@ sph_status sph_h_train(sph_ctx* c, int epochs, int batch, double lr, uint64_t se
     if (N < 2) return SPH_ERR_STATE;
     if (!init && !c->mlp_have) return SPH_ERR_STATE;
     SPH_TRY(ensure_params(c));
-    const float* dX = (const float*)c->ds_X.p;
-    const float* dy = (const float*)c->ds_y.p;
+    const float* dX = c->ds_X;
+    const float* dy = c->ds_y;
     if (init) {
         // standardisation from the samples, fresh weights, zero moments
         DevBuf mom;
@@ -948,6 +970,7 @@ sph_status sph_h_train(sph_ctx* c, int epochs, int batch, double lr, uint64_t se
 sph_status sph_h_set_params(sph_ctx* c, const float* params)
 {
     if (!c || !params) return SPH_ERR_INVALID;
+    PoolScope ps(&c->pool);
     for (int k = 0; k < NIN; k++)
         if (!(params[O_XSD + k] != 0.0f)) return SPH_ERR_INVALID;
     if (!(params[O_YSD] == params[O_YSD])) return SPH_ERR_INVALID;

@@ -979,7 +979,7 @@ sph_status plist_build(sph_ctx* c)
     SPH_CHECK_HIP(hipMemcpyAsync(&ne, &cnt[CNT_NPLIST], 8, hipMemcpyDeviceToHost, c->stream));
     SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
     if (fl & FLAG_INVALID) return SPH_ERR_INVALID;  // a chunk's union exceeds 16-bit positions
-    if (tot[0] < 0 || tot[1] < 0 || (int64_t)tot[1] * 64 > ((int64_t)1 << 40)) return SPH_ERR_ALLOC;
+    if (tot[0] < 0 || tot[1] < 0 || (int64_t)tot[1] * 64 > ((int64_t)1 << 40)) return SPH_ERR_WORKSPACE;
     c->n_union = tot[0];
     c->plist_rows = tot[1];
     c->n_plist = (int64_t)ne;
@@ -1030,7 +1030,8 @@ sph_status plist_ext(sph_ctx* c, bool final, double* boxmax_host)
     return SPH_OK;
 }
 
-// Kept lists after a drift: new fixed-point positions and the validity test.
+// Kept lists after a drift: new fixed-point positions and the validity test
+// (fresh = NULL: the flag and the counts stay on the device for the caller).
 sph_status plist_refresh(sph_ctx* c, bool* fresh)
 {
     int* flags = (int*)c->flags.p;
@@ -1049,6 +1050,7 @@ sph_status plist_refresh(sph_ctx* c, bool* fresh)
             (const float*)c->pR.p, (const float*)c->pskin.p, (const PQ<float>*)c->pq0.p, (PQ<float>*)c->pq.p,
             (float4*)c->prem.p, flags, cnt);
     SPH_CHECK_LAUNCH();
+    if (!fresh) return SPH_OK;  // the caller reads the flag and the counts
     int fl = 0;
     unsigned long long why[2] = {0, 0};
     SPH_CHECK_HIP(hipMemcpyAsync(&fl, flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));

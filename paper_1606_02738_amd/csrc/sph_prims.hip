@@ -61,7 +61,7 @@ static sph_status scan_rec(sph_ctx* c, const int* in, int* out, int n, int* d_to
         SPH_CHECK_LAUNCH();
         return SPH_OK;
     }
-    if (tmp_left < nb) return SPH_ERR_ALLOC;
+    if (tmp_left < nb) return SPH_ERR_WORKSPACE;
     int* bs = tmp;
     k_scan_block<<<nb, SCAN_T, 0, c->stream>>>(in, out, n, bs);
     SPH_CHECK_LAUNCH();

@@ -1,9 +1,11 @@
 """ctypes binding of libsph_hip (the C-ABI in include/sph.h).
 
 Argument marshalling only: every stage runs in the library's HIP kernels.
-Particle arrays are torch tensors on the GPU (float64 unless stated); torch
-provides device memory and the stream, nothing else.  If the library is not
-built this module raises at import of :func:`lib` -- there is no CPU path.
+Particle arrays are torch tensors on the GPU (float64 unless stated), and so
+is the workspace the library carves its device buffers from (a uint8 tensor
+sized by sph_workspace_size); torch provides device memory and the stream,
+nothing else.  If the library is not built this module raises at import of
+:func:`lib` -- there is no CPU path.
 """
 from __future__ import annotations
 
@@ -28,8 +30,9 @@ SPH_LISTS_CELL, SPH_LISTS_PARTICLE = 0, 1
 LIST_MODES = {"cell": SPH_LISTS_CELL, "particle": SPH_LISTS_PARTICLE}
 
 STATUS = {0: "SPH_OK", -1: "SPH_ERR_INVALID", -2: "SPH_ERR_HIP", -3: "SPH_ERR_NOT_CONVERGED",
-          -4: "SPH_ERR_H_EXCEEDS_CELL", -5: "SPH_ERR_BOX_TOO_SMALL", -6: "SPH_ERR_ALLOC",
+          -4: "SPH_ERR_H_EXCEEDS_CELL", -5: "SPH_ERR_BOX_TOO_SMALL", -6: "SPH_ERR_WORKSPACE",
           -7: "SPH_ERR_STATE"}
+WORKSPACE_MIN = 1 << 20
 
 FLOAT_FIELDS = ("x", "y", "z", "vx", "vy", "vz", "u", "m", "H", "rho", "drho_dH", "omega", "P",
                 "ax", "ay", "az", "dudt")
@@ -69,7 +72,10 @@ class Stats(C.Structure):
                 ("unconv_after", C.c_int32 * 8), ("t_predict_ms", C.c_double),
                 ("steps_since_build", C.c_int64), ("n_builds", C.c_int64), ("list_margin", C.c_double),
                 ("n_chunks", C.c_int64), ("n_plist", C.c_int64), ("n_union", C.c_int64),
-                ("stale_moved", C.c_int64), ("stale_grown", C.c_int64)]
+                ("stale_moved", C.c_int64), ("stale_grown", C.c_int64),
+                ("workspace_bytes", C.c_int64), ("workspace_in_use", C.c_int64),
+                ("workspace_high", C.c_int64), ("workspace_needed", C.c_int64),
+                ("n_force_total", C.c_int64), ("n_dens_total", C.c_int64), ("force_calls", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -79,7 +85,7 @@ class Stats(C.Structure):
 
 
 _lib = None
-EXPORTS = ("sph_create", "sph_destroy", "sph_build_cells", "sph_sort_cells", "sph_density",
+EXPORTS = ("sph_workspace_size", "sph_mlp_workspace_size", "sph_create", "sph_destroy", "sph_build_cells", "sph_sort_cells", "sph_density",
            "sph_ghost", "sph_force", "sph_density_ghost_force", "sph_step", "sph_get_stats", "sph_domain_sums",
            "sph_status_str", "sph_version", "sph_mlp_forward", "sph_mlp_loss_grad", "sph_mlp_adam",
            "sph_h_features", "sph_h_record", "sph_h_train", "sph_h_set_params", "sph_h_get_params",
@@ -96,7 +102,9 @@ def lib():
             raise RuntimeError("libsph_hip.so is not built (run paper_1606_02738_amd/build.py)")
         L = C.CDLL(LIB_PATH)
         vp = C.c_void_p
-        L.sph_create.argtypes = [C.POINTER(Params), vp, C.POINTER(vp)]
+        L.sph_workspace_size.argtypes = [C.POINTER(Params), C.c_int64, C.POINTER(C.c_size_t)]
+        L.sph_mlp_workspace_size.argtypes = [C.c_int64, C.POINTER(C.c_size_t)]
+        L.sph_create.argtypes = [C.POINTER(Params), vp, C.c_size_t, vp, C.POINTER(vp)]
         L.sph_destroy.argtypes = [vp]
         L.sph_build_cells.argtypes = [vp, C.POINTER(Particles)]
         for f in ("sph_sort_cells", "sph_density", "sph_ghost", "sph_force", "sph_density_ghost_force"):
@@ -107,11 +115,11 @@ def lib():
         L.sph_status_str.restype = C.c_char_p
         L.sph_status_str.argtypes = [C.c_int]
         L.sph_version.restype = C.c_char_p
-        L.sph_mlp_forward.argtypes = [vp, vp, C.c_int64, vp, vp]
-        L.sph_mlp_loss_grad.argtypes = [vp, vp, vp, C.c_int64, vp, C.POINTER(C.c_double), vp]
+        L.sph_mlp_forward.argtypes = [vp, vp, C.c_int64, vp, vp, C.c_size_t, vp]
+        L.sph_mlp_loss_grad.argtypes = [vp, vp, vp, C.c_int64, vp, C.POINTER(C.c_double), vp, C.c_size_t, vp]
         L.sph_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, vp]
         L.sph_h_features.argtypes = [vp, C.c_double, vp]
-        L.sph_h_record.argtypes = [vp, C.c_int64, C.c_double, C.c_uint64, C.POINTER(C.c_int64)]
+        L.sph_h_record.argtypes = [vp, vp, vp, C.c_int64, C.c_double, C.c_uint64, C.POINTER(C.c_int64)]
         L.sph_h_train.argtypes = [vp, C.c_int, C.c_int, C.c_double, C.c_uint64, C.c_int, C.POINTER(C.c_double)]
         L.sph_h_set_params.argtypes = [vp, C.POINTER(C.c_float)]
         L.sph_h_get_params.argtypes = [vp, C.POINTER(C.c_float)]
@@ -135,6 +143,13 @@ def _stream_ptr(stream):
     return C.c_void_p(s.cuda_stream)
 
 
+def _mlp_workspace(n, device):
+    import torch
+    b = C.c_size_t()
+    _check(lib().sph_mlp_workspace_size(int(n), C.byref(b)), "sph_mlp_workspace_size")
+    return torch.empty(b.value, dtype=torch.uint8, device=device)
+
+
 def mlp_forward(params, X, stream=None):
     """Network output y (predicted log(H_new/H_prev)) for feature rows X
     (n x 8 float32 device tensor); params: float32 device tensor of MLP_NP."""
@@ -143,8 +158,9 @@ def mlp_forward(params, X, stream=None):
     assert X.dtype == torch.float32 and X.is_contiguous() and X.shape[-1] == MLP_XSTRIDE
     n = X.shape[0]
     y = torch.empty(n, dtype=torch.float32, device=X.device)
-    _check(lib().sph_mlp_forward(params.data_ptr(), X.data_ptr(), n, y.data_ptr(), _stream_ptr(stream)),
-           "sph_mlp_forward")
+    ws = _mlp_workspace(n, X.device)
+    _check(lib().sph_mlp_forward(params.data_ptr(), X.data_ptr(), n, y.data_ptr(), ws.data_ptr(), ws.numel(),
+                                 _stream_ptr(stream)), "sph_mlp_forward")
     return y
 
 
@@ -155,8 +171,10 @@ def mlp_loss_grad(params, X, y, stream=None):
     assert y.dtype == torch.float32 and y.numel() == X.shape[0]
     g = torch.empty(MLP_NT, dtype=torch.float32, device=X.device)
     L = C.c_double()
+    ws = _mlp_workspace(X.shape[0], X.device)
     _check(lib().sph_mlp_loss_grad(params.data_ptr(), X.data_ptr(), y.data_ptr(), X.shape[0], g.data_ptr(),
-                                   C.byref(L), _stream_ptr(stream)), "sph_mlp_loss_grad")
+                                   C.byref(L), ws.data_ptr(), ws.numel(), _stream_ptr(stream)),
+           "sph_mlp_loss_grad")
     return L.value, g
 
 
@@ -200,7 +218,7 @@ class SPH:
     def __init__(self, boxes, precision="fp32c", exec_mode="grid", gamma=5.0 / 3.0, eta=1.2348,
                  kernel_gamma=math.sqrt(10.0 / 3.0), h_tol=None, max_h_iter=40, n_split=64,
                  persistent_wgs=0, prune="box", use_graph=False, rebuild_steps=0, h_drift=True, force=None,
-                 lists="cell", tile=0, stream=None):
+                 lists="cell", tile=0, workspace_bytes=None, stream=None):
         import torch
         self._torch = torch
         b = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(-1, 3))
@@ -226,10 +244,29 @@ class SPH:
         self.params = p
         s = stream if stream is not None else torch.cuda.current_stream()
         self.stream = s
-        h = C.c_void_p()
-        _check(lib().sph_create(C.byref(p), C.c_void_p(s.cuda_stream), C.byref(h)), "sph_create")
-        self.h = h
+        self._ws_bytes = workspace_bytes
+        self.ws = None
+        self.h = C.c_void_p()
+        self._predict = False
         self.t = None
+        # the context checks the parameters now; it is created again with a
+        # workspace sized for the particle set at bind()
+        self._create(4 * WORKSPACE_MIN)
+
+    def workspace_size(self, n):
+        """sph_workspace_size for n particles with this context's parameters."""
+        b = C.c_size_t()
+        _check(lib().sph_workspace_size(C.byref(self.params), int(n), C.byref(b)), "sph_workspace_size")
+        return b.value
+
+    def _create(self, nbytes):
+        torch = self._torch
+        ws = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+        h = C.c_void_p()
+        _check(lib().sph_create(C.byref(self.params), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                C.c_void_p(self.stream.cuda_stream), C.byref(h)), "sph_create")
+        self.h = h
+        self.ws = ws
 
     def close(self):
         if getattr(self, "h", None) and self.h.value:
@@ -237,14 +274,32 @@ class SPH:
                 return
             _lib.sph_destroy(self.h)
             self.h = C.c_void_p()
+        self.ws = None
 
     __del__ = close
 
     def bind(self, t):
-        """Attach device tensors (dict from :func:`to_device`)."""
+        """Attach device tensors (dict from :func:`to_device`).  The context is
+        (re)created with a workspace for this many particles when its
+        workspace is smaller (the predictor's parameters are carried over)."""
         for k in FLOAT_FIELDS:
             v = t[k]
             assert v.is_cuda and v.dtype == self._torch.float64 and v.is_contiguous(), k
+        n = t["x"].numel()
+        # (an empty set keeps the workspace: the library rejects it at the build)
+        need = int(self._ws_bytes) if self._ws_bytes else (self.workspace_size(n) if n > 0 else 0)
+        if self.ws is None or self.ws.numel() < need:
+            keep = None
+            try:
+                keep = self.h_get_params()
+            except SPHError:
+                pass
+            self.close()
+            self._create(need)
+            if keep is not None:
+                self.h_set_params(keep)
+                if self._predict:
+                    self.h_predict(True)
         self.t = t
         P = Particles()
         P.n = t["x"].numel()
@@ -302,9 +357,21 @@ class SPH:
 
     def h_record(self, capacity, rate=1.0, seed=1):
         """Start (capacity > 0) or stop (0) recording training samples in
-        sph_step; returns the number held."""
+        sph_step into device tensors this object keeps; returns the number
+        held."""
+        torch = self._torch
         held = C.c_int64()
-        _check(lib().sph_h_record(self.h, int(capacity), float(rate), int(seed), C.byref(held)), "sph_h_record")
+        if capacity > 0:
+            rec = getattr(self, "_rec", None)
+            if rec is None or rec[1].numel() != capacity:
+                rec = (torch.empty((capacity, MLP_XSTRIDE), dtype=torch.float32, device="cuda"),
+                       torch.empty(capacity, dtype=torch.float32, device="cuda"))
+                self._rec = rec
+            _check(lib().sph_h_record(self.h, rec[0].data_ptr(), rec[1].data_ptr(), int(capacity), float(rate),
+                                      int(seed), C.byref(held)), "sph_h_record")
+        else:
+            _check(lib().sph_h_record(self.h, None, None, 0, float(rate), int(seed), C.byref(held)), "sph_h_record")
+            self._rec = None
         return held.value
 
     def h_train(self, epochs, batch=16384, lr=1e-3, seed=1, init=True):
@@ -327,6 +394,7 @@ class SPH:
 
     def h_predict(self, on=True):
         _check(lib().sph_h_predict(self.h, int(bool(on))), "sph_h_predict")
+        self._predict = bool(on)
 
     def stats(self):
         s = Stats()
