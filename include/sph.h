@@ -330,6 +330,8 @@ sph_status sph_interpolate(sph_ctx* ctx, const double* Q, const double* px, cons
 #define SPH_MLP_NH 64
 #define SPH_MLP_NT 9473
 #define SPH_MLP_NP 9507
+/* Rows one sph_mlp_loss_grad call takes at most (row indices are 32-bit). */
+#define SPH_MLP_MAX_ROWS 2147483647LL
 
 /* Workspace bytes (HOST *bytes) of sph_mlp_forward and sph_mlp_loss_grad over
  * n rows. */
@@ -351,7 +353,8 @@ sph_status sph_mlp_forward(const float* params, const float* X, int64_t n, float
  * n target values of log(H_new/H_prev)); float32 arithmetic with the
  * bfloat16-rounded weights.  workspace: DEVICE scratch of `bytes` bytes
  * (per-workgroup partial gradients; sph_mlp_workspace_size).  Synchronises
- * the stream (for *loss). */
+ * the stream (for *loss).  SPH_ERR_INVALID on n < 1, n > SPH_MLP_MAX_ROWS or
+ * a NULL pointer; SPH_ERR_WORKSPACE if the workspace is too small. */
 sph_status sph_mlp_loss_grad(const float* params, const float* X, const float* y, int64_t n, float* grad,
                              double* loss, void* workspace, size_t bytes, void* hip_stream);
 

@@ -237,6 +237,9 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const MlpPacked* __restrict__
 // gradients per workgroup, then a reduction fused with Adam.
 // ---------------------------------------------------------------------------
 #define MB 32
+// Workgroups of k_mlp_fb at most: one per compute unit (about 88 KB of LDS
+// each); each loops over row tiles of MB rows.
+#define MLP_FB_WGS 256
 
 struct TrainArgs {
     const float* p;          // parameter vector (float32 masters)
@@ -250,6 +253,12 @@ struct TrainArgs {
     float* part;             // [workgroups][NT] partial gradients
     float* part_loss;        // [workgroups]
 };
+
+// Workgroups of one k_mlp_fb launch over `count` rows.
+inline int fb_workgroups(int64_t count)
+{
+    return (int)std::max<int64_t>(1, std::min<int64_t>((count + MB - 1) / MB, MLP_FB_WGS));
+}
 
 __global__ __launch_bounds__(256) void k_mlp_fb(TrainArgs a)
 {
@@ -276,118 +285,123 @@ __global__ __launch_bounds__(256) void k_mlp_fb(TrainArgs a)
         rxsd[tid] = 1.0f / a.p[O_XSD + tid];
     }
     const float b4 = a.p[O_B4], ymu = a.p[O_YMU], rysd = 1.0f / a.p[O_YSD];
-    // rows of this workgroup
     const int s = tid >> 3, q = tid & 7;   // sample, eighth of the units
-    const int64_t pos = (int64_t)blockIdx.x * MB + s;
-    const bool valid = pos < a.count;
-    int64_t row = 0;
-    if (valid) {
-        // N < 2^31, so the product stays below 2^62
-        const uint64_t k = (uint64_t)(a.row0 + pos) % (uint64_t)a.N;
-        row = (int64_t)((a.pa * k + a.pb) % (uint64_t)a.N);
-    }
-    __syncthreads();
-    // standardised inputs: thread (s, q) loads inputs 2q, 2q+1
-    for (int j = 0; j < 2; j++) {
-        const int k = 2 * q + j;
-        const float raw = (valid && k < XS) ? a.X[row * XS + k] : 0.f;
-        xh[s][k] = valid ? (raw - xmu[k]) * rxsd[k] : 0.f;
-    }
-    __syncthreads();
-    // forward: thread (s, q) computes units 8q..8q+7 of sample s
-    for (int l = 0; l < 3; l++) {
-        float z[8];
-        for (int j = 0; j < 8; j++) z[j] = bb[l][8 * q + j];
-        if (l == 0) {
-            for (int k = 0; k < NIN; k++) {
-                const float x = xh[s][k];
-                for (int j = 0; j < 8; j++) z[j] += x * W1[k * NH + 8 * q + j];
+    // this thread's share of the gradient, summed over the workgroup's tiles:
+    // W2, W3 row kw = tid/4, columns 16 (tid%4) .. +15; W1 row k1 = tid/16,
+    // columns 4 (tid%16) .. +3; unit tid of b1, b2, b3, w4 (tid < NH); b4
+    // and the loss (tid 0)
+    const int kw = tid >> 2, c0 = 16 * (tid & 3);
+    const int k1 = tid >> 4, c1 = 4 * (tid & 15);
+    float accW[2][16], acc1[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 16; j++) accW[0][j] = accW[1][j] = 0.f;
+    float g1 = 0.f, g2 = 0.f, g3 = 0.f, g4 = 0.f, gb = 0.f, Lsum = 0.f;
+    const int64_t n_tiles = (a.count + MB - 1) / MB;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t pos = tile * MB + s;
+        const bool valid = pos < a.count;
+        int64_t row = 0;
+        if (valid) {
+            // N < 2^31, so the product stays below 2^62
+            const uint64_t k = (uint64_t)(a.row0 + pos) % (uint64_t)a.N;
+            row = (int64_t)((a.pa * k + a.pb) % (uint64_t)a.N);
+        }
+        // weights loaded; the previous tile's readers of xh, hA, dA are done
+        __syncthreads();
+        // standardised inputs: thread (s, q) loads inputs 2q, 2q+1
+        for (int j = 0; j < 2; j++) {
+            const int k = 2 * q + j;
+            const float raw = (valid && k < XS) ? a.X[row * XS + k] : 0.f;
+            xh[s][k] = valid ? (raw - xmu[k]) * rxsd[k] : 0.f;
+        }
+        __syncthreads();
+        // forward: thread (s, q) computes units 8q..8q+7 of sample s
+        for (int l = 0; l < 3; l++) {
+            float z[8];
+            for (int j = 0; j < 8; j++) z[j] = bb[l][8 * q + j];
+            if (l == 0) {
+                for (int k = 0; k < NIN; k++) {
+                    const float x = xh[s][k];
+                    for (int j = 0; j < 8; j++) z[j] += x * W1[k * NH + 8 * q + j];
+                }
+            } else {
+                const float* Wl = l == 1 ? W2 : W3;
+                for (int k = 0; k < NH; k++) {
+                    const float x = hA[l - 1][s][k];
+                    for (int j = 0; j < 8; j++) z[j] += x * Wl[k * NH + 8 * q + j];
+                }
             }
-        } else {
-            const float* Wl = l == 1 ? W2 : W3;
+            for (int j = 0; j < 8; j++) {
+                hA[l][s][8 * q + j] = silu_f(z[j]);
+                dA[l][s][8 * q + j] = dsilu_f(z[j]);
+            }
+            __syncthreads();
+        }
+        // output and dL/do
+        float part = 0.f;
+        for (int j = 0; j < 8; j++) part += hA[2][s][8 * q + j] * w4[8 * q + j];
+        part += __shfl_xor(part, 1);
+        part += __shfl_xor(part, 2);
+        part += __shfl_xor(part, 4);
+        if (q == 0) {
+            float r = 0.f;
+            if (valid) r = part + b4 - (a.y[row] - ymu) * rysd;
+            dout[s] = r * a.inv_count;
+            red[s] = 0.5f * r * r;
+        }
+        __syncthreads();
+        // backward through the layers: dA[l] becomes dL/dz_l
+        for (int j = 0; j < 8; j++) dA[2][s][8 * q + j] *= dout[s] * w4[8 * q + j];
+        __syncthreads();
+        for (int l = 2; l >= 1; l--) {
+            const float* Wl = l == 2 ? W3 : W2;
+            float dh[8];
+            for (int j = 0; j < 8; j++) dh[j] = 0.f;
             for (int k = 0; k < NH; k++) {
-                const float x = hA[l - 1][s][k];
-                for (int j = 0; j < 8; j++) z[j] += x * Wl[k * NH + 8 * q + j];
+                const float d = dA[l][s][k];
+                for (int j = 0; j < 8; j++) dh[j] += d * Wl[(8 * q + j) * NH + k];
             }
+            for (int j = 0; j < 8; j++) dA[l - 1][s][8 * q + j] *= dh[j];
+            __syncthreads();
         }
-        for (int j = 0; j < 8; j++) {
-            hA[l][s][8 * q + j] = silu_f(z[j]);
-            dA[l][s][8 * q + j] = dsilu_f(z[j]);
-        }
-        __syncthreads();
-    }
-    // output and dL/do
-    float part = 0.f;
-    for (int j = 0; j < 8; j++) part += hA[2][s][8 * q + j] * w4[8 * q + j];
-    part += __shfl_xor(part, 1);
-    part += __shfl_xor(part, 2);
-    part += __shfl_xor(part, 4);
-    if (q == 0) {
-        float r = 0.f;
-        if (valid) r = part + b4 - (a.y[row] - ymu) * rysd;
-        dout[s] = r * a.inv_count;
-        red[s] = 0.5f * r * r;
-    }
-    __syncthreads();
-    // backward through the layers: dA[l] becomes dL/dz_l
-    for (int j = 0; j < 8; j++) dA[2][s][8 * q + j] *= dout[s] * w4[8 * q + j];
-    __syncthreads();
-    for (int l = 2; l >= 1; l--) {
-        const float* Wl = l == 2 ? W3 : W2;
-        float dh[8];
-        for (int j = 0; j < 8; j++) dh[j] = 0.f;
-        for (int k = 0; k < NH; k++) {
-            const float d = dA[l][s][k];
-            for (int j = 0; j < 8; j++) dh[j] += d * Wl[(8 * q + j) * NH + k];
-        }
-        for (int j = 0; j < 8; j++) dA[l - 1][s][8 * q + j] *= dh[j];
-        __syncthreads();
-    }
-    // partial gradients of this workgroup
-    float* G = a.part + (size_t)blockIdx.x * NT;
-    {
-        // W2, W3: thread -> row k = tid/4, columns 16 (tid%4) .. +15
-        const int k = tid >> 2, c0 = 16 * (tid & 3);
-        for (int l = 1; l <= 2; l++) {
-            float acc[16];
-            for (int j = 0; j < 16; j++) acc[j] = 0.f;
+        // this tile's contribution to the gradient
+        for (int l = 1; l <= 2; l++)
             for (int r = 0; r < MB; r++) {
-                const float hv = hA[l - 1][r][k];
-                for (int j = 0; j < 16; j++) acc[j] += hv * dA[l][r][c0 + j];
+                const float hv = hA[l - 1][r][kw];
+                for (int j = 0; j < 16; j++) accW[l - 1][j] += hv * dA[l][r][c0 + j];
             }
-            const int off = l == 1 ? O_W2 : O_W3;
-            for (int j = 0; j < 16; j++) G[off + k * NH + c0 + j] = acc[j];
-        }
-        // W1: row k = tid/16, columns 4 (tid%16) .. +3
-        const int k1 = tid >> 4, c1 = 4 * (tid & 15);
-        float acc1[4] = {0.f, 0.f, 0.f, 0.f};
         for (int r = 0; r < MB; r++) {
             const float xv = xh[r][k1];
             for (int j = 0; j < 4; j++) acc1[j] += xv * dA[0][r][c1 + j];
         }
-        for (int j = 0; j < 4; j++) G[O_W1 + k1 * NH + c1 + j] = acc1[j];
+        if (tid < NH)
+            for (int r = 0; r < MB; r++) {
+                g1 += dA[0][r][tid];
+                g2 += dA[1][r][tid];
+                g3 += dA[2][r][tid];
+                g4 += hA[2][r][tid] * dout[r];
+            }
+        if (tid == 0)
+            for (int r = 0; r < MB; r++) {
+                gb += dout[r];
+                Lsum += red[r];
+            }
     }
+    // partial gradients of this workgroup (every one of the NT entries)
+    float* G = a.part + (size_t)blockIdx.x * NT;
+    for (int j = 0; j < 16; j++) {
+        G[O_W2 + kw * NH + c0 + j] = accW[0][j];
+        G[O_W3 + kw * NH + c0 + j] = accW[1][j];
+    }
+    for (int j = 0; j < 4; j++) G[O_W1 + k1 * NH + c1 + j] = acc1[j];
     if (tid < NH) {
-        float g1 = 0.f, g2 = 0.f, g3 = 0.f, g4 = 0.f;
-        for (int r = 0; r < MB; r++) {
-            g1 += dA[0][r][tid];
-            g2 += dA[1][r][tid];
-            g3 += dA[2][r][tid];
-            g4 += hA[2][r][tid] * dout[r];
-        }
         G[O_B1 + tid] = g1;
         G[O_B2 + tid] = g2;
         G[O_B3 + tid] = g3;
         G[O_W4 + tid] = g4;
     }
     if (tid == 0) {
-        float gb = 0.f, L = 0.f;
-        for (int r = 0; r < MB; r++) {
-            gb += dout[r];
-            L += red[r];
-        }
         G[O_B4] = gb;
-        a.part_loss[blockIdx.x] = L;
+        a.part_loss[blockIdx.x] = Lsum;
     }
 }
 
@@ -615,13 +629,15 @@ struct TrainScratch {
     DevBuf part, part_loss, loss;
 };
 
-static sph_status minibatch(TrainScratch& S, const float* p, const float* X, const float* y, int64_t N, int64_t row0,
-                            int64_t count, uint64_t pa, uint64_t pb, float* grad, float* pw, float* m, float* v,
-                            bool adam, float lr, float b1, float b2, float eps, int t, float* loss_slot, hipStream_t s)
+// Forward + backward over `count` rows into nwg = fb_workgroups(count)
+// workgroup partials (part: nwg x NT floats, part_loss: nwg floats), then
+// their sum into grad and/or one Adam step.
+static sph_status fb_reduce(float* part, float* part_loss, const float* p, const float* X, const float* y, int64_t N,
+                            int64_t row0, int64_t count, uint64_t pa, uint64_t pb, float* grad, float* pw, float* m,
+                            float* v, bool adam, float lr, float b1, float b2, float eps, int t, float* loss_slot,
+                            hipStream_t s)
 {
-    const int nwg = nblocks(count, MB);
-    SPH_TRY(buf_ensure(S.part, (size_t)nwg * NT * sizeof(float)));
-    SPH_TRY(buf_ensure(S.part_loss, (size_t)nwg * sizeof(float)));
+    const int nwg = fb_workgroups(count);
     TrainArgs a;
     a.p = p;
     a.X = X;
@@ -632,17 +648,27 @@ static sph_status minibatch(TrainScratch& S, const float* p, const float* X, con
     a.pa = pa;
     a.pb = pb;
     a.inv_count = 1.0f / (float)count;
-    a.part = (float*)S.part.p;
-    a.part_loss = (float*)S.part_loss.p;
+    a.part = part;
+    a.part_loss = part_loss;
     k_mlp_fb<<<nwg, 256, 0, s>>>(a);
     SPH_CHECK_LAUNCH();
     const float c1 = adam ? (float)(1.0 - pow((double)b1, t)) : 1.f;
     const float c2 = adam ? (float)(1.0 - pow((double)b2, t)) : 1.f;
-    k_mlp_reduce<<<nblocks(NT, 256), 256, 0, s>>>((const float*)S.part.p, (const float*)S.part_loss.p, nwg,
-                                                   1.0f / (float)count, grad, pw, m, v, adam ? 1 : 0, lr, b1, b2, eps,
-                                                   c1, c2, loss_slot);
+    k_mlp_reduce<<<nblocks(NT, 256), 256, 0, s>>>(part, part_loss, nwg, 1.0f / (float)count, grad, pw, m, v,
+                                                   adam ? 1 : 0, lr, b1, b2, eps, c1, c2, loss_slot);
     SPH_CHECK_LAUNCH();
     return SPH_OK;
+}
+
+static sph_status minibatch(TrainScratch& S, const float* p, const float* X, const float* y, int64_t N, int64_t row0,
+                            int64_t count, uint64_t pa, uint64_t pb, float* grad, float* pw, float* m, float* v,
+                            bool adam, float lr, float b1, float b2, float eps, int t, float* loss_slot, hipStream_t s)
+{
+    const int nwg = fb_workgroups(count);
+    SPH_TRY(buf_ensure(S.part, (size_t)nwg * NT * sizeof(float)));
+    SPH_TRY(buf_ensure(S.part_loss, (size_t)nwg * sizeof(float)));
+    return fb_reduce((float*)S.part.p, (float*)S.part_loss.p, p, X, y, N, row0, count, pa, pb, grad, pw, m, v, adam,
+                     lr, b1, b2, eps, t, loss_slot, s);
 }
 
 static uint64_t gcd_u64(uint64_t a, uint64_t b)
@@ -772,7 +798,7 @@ extern "C" {
 // gradients of each workgroup (k_mlp_fb, MB rows each) and the loss slot.
 static size_t mlp_scratch_bytes(int64_t n)
 {
-    const size_t nwg = (size_t)std::max<int64_t>(1, nblocks(std::max<int64_t>(n, 1), MB));
+    const size_t nwg = (size_t)fb_workgroups(n);
     const size_t r = 256;
     auto up = [&](size_t b) { return (b + r - 1) / r * r + r; };
     return up(sizeof(MlpPacked)) + up(nwg * NT * sizeof(float)) + up(nwg * sizeof(float)) + up(sizeof(float)) +
@@ -807,7 +833,7 @@ sph_status sph_mlp_forward(const float* params, const float* X, int64_t n, float
 sph_status sph_mlp_loss_grad(const float* params, const float* X, const float* y, int64_t n, float* grad,
                              double* loss, void* workspace, size_t bytes, void* hip_stream)
 {
-    if (n <= 0 || !params || !X || !y || !grad || !workspace) return SPH_ERR_INVALID;
+    if (n <= 0 || n > SPH_MLP_MAX_ROWS || !params || !X || !y || !grad || !workspace) return SPH_ERR_INVALID;
     const hipStream_t s = (hipStream_t)hip_stream;
     Pool pool;
     pool.init(workspace, bytes);

@@ -88,8 +88,15 @@ def test_workspace_size_queries(L):
     assert L.sph_workspace_size(None, 10, C.byref(b)) == -1
     p2, _ = _params(lists=1, force_mode=1)
     assert L.sph_workspace_size(C.byref(p2), 1 << 24, C.byref(b)) == 0
+    # the gradient kernel runs at most 256 workgroups of 32-row tiles: the
+    # workspace grows with n up to 256 workgroups' partials, then stays
+    assert L.sph_mlp_workspace_size(1024, C.byref(b)) == 0
+    assert b.value >= 1024 // 32 * S.MLP_NT * 4
     assert L.sph_mlp_workspace_size(16384, C.byref(b)) == 0
-    assert b.value >= 16384 // 32 * S.MLP_NT * 4
+    cap = b.value
+    assert cap >= 256 * S.MLP_NT * 4
+    assert L.sph_mlp_workspace_size(1 << 26, C.byref(b)) == 0
+    assert b.value == cap
     assert L.sph_mlp_workspace_size(-1, C.byref(b)) == -1
 
 

@@ -68,12 +68,15 @@ def test_forward_matches_oracle(n):
     assert err.max() < 2e-5
 
 
-def test_loss_grad_matches_oracle():
+@pytest.mark.parametrize("n", [1000, 20011])
+def test_loss_grad_matches_oracle(n):
+    """1000 rows: one tile of 32 rows per workgroup; 20011: 626 tiles over
+    the 256 workgroups, the last one ragged."""
     import torch
     from paper_1606_02738_amd import sph as S
-    log("case mlp loss/grad n=1000")
+    log("case mlp loss/grad n=%d" % n)
     p = _params(5)
-    X, y = _rows(1000, 9)
+    X, y = _rows(n, 9)
     L, g = S.mlp_loss_grad(torch.from_numpy(p).cuda(), torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda())
     g = g.cpu().numpy().astype(np.float64)
     Lo, go = M.loss_grad(p.astype(np.float64), _pad(X.astype(np.float64)), y.astype(np.float64))
