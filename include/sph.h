@@ -358,6 +358,24 @@ sph_status sph_mlp_forward(const float* params, const float* X, int64_t n, float
 sph_status sph_mlp_loss_grad(const float* params, const float* X, const float* y, int64_t n, float* grad,
                              double* loss, void* workspace, size_t bytes, void* hip_stream);
 
+/* sph_mlp_loss_grad for callers that cannot allocate device memory or hand
+ * over a workspace (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): same arguments without the workspace,
+ * same kernels and the same result.  The partial gradients live in a fixed
+ * array inside this library, about 9.7 MB (256 x SPH_MLP_NT + 256 floats
+ * + the loss), which each GPU the library runs on holds until the process
+ * ends; it serves any n up to SPH_MLP_MAX_ROWS, since the gradient kernel
+ * runs at most 256 workgroups.  Nothing is allocated: no hipMalloc,
+ * hipFree or allocating library call.  All calls on one GPU share that GPU's
+ * array, so calls that overlap on one GPU (different streams or host
+ * threads without ordering between them) race; calls ordered on one stream
+ * do not.  hip_stream must belong to the current device.  Synchronises the
+ * stream (for *loss).  SPH_ERR_INVALID on n < 1, n > SPH_MLP_MAX_ROWS or a
+ * NULL pointer; SPH_ERR_HIP if the array's device address cannot be
+ * obtained. */
+sph_status sph_mlp_loss_grad_noalloc(const float* params, const float* X, const float* y, int64_t n, float* grad,
+                                     double* loss, void* hip_stream);
+
 /* One Adam step (step number t >= 1) on the SPH_MLP_NT trained values of
  * params with moment buffers m, v (SPH_MLP_NT floats each, DEVICE):
  * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,

@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "sph_ctx.h"
@@ -844,6 +845,62 @@ sph_status sph_mlp_loss_grad(const float* params, const float* X, const float* y
                       (float*)S.loss.p, s));
     float L = 0.f;
     SPH_CHECK_HIP(hipMemcpyAsync(&L, S.loss.p, sizeof(float), hipMemcpyDeviceToHost, s));
+    SPH_CHECK_HIP(hipStreamSynchronize(s));
+    if (loss) *loss = L;
+    return SPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// sph_mlp_loss_grad without a workspace.  The workgroup partials and the loss
+// live in `scratch`, a fixed array of this library that every GPU holds
+// once (MLP_FB_WGS x NT partial gradients, MLP_FB_WGS partial losses, the
+// loss): about 9.7 MB, enough for any row count since k_mlp_fb runs at most
+// MLP_FB_WGS workgroups.  Every call on one GPU shares that GPU's copy.
+// ---------------------------------------------------------------------------
+constexpr size_t NOALLOC_PART = (size_t)MLP_FB_WGS * NT;
+constexpr size_t NOALLOC_FLOATS = NOALLOC_PART + MLP_FB_WGS + 64;
+static __device__ __align__(256) float scratch[NOALLOC_FLOATS];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static float* g_scratch_ptr[NOALLOC_MAX_DEVICES];
+
+// Device address of the current device's copy of `scratch` (its host-side
+// name is not a device address), looked up on the first call on a device.
+static sph_status scratch_address(float** out)
+{
+    int dev = -1;
+    SPH_CHECK_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return SPH_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        SPH_CHECK_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return SPH_ERR_HIP;
+        g_scratch_ptr[dev] = (float*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SPH_OK;
+}
+
+sph_status sph_mlp_loss_grad_noalloc(const float* params, const float* X, const float* y, int64_t n, float* grad,
+                                     double* loss, void* hip_stream)
+{
+    if (n <= 0 || n > SPH_MLP_MAX_ROWS || !params || !X || !y || !grad) return SPH_ERR_INVALID;
+    static_assert((size_t)MLP_FB_WGS * NT + MLP_FB_WGS + 1 <= NOALLOC_FLOATS, "scratch too small");
+    if ((size_t)fb_workgroups(n) > MLP_FB_WGS) return SPH_ERR_WORKSPACE;
+    float* ptr = nullptr;
+    SPH_TRY(scratch_address(&ptr));
+    const hipStream_t s = (hipStream_t)hip_stream;
+    // every partial and the loss are written before they are read: nothing
+    // in the array needs clearing between calls
+    float* part = ptr;
+    float* part_loss = ptr + NOALLOC_PART;
+    float* loss_slot = part_loss + MLP_FB_WGS;
+    SPH_TRY(fb_reduce(part, part_loss, params, X, y, n, 0, n, 1, 0, grad, nullptr, nullptr, nullptr, false, 0.f, 0.f,
+                      0.f, 0.f, 0, loss_slot, s));
+    float L = 0.f;
+    SPH_CHECK_HIP(hipMemcpyAsync(&L, loss_slot, sizeof(float), hipMemcpyDeviceToHost, s));
     SPH_CHECK_HIP(hipStreamSynchronize(s));
     if (loss) *loss = L;
     return SPH_OK;

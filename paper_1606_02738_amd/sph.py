@@ -87,7 +87,7 @@ class Stats(C.Structure):
 _lib = None
 EXPORTS = ("sph_workspace_size", "sph_mlp_workspace_size", "sph_create", "sph_destroy", "sph_build_cells", "sph_sort_cells", "sph_density",
            "sph_ghost", "sph_force", "sph_density_ghost_force", "sph_step", "sph_get_stats", "sph_domain_sums",
-           "sph_status_str", "sph_version", "sph_mlp_forward", "sph_mlp_loss_grad", "sph_mlp_adam",
+           "sph_status_str", "sph_version", "sph_mlp_forward", "sph_mlp_loss_grad", "sph_mlp_loss_grad_noalloc", "sph_mlp_adam",
            "sph_h_features", "sph_h_record", "sph_h_train", "sph_h_set_params", "sph_h_get_params",
            "sph_h_predict", "sph_interpolate")
 
@@ -117,6 +117,7 @@ def lib():
         L.sph_version.restype = C.c_char_p
         L.sph_mlp_forward.argtypes = [vp, vp, C.c_int64, vp, vp, C.c_size_t, vp]
         L.sph_mlp_loss_grad.argtypes = [vp, vp, vp, C.c_int64, vp, C.POINTER(C.c_double), vp, C.c_size_t, vp]
+        L.sph_mlp_loss_grad_noalloc.argtypes = [vp, vp, vp, C.c_int64, vp, C.POINTER(C.c_double), vp]
         L.sph_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, vp]
         L.sph_h_features.argtypes = [vp, C.c_double, vp]
         L.sph_h_record.argtypes = [vp, vp, vp, C.c_int64, C.c_double, C.c_uint64, C.POINTER(C.c_int64)]
@@ -175,6 +176,21 @@ def mlp_loss_grad(params, X, y, stream=None):
     _check(lib().sph_mlp_loss_grad(params.data_ptr(), X.data_ptr(), y.data_ptr(), X.shape[0], g.data_ptr(),
                                    C.byref(L), ws.data_ptr(), ws.numel(), _stream_ptr(stream)),
            "sph_mlp_loss_grad")
+    return L.value, g
+
+
+def mlp_loss_grad_noalloc(params, X, y, grad=None, stream=None):
+    """mlp_loss_grad through the entry point that allocates nothing (its
+    partials live in the library's own device array); grad: an optional
+    preallocated float32 tensor of MLP_NT."""
+    import torch
+    assert X.dtype == torch.float32 and X.is_contiguous() and X.shape[-1] == MLP_XSTRIDE
+    assert y.dtype == torch.float32 and y.numel() == X.shape[0]
+    g = grad if grad is not None else torch.empty(MLP_NT, dtype=torch.float32, device=X.device)
+    assert g.dtype == torch.float32 and g.numel() == MLP_NT and g.is_contiguous()
+    L = C.c_double()
+    _check(lib().sph_mlp_loss_grad_noalloc(params.data_ptr(), X.data_ptr(), y.data_ptr(), X.shape[0], g.data_ptr(),
+                                           C.byref(L), _stream_ptr(stream)), "sph_mlp_loss_grad_noalloc")
     return L.value, g
 
 
