@@ -188,7 +188,7 @@ sph_status sph_destroy(sph_ctx* c)
                      &c->l_origin, &c->l_lo, &c->l_hi, &c->l_hlist, &c->l_dom, &c->l_off, &c->l_active, &c->l_sorted,
                      &c->l_cnt, &c->list, &c->pos4, &c->fv4, &c->hf, &c->skey, &c->sidx,
                      &c->hlo, &c->hhi, &c->conv, &c->flags, &c->counters,
-                     &c->scan_tmp, &c->rs_hist, &c->sums, &c->dsum_part, &c->fgrid, &c->fcount, &c->mlp_X, &c->mlp_hprev, &c->mlp_params, &c->mlp_packed, &c->mlp_m, &c->mlp_v, &c->ds_count, &c->dparam, &c->walk_scratch,
+                     &c->scan_tmp, &c->rs_hist, &c->sums, &c->dsum_part, &c->fgrid, &c->fcount, &c->mlp_X, &c->mlp_hprev, &c->mlp_params, &c->mlp_packed, &c->mlp_m, &c->mlp_v, &c->ds_count, &c->dparam, &c->walk_scratch, &c->walk_ovf, &c->walk_link,
                      &c->pq, &c->pR, &c->plist, &c->prem, &c->plen, &c->pskin, &c->pq0, &c->pext, &c->pbox,
                      &c->ch_base, &c->ch_p0, &c->ch_n, &c->ch_uo, &c->ch_ro, &c->ch_U};
     for (DevBuf* b : all) buf_free(*b);

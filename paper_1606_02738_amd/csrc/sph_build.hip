@@ -543,23 +543,28 @@ __device__ inline float box_dist_f(const float* alo, const float* ahi, const flo
 }
 
 // MODE 0: count the entries of each leaf; 1: write them at the scanned
-// offsets l_off (with list_cap > 0, only the leaves of more than list_cap
-// entries: the others come from their slots); 2: write up to list_cap
-// entries of leaf A at A * list_cap and count them all.
+// offsets l_off (with `link`, only the leaves it marks incomplete); 2: write
+// the first list_cap entries of leaf A at A * list_cap, the rest into
+// 64-entry chunks of `ovf` taken one at a time (link: [head of each leaf's
+// chain | incomplete flag of each leaf | next chunk]), and count them all.
 template <int MODE>
 __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restrict__ leaf_node, const WNode* __restrict__ wn,
                                               const double* __restrict__ l_lo, const double* __restrict__ l_hi,
                                               const int* __restrict__ l_dom, const int* __restrict__ l_top,
                                               const DomainInfo* __restrict__ di, const double* __restrict__ l_hlist,
                                               int* counts, const int* __restrict__ l_off, ListEntry* __restrict__ list,
-                                              int list_cap, int with_dir, int sym, int* flags)
+                                              int list_cap, int with_dir, int sym, int* flags, ListEntry* ovf,
+                                              int* link, int ovf_chunks)
 {
     const int A = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (A >= n_leaves) return;
+    if (MODE == 1 && link && !link[n_leaves + A]) return;
+    int* next = link ? link + 2 * (size_t)n_leaves : nullptr;
+    int last = -1;          // this leaf's current overflow chunk
+    bool failed = false;    // no chunk was free: the leaf is walked again
     const DomainInfo& I = di[l_dom[A]];
     const int loc = l_top[A] - I.top_offset;
     const int tc[3] = {loc / (I.n_top[2] * I.n_top[1]), (loc / I.n_top[2]) % I.n_top[1], loc % I.n_top[2]};
-    if (MODE == 1 && list_cap > 0 && l_off[A + 1] - l_off[A] <= list_cap) return;
     const double hA = l_hlist[A];
     // conservative float pruning radius: the float boxes are rounded outward;
     // the absolute term covers the rounding of box + periodic shift in float
@@ -619,7 +624,25 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
                 }
                 if (!(d < (sym ? fmax(hA, l_hlist[B]) : hA))) continue;
                 if (FILL) {
+                    ListEntry* dst = nullptr;
                     if (out < out_len) {
+                        dst = list + out_base + out;
+                    } else if (MODE == 2 && !failed) {
+                        const int k = out - out_len;
+                        if ((k & 63) == 0) {
+                            const int ch = atomicAdd(flags + FI_WOVF, 1);
+                            if (ch >= ovf_chunks) {
+                                failed = true;
+                            } else {
+                                if (last < 0) link[A] = ch;
+                                else next[last] = ch;
+                                next[ch] = -1;
+                                last = ch;
+                            }
+                        }
+                        if (!failed) dst = ovf + (size_t)last * 64 + (k & 63);
+                    }
+                    if (dst) {
                         int best = 0;
                         if (with_dir) {
                             // sort direction: the one of 13 most aligned with the centre offset
@@ -636,7 +659,7 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
                         e.B = B;
                         e.code = code_shift | (best << 8);
                         e.dist = d;
-                        list[out_base + out] = e;
+                        *dst = e;
                     } else if (MODE == 1) {
                         atomicOr(flags, FLAG_INVALID);
                     }
@@ -647,21 +670,34 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
         }
     }
     if (MODE != 1) counts[A] = cnt;
-    if (MODE == 2 && cnt > list_cap) atomicMax(flags + FI_MAXLIST, cnt);
+    if (MODE == 2) {
+        if (cnt > list_cap) atomicMax(flags + FI_MAXLIST, cnt);
+        if (last < 0) link[A] = -1;
+        link[n_leaves + A] = failed ? 1 : 0;
+        if (failed) atomicAdd(flags + FI_WINC, 1);
+    }
 }
 
-// Move the entries of the one-pass walk from the per-leaf slots to the
-// scanned offsets (leaves of more than cap entries are walked again).  One
-// wave per leaf.
+// Move the entries of the one-pass walk from the per-leaf slots and their
+// overflow chains to the scanned offsets (incomplete leaves are walked
+// again).  One wave per leaf.
 __global__ __launch_bounds__(256) void k_list_compact(int n_leaves, int cap, const ListEntry* __restrict__ scratch,
+                                                      const ListEntry* __restrict__ ovf, const int* __restrict__ link,
                                                       const int* __restrict__ l_off, ListEntry* __restrict__ list)
 {
     const int A = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (A >= n_leaves) return;
+    if (link[n_leaves + A]) return;
     const int lane = threadIdx.x & 63;
     const int o = l_off[A], n = l_off[A + 1] - o;
-    if (n > cap) return;
-    for (int e = lane; e < n; e += 64) list[o + e] = scratch[(size_t)A * cap + e];
+    const int ns = min(n, cap);
+    for (int e = lane; e < ns; e += 64) list[o + e] = scratch[(size_t)A * cap + e];
+    const int* next = link + 2 * (size_t)n_leaves;
+    int ch = __builtin_amdgcn_readfirstlane(link[A]);
+    for (int b = ns; b < n && ch >= 0; b += 64) {
+        if (b + lane < n) list[o + b + lane] = ovf[(size_t)ch * 64 + lane];
+        ch = __builtin_amdgcn_readfirstlane(next[ch]);
+    }
 }
 
 // Largest H per cell, bottom-up over one level (leaves from particles,
@@ -888,40 +924,47 @@ sph_status relist(sph_ctx* c)
     int cap = c->walk_cap;
     while (cap > 16 && (size_t)nL * cap * sizeof(ListEntry) > (size_t)c->n * SPH_WALK_SLOT_BYTES) cap /= 2;
     const bool one_pass = (size_t)nL * cap * sizeof(ListEntry) <= (size_t)c->n * SPH_WALK_SLOT_BYTES + ((size_t)1 << 20);
+    const int ovf_chunks = (int)std::min<int64_t>(std::max<int64_t>(1024, c->n * SPH_WALK_OVF_BYTES / (64 * 16)),
+                                                  INT32_MAX / 64);
     if (one_pass) {
         SPH_TRY(buf_ensure(c->walk_scratch, (size_t)nL * cap * sizeof(ListEntry)));
+        SPH_TRY(buf_ensure(c->walk_ovf, (size_t)ovf_chunks * 64 * sizeof(ListEntry)));
+        SPH_TRY(buf_ensure(c->walk_link, (2 * (size_t)nL + ovf_chunks) * sizeof(int)));
         SPH_CHECK_HIP(hipMemsetAsync(flags + FI_MAXLIST, 0, sizeof(int), c->stream));
+        SPH_CHECK_HIP(hipMemsetAsync(flags + FI_WOVF, 0, 2 * sizeof(int), c->stream));
         k_walk<2><<<blocks_for(nL, 128), 128, 0, c->stream>>>(
             nL, (const int*)c->leaf_node.p, (const WNode*)c->wnodes.p, (const double*)c->l_lo.p,
             (const double*)c->l_hi.p, (const int*)c->l_dom.p, (const int*)c->l_cnt.p, (const DomainInfo*)c->dom_d.p,
-            (const double*)c->l_hlist.p, counts, nullptr, (ListEntry*)c->walk_scratch.p, cap, with_dir, sym, flags);
+            (const double*)c->l_hlist.p, counts, nullptr, (ListEntry*)c->walk_scratch.p, cap, with_dir, sym, flags,
+            (ListEntry*)c->walk_ovf.p, (int*)c->walk_link.p, ovf_chunks);
     } else {
         k_walk<0><<<blocks_for(nL, 128), 128, 0, c->stream>>>(
             nL, (const int*)c->leaf_node.p, (const WNode*)c->wnodes.p, (const double*)c->l_lo.p,
             (const double*)c->l_hi.p, (const int*)c->l_dom.p, (const int*)c->l_cnt.p, (const DomainInfo*)c->dom_d.p,
-            (const double*)c->l_hlist.p, counts, nullptr, nullptr, 0, with_dir, sym, flags);
+            (const double*)c->l_hlist.p, counts, nullptr, nullptr, 0, with_dir, sym, flags, nullptr, nullptr, 0);
     }
     SPH_CHECK_LAUNCH();
     SPH_TRY(scan_exclusive(c, counts, counts, nL + 1, flags + FI_NLIST));
-    int hf[FI_MAXLIST - FI_NLIST + 1];
+    int hf[FI_WINC - FI_NLIST + 1];
     SPH_CHECK_HIP(hipMemcpyAsync(hf, flags + FI_NLIST, sizeof(hf), hipMemcpyDeviceToHost, c->stream));
     SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
-    const int total = hf[0], over = hf[FI_MAXLIST - FI_NLIST];
+    const int total = hf[0], incomplete = one_pass ? hf[FI_WINC - FI_NLIST] : 0;
     if (total < 0) return SPH_ERR_WORKSPACE;
     SPH_TRY(buf_ensure(c->list, (size_t)std::max(total, 1) * sizeof(ListEntry)));
     if (one_pass) {
-        k_list_compact<<<blocks_for(nL, 4), 256, 0, c->stream>>>(nL, cap, (const ListEntry*)c->walk_scratch.p,
-                                                                 (const int*)c->l_off.p, (ListEntry*)c->list.p);
+        k_list_compact<<<blocks_for(nL, 4), 256, 0, c->stream>>>(
+            nL, cap, (const ListEntry*)c->walk_scratch.p, (const ListEntry*)c->walk_ovf.p, (const int*)c->walk_link.p,
+            (const int*)c->l_off.p, (ListEntry*)c->list.p);
         SPH_CHECK_LAUNCH();
     }
-    if (!one_pass || over > 0) {
-        // leaves with more entries than their slot (all leaves without the
+    if (!one_pass || incomplete > 0) {
+        // leaves that found no free overflow chunk (all leaves without the
         // one pass): walked again, writing at the scanned offsets
         k_walk<1><<<blocks_for(nL, 128), 128, 0, c->stream>>>(
             nL, (const int*)c->leaf_node.p, (const WNode*)c->wnodes.p, (const double*)c->l_lo.p,
             (const double*)c->l_hi.p, (const int*)c->l_dom.p, (const int*)c->l_cnt.p, (const DomainInfo*)c->dom_d.p,
-            (const double*)c->l_hlist.p, nullptr, (const int*)c->l_off.p, (ListEntry*)c->list.p,
-            one_pass ? cap : 0, with_dir, sym, flags);
+            (const double*)c->l_hlist.p, nullptr, (const int*)c->l_off.p, (ListEntry*)c->list.p, 0, with_dir, sym,
+            flags, nullptr, one_pass ? (int*)c->walk_link.p : nullptr, 0);
         SPH_CHECK_LAUNCH();
     }
     // slot for the next build: the power of two at or above twice the mean

@@ -90,6 +90,7 @@ struct sph_ctx {
     DevBuf l_begin, l_count, l_origin, l_lo, l_hi, l_hlist, l_dom, l_off, l_active, l_sorted, l_cnt;
     DevBuf list;
     DevBuf walk_scratch;          // per-leaf slots of the one-pass list walk
+    DevBuf walk_ovf, walk_link;   // its overflow chunks; chunk links (head, incomplete, next)
     int walk_cap = 128;           // entries per slot (grows after an overflow)
     DevBuf pos4, fv4, hf;         // kernel-side particle data (T = float or double)
     // per-particle lists (lists = SPH_LISTS_PARTICLE)

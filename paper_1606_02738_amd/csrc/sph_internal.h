@@ -68,9 +68,12 @@ struct WNode {
 // sort direction to use for the pair.  A's list holds every leaf B whose
 // bounding box (image) lies closer than h_A (the radius the list was built
 // for), i.e. the cells the density gather of A needs.
-// Bytes per particle the one-pass list walk may hold in per-leaf slots
-// (leaves with more entries than their slot are walked a second time).
+// Bytes per particle the one-pass list walk may hold in per-leaf slots, and
+// in the shared overflow chunks of 64 entries that leaves with more entries
+// than their slot continue into (leaves that find no free chunk are walked
+// a second time).
 #define SPH_WALK_SLOT_BYTES 64
+#define SPH_WALK_OVF_BYTES 16
 
 struct ListEntry {
     int B;
@@ -120,7 +123,8 @@ enum {
 };
 
 // Slots of the int[64] flags buffer.
-enum { FI_FLAGS = 0, FI_SCRATCH = 8, FI_NCHILD = 9, FI_NLEAVES = 10, FI_NLIST = 11, FI_GATE = 12, FI_MAXLEAF = 13, FI_MAXLIST = 14, FI_PLROWS = 15, FI_NFLAGS = 64 };
+enum { FI_FLAGS = 0, FI_SCRATCH = 8, FI_NCHILD = 9, FI_NLEAVES = 10, FI_NLIST = 11, FI_GATE = 12, FI_MAXLEAF = 13, FI_MAXLIST = 14, FI_PLROWS = 15, FI_WOVF = 16,
+       FI_WINC = 17, FI_NFLAGS = 64 };
 
 // Counters written by kernels (device, int64).
 enum { CNT_UNCONV = 0, CNT_NDENS = 1, CNT_NFORCE = 2, CNT_NPLIST = 3, CNT_DEVAL = 5, CNT_NPAIR = 6, CNT_NDENS_F = 7, CNT_GSWEEPS = 8, CNT_UHIST = 9, CNT_N = 16 };
