@@ -204,6 +204,60 @@ def parity_eval(sim, t, box, n_sample=3000, tails=200, seed=7):
     return out
 
 
+def wide_h_eval(S, prec, cfg, n_side=128, steps=10, warmup=2, seed=77):
+    """Smoothing lengths over three decades (Sec. 2: h follows the local
+    density over orders of magnitude): log-density sigma 3, half of the
+    particles in concentrated halos over four decades of mass, at n_side^3,
+    stepped in the timed configuration; step time and interactions per
+    second, then the sampled oracle parity of the stepped state."""
+    import numpy as np
+    import torch
+    import gen
+    n_halos = max(1, int(round(40 * (n_side / 40) ** 3)))
+    log("wide H range: generating %d^3 ..." % n_side)
+    d = gen.clustered(n_side, seed=seed, n_halos=n_halos, sigma_ln=3.0, halo_frac=0.5, c_range=(15.0, 40.0),
+                      decades=4.0)
+    box = d["box"]
+    t = S.to_device(d)
+    del d
+    sim = S.SPH(box, precision=prec, **cfg)
+    sim.bind(t)
+    t0 = time.perf_counter()
+    sim.run()
+    torch.cuda.synchronize()
+    cold = time.perf_counter() - t0
+    stc = sim.stats()
+    H = t["H"]
+    Hs = H.float()
+    q = torch.quantile(Hs[::max(1, Hs.numel() // 2_000_000)], torch.tensor([0.001, 0.999], device=Hs.device))
+    q = q.cpu().numpy()
+    span = float(H.max() / H.min())
+    cs = math.sqrt(5.0 / 3.0 * (2.0 / 3.0) * float(t["u"].max()))
+    dt = 0.25 * float(H.min()) / math.sqrt(10.0 / 3.0) / cs
+    for _ in range(warmup):
+        sim.step(dt)
+    torch.cuda.synchronize()
+    st0 = sim.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sim.step(dt)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st1 = sim.stats()
+    inter = (st1["n_dens_total"] - st0["n_dens_total"]) + 2 * (st1["n_force_total"] - st0["n_force_total"])
+    out = {"n_particles": int(H.numel()), "n_halos": n_halos, "H_span_min_max": span,
+           "H_span_0.1_99.9": float(q[1] / q[0]), "cold_start_s": cold, "cold_start_sweeps": stc["sweeps"],
+           "depth": stc["depth"], "leaves": stc["n_leaves"], "dt": dt, "steps": steps,
+           "ms_per_step": wall / steps * 1e3, "interactions_per_s": inter / wall,
+           "builds": st1["n_builds"] - st0["n_builds"]}
+    log("wide H range %d^3: H span %.0f, %.2f ms/step, %.3g interactions/s" % (
+        n_side, span, out["ms_per_step"], out["interactions_per_s"]))
+    out["parity"] = parity_eval(sim, t, box)
+    sim.close()
+    return out
+
+
 def mlp_eval(S, sim, t, dt, steps, make_sim, rec_steps=50, seed=17):
     """Learned H predictor on the same workload: record samples over
     `rec_steps` plain steps, train with the library's kernels, then time
@@ -437,11 +491,16 @@ def main():
     ap.add_argument("--lists", choices=("cell", "particle"), default="cell",
                     help="neighbour lists of the density and force kernels (default: the autotuner's choice)")
     ap.add_argument("--tile", type=int, default=0, help="LDS segment of the particle-list kernels")
+    ap.add_argument("--waves-density", type=int, default=0, help="occupancy target of the density kernel (0: 6)")
+    ap.add_argument("--waves-force", type=int, default=0, help="occupancy target of the force kernel (0: 5)")
+    ap.add_argument("--batch", type=int, default=0, help="neighbour-cell entries staged per batch (0: 32)")
     ap.add_argument("--no-h-drift", action="store_true",
                     help="start the H iteration of a step from the previous H as is")
     ap.add_argument("--seed", type=int, default=2741)
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned H predictor comparison")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-box ensemble comparison")
+    ap.add_argument("--no-wide-h", action="store_true", help="skip the three-decade smoothing-length workload")
+    ap.add_argument("--wide-h-n-side", type=int, default=128)
     ap.add_argument("--no-forms", action="store_true", help="skip the FP64 / FP32 / FP32C step comparison")
     ap.add_argument("--mlp-steps", type=int, default=5)
     ap.add_argument("--no-parity", action="store_true",
@@ -479,7 +538,8 @@ def main():
     cfg = dict(n_split=args.n_split, exec_mode=args.exec_mode, persistent_wgs=args.persistent_wgs,
                prune=args.prune, use_graph=args.graph, rebuild_steps=args.rebuild_steps,
                h_drift=not args.no_h_drift, force=args.force or ("gather" if args.prune == "box" else "pairs"),
-               lists=args.lists, tile=args.tile)
+               lists=args.lists, tile=args.tile, waves_density=args.waves_density, waves_force=args.waves_force,
+               batch=args.batch)
     sim = S.SPH(box, precision=args.precision, **cfg)
     t = S.to_device(d)
     del d
@@ -618,6 +678,8 @@ def main():
                    "persistent_wgs": cfg["persistent_wgs"], "prune": cfg["prune"], "graph": bool(cfg["use_graph"]),
                    "rebuild_steps": cfg["rebuild_steps"], "h_drift": bool(cfg["h_drift"]),
                    "force": cfg["force"], "lists": cfg.get("lists", "cell"), "tile": cfg.get("tile", 0),
+                   "waves_density": cfg.get("waves_density", 0), "waves_force": cfg.get("waves_force", 0),
+                   "batch": cfg.get("batch", 0),
                    "autotuned": bool(args.tune), "dt": dt},
         "builds": builds,
         "interactions_per_step": inter / args.steps,
@@ -653,6 +715,9 @@ def main():
     sim.close()
     del t
     torch.cuda.empty_cache()
+    if not args.no_wide_h:
+        out["wide_h_range"] = wide_h_eval(S, args.precision, cfg, n_side=args.wide_h_n_side)
+        torch.cuda.empty_cache()
     if not args.no_ensemble:
         out["ensemble"] = ensemble_eval(S, args.precision, rebuild_steps=cfg["rebuild_steps"])
         torch.cuda.empty_cache()

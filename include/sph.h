@@ -126,6 +126,12 @@ typedef struct {
     int tile;            /* particle lists: candidates staged in LDS per segment, 256, 512
                             or 1024 (0: 1024 for the density and 512 for the force; FP64
                             at most 512 / 256) */
+    int waves_density;   /* cell lists, FP32 modes: occupancy target (waves per SIMD) the
+                            packed density kernel is compiled for, 4, 5, 6 or 8 (0: 6) */
+    int waves_force;     /* the same for the gather force kernel, 4, 5, 6 or 8 (0: 5) */
+    int batch;           /* cell lists, FP32 modes: neighbour-cell entries staged per batch
+                            by those two kernels, 16 or 32 (0: 32).  These three only tune
+                            speed: every choice gives the same results bit for bit */
     const double* boxes; /* HOST pointer, n_domains x 3 box edge lengths; copied */
 } sph_params;
 
@@ -152,7 +158,12 @@ typedef struct {
     int64_t n_leaves;        /* leaf cells (self tasks) */
     int64_t n_nodes;         /* cells of all levels */
     int64_t n_list;          /* neighbour-cell entries (ordered pairs incl. self) */
-    int64_t n_pair_tasks;    /* unordered pair tasks (B > A) of the current lists */
+    int64_t n_pair_tasks;    /* unordered pairs of distinct leaves (A, B) in the current
+                                lists, each counted once by its owner: the lower index
+                                when the pair is in both leaves' lists (always, with the
+                                symmetric lists of the gather form), else the leaf whose
+                                list holds it; periodic self-images (B = A shifted) are
+                                not counted */
     int64_t n_dens;          /* sum_i #{j : r_ij < H_i}, self included, at the final H
                                 (from the last force call; after density alone, at the
                                 last H the density stage evaluated) */
@@ -252,8 +263,12 @@ sph_status sph_density(sph_ctx* ctx);
  * Requires sph_density. */
 sph_status sph_ghost(sph_ctx* ctx);
 
-/* Force stage, eqs. (dvdt) and (dudt): every unordered pair with r_ij <
- * max(H_i, H_j) evaluated once and applied to both particles.  Writes ax,
+/* Force stage, eqs. (dvdt) and (dudt) over every pair with r_ij <
+ * max(H_i, H_j).  force_mode = SPH_FORCE_GATHER (default): each particle
+ * sums its own pairs, so every unordered pair is evaluated from both sides
+ * and each output is written once (no atomics).  SPH_FORCE_PAIRS: every
+ * unordered pair is evaluated once and its equal and opposite contributions
+ * are applied to both particles (j-side sums with atomic adds).  Writes ax,
  * ay, az, dudt.  Requires sph_ghost. */
 sph_status sph_force(sph_ctx* ctx);
 

@@ -8,7 +8,10 @@ or persistent workgroups draining per-XCD leaf queues, with the number of
 resident workgroups), the pair-pruning mode, the force form (each pair once with
 atomic j-side sums, or every particle gathering its own pairs), hipGraph
 capture of the density, ghost and force stages, and how many steps the
-cells and lists are kept (the list skin).  Every candidate starts from the same saved state, so each is timed
+cells and lists are kept (the list skin).  A second stage sweeps, around
+the fastest of those, the kernel axes: the occupancy target (waves per SIMD)
+the density and the force kernels are compiled for, and the neighbour-cell
+entries they stage per batch.  Every candidate starts from the same saved state, so each is timed
 on identical work; the particle tensors are restored afterwards.  Steps are
 averaged (not the median) so that the occasional rebuild of a candidate
 that keeps its lists is paid for.
@@ -70,6 +73,23 @@ def candidates(full=False):
     return out
 
 
+KERNEL_WAVES = (4, 5, 6, 8)
+KERNEL_BATCH = (16, 32)
+
+
+def kernel_candidates(best):
+    """Second-stage candidates: the kernel axes swept one at a time around
+    `best` (the other two at their defaults, 0)."""
+    base = dict(best, waves_density=0, waves_force=0, batch=0)
+    out = []
+    for w in KERNEL_WAVES:
+        out.append(dict(base, waves_density=w))
+        out.append(dict(base, waves_force=w))
+    for b in KERNEL_BATCH:
+        out.append(dict(base, batch=b))
+    return out
+
+
 def _time_config(boxes, t, state, cfg, precision, dt, steps, warmup):
     """Mean ms per step.  A candidate that keeps its cells and lists for
     many steps may rebuild rarely or never inside the few timed steps, so
@@ -122,9 +142,11 @@ def amortised_ms(wall_ms, per, n_builds0, cold_build_ms, rebuild_steps):
     return rest + mean_build / interval
 
 
-def autotune(boxes, t, precision, dt, steps=8, warmup=1, cands=None, cache=DEFAULT_CACHE, log=None, refresh=False):
+def autotune(boxes, t, precision, dt, steps=8, warmup=1, cands=None, cache=DEFAULT_CACHE, log=None, refresh=False,
+             kernel_axes=True):
     """Return (best configuration dict, table of (configuration, ms/step)).
-    t: the particle tensors (restored on return); dt: the step to time."""
+    t: the particle tensors (restored on return); dt: the step to time.
+    kernel_axes: run the second stage over the kernel axes (FP32 modes)."""
     import numpy as np
     import torch
     n_domains = int(np.asarray(boxes).reshape(-1, 3).shape[0])
@@ -139,12 +161,27 @@ def autotune(boxes, t, precision, dt, steps=8, warmup=1, cands=None, cache=DEFAU
         return db[key]["best"], db[key]["table"]
     state = {k: v.clone() for k, v in t.items()}
     table = []
-    try:
-        for cfg in (cands or candidates()):
+
+    def run(cfgs):
+        for cfg in cfgs:
             ms = _time_config(boxes, t, state, cfg, precision, dt, steps, warmup)
             table.append((cfg, ms))
             if log:
                 log("autotune %s: %.2f ms/step" % (cfg, ms))
+
+    try:
+        run(cands or candidates())
+        if kernel_axes and precision != "fp64":
+            stage1 = min(table, key=lambda r: r[1])[0]
+            run(kernel_candidates(stage1))
+            # the best value of each kernel axis together
+            best_of = {}
+            for cfg, ms in table[-len(kernel_candidates(stage1)):]:
+                for ax in ("waves_density", "waves_force", "batch"):
+                    if cfg[ax] and (ax not in best_of or ms < best_of[ax][1]):
+                        best_of[ax] = (cfg[ax], ms)
+            combo = dict(stage1, **{ax: v for ax, (v, _) in best_of.items()})
+            run([combo])
     finally:
         for k in t:
             t[k].copy_(state[k])

@@ -147,6 +147,9 @@ sph_status sph_create(const sph_params* params, void* workspace, size_t bytes, v
     if (p.lists != SPH_LISTS_CELL && p.lists != SPH_LISTS_PARTICLE) return SPH_ERR_INVALID;
     if (p.lists == SPH_LISTS_PARTICLE && p.force_mode != SPH_FORCE_GATHER) return SPH_ERR_INVALID;
     if (p.tile != 0 && p.tile != 256 && p.tile != 512 && p.tile != 1024) return SPH_ERR_INVALID;
+    for (int wv : {p.waves_density, p.waves_force})
+        if (wv != 0 && wv != 4 && wv != 5 && wv != 6 && wv != 8) return SPH_ERR_INVALID;
+    if (p.batch != 0 && p.batch != 16 && p.batch != 32) return SPH_ERR_INVALID;
     for (int k = 0; k < 3 * p.n_domains; k++)
         if (!(p.boxes[k] > 0.0) || !isfinite(p.boxes[k])) return SPH_ERR_INVALID;
     sph_ctx* c = new (std::nothrow) sph_ctx();

@@ -18,15 +18,21 @@
 #include "sph_ctx.h"
 #include "sph_device.h"
 
-#define PD_ENTRIES 32  // list entries per batch of the packed density path
+// List entries staged per batch (NE) and the occupancy target (waves per
+// SIMD, WPE) of the packed density and gather force kernels are template
+// parameters chosen per context (the autotuner's tile and wave axes); the
+// defaults are the measured best at 256^3 clustered.
+#define SPH_DENS_WAVES 6
+#define SPH_FORCEG_WAVES 5
+#define SPH_BATCH 32
 
 // Candidate buffer of the packed density path (one wave): candidates j of
 // all neighbour cells in A's frame, packed 64 at a time, and A's particles.
-template <typename T>
+template <typename T, int NE>
 struct PTile {
     typename vec4<T>::type cand[128];  // j in A's frame, w = m
     typename vec4<T>::type si[64];     // i of A: x, y, z (A frame), H^2 (negative when inactive)
-    EBatchBox<T, PD_ENTRIES> e;
+    EBatchBox<T, NE> e;
 };
 
 // Density sweep of one leaf (at most 64 particles, box pruning).  The
@@ -36,8 +42,8 @@ struct PTile {
 // that particle's in-range mask) and phase 2 i-major (lane = particle,
 // evaluating only the set bits).  Phase 1 keeps every lane busy whatever
 // the leaf's occupancy.
-template <typename T, bool COMP>
-__device__ void density_leaf_packed(const DensArgs& a, int A, PTile<T>& L, int lane)
+template <typename T, bool COMP, int NE>
+__device__ void density_leaf_packed(const DensArgs& a, int A, PTile<T, NE>& L, int lane)
 {
     constexpr bool EXTRAP = sizeof(T) == 4;
     typedef typename vec4<T>::type V4;
@@ -120,8 +126,8 @@ __device__ void density_leaf_packed(const DensArgs& a, int A, PTile<T>& L, int l
     int ncand = 0;
     // cell boxes grow by the displacement since the build plus float rounding
     const double grow = 0.5 * mg + 1e-5 * fmax(hlA, hA);
-    for (int eb = e0; eb < e1; eb += PD_ENTRIES) {
-        const int nbt = min(PD_ENTRIES, e1 - eb);
+    for (int eb = e0; eb < e1; eb += NE) {
+        const int nbt = min(NE, e1 - eb);
         const int nv = load_batch_box<T>(a.list, eb, nbt, lane, a.l_begin, a.l_count, a.l_origin, a.l_lo, a.l_hi,
                                          a.l_hlist, oA, I,
                                          grow, [&](const ListEntry& E) { return E.dist < hA + mg; }, L.e);
@@ -361,21 +367,17 @@ __global__ __launch_bounds__(256) void k_density(DensArgs a)
 // Packed density sweep over the leaves of at most 64 particles (box
 // pruning); the LDS is only the packed candidate buffer, so more waves fit
 // on a CU than with the two-phase tiles.
-#ifndef SPH_DENS_WAVES
-#define SPH_DENS_WAVES 6  // measured best (8 waves spill more than they gain)
-#endif
-template <typename T, bool COMP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPH_DENS_WAVES, 8))) void k_density_packed(
-    DensArgs a)
+template <typename T, bool COMP, int WPE, int NE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_density_packed(DensArgs a)
 {
-    __shared__ PTile<T> tiles[WAVES_PER_WG];
+    __shared__ PTile<T, NE> tiles[WAVES_PER_WG];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (a.gate && uniform(*a.gate) != 0) return;
     const int nL = a.nl_dev ? uniform(*a.nl_dev) : a.n_leaves;
     const int A = uniform(xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_WG + w);
     if (A >= nL) return;
     if (!a.l_active[A] || a.l_count[A] > 64) return;
-    density_leaf_packed<T, COMP>(a, A, tiles[w], lane);
+    density_leaf_packed<T, COMP, NE>(a, A, tiles[w], lane);
 }
 
 __global__ __launch_bounds__(256) void k_density_reset(int64_t n, int n_leaves, double* hlo, double* hhi, uint8_t* conv,
@@ -895,19 +897,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPH_FORCE_W
 // phase 1 j-major (lane = candidate, one ballot per particle of A reaching
 // the tile), phase 2 i-major over the set bits.
 // ---------------------------------------------------------------------------
-#define FG_ENTRIES 32
-
-template <typename T>
+template <typename T, int NE>
 struct GTile {
     typename vec4<T>::type cp[128];   // j in A's frame: x, y, z, m
     typename vec4<T>::type cv[128];   // vx, vy, vz, k_j = A_j (8/pi) / H_j^4
     typename vec2t<T>::type ch[128];  // H_j^2, 1/H_j
     typename vec4<T>::type si[64];    // i of A: x, y, z (A frame), H_i^2 (negative: no particle)
-    EBatchBox<T, FG_ENTRIES> e;
+    EBatchBox<T, NE> e;
 };
 
-template <typename T, bool COMP>
-__device__ void force_leaf_gather(const ForceArgs& a, int A, GTile<T>& L, int lane)
+template <typename T, bool COMP, int NE>
+__device__ void force_leaf_gather(const ForceArgs& a, int A, GTile<T, NE>& L, int lane)
 {
     typedef typename vec4<T>::type V4;
     typedef typename vec2t<T>::type V2;
@@ -998,8 +998,8 @@ __device__ void force_leaf_gather(const ForceArgs& a, int A, GTile<T>& L, int la
         int ncand = 0;
         // cell boxes grow by the displacement since the build plus float rounding
         const double grow = 0.5 * mg + 1e-5 * hA;
-        for (int eb = e0; eb < e1; eb += FG_ENTRIES) {
-            const int nbt = min(FG_ENTRIES, e1 - eb);
+        for (int eb = e0; eb < e1; eb += NE) {
+            const int nbt = min(NE, e1 - eb);
             const double* hl = a.l_hlist;
             const int nv = load_batch_box<T>(a.list, eb, nbt, lane, a.l_begin, a.l_count, a.l_origin, a.l_lo, a.l_hi,
                                              hl, oA, I, grow,
@@ -1111,29 +1111,24 @@ __device__ void force_leaf_gather(const ForceArgs& a, int A, GTile<T>& L, int la
     if (lane == 0 && ndens_w) atomicAdd(&a.counters[CNT_NDENS_F], ndens_w);
 }
 
-#ifndef SPH_FORCEG_WAVES
-#define SPH_FORCEG_WAVES 5
-#endif
-
-template <typename T, bool COMP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPH_FORCEG_WAVES, 8))) void k_force_gather(
-    ForceArgs a)
+template <typename T, bool COMP, int WPE, int NE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_force_gather(ForceArgs a)
 {
-    __shared__ GTile<T> tiles[WAVES_PER_WG];
+    __shared__ GTile<T, NE> tiles[WAVES_PER_WG];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (a.gate && uniform(*a.gate) != 1) return;
     const int nL = a.nl_dev ? uniform(*a.nl_dev) : a.n_leaves;
     if (!a.persistent) {
         const int A = uniform(xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_WG + w);
         if (A >= nL) return;
-        force_leaf_gather<T, COMP>(a, A, tiles[w], lane);
+        force_leaf_gather<T, COMP, NE>(a, A, tiles[w], lane);
         return;
     }
     int k = 0;
     for (int it = 0; it <= nL; it++) {
         const int A = xq_pop(&a.counters[XQ_FORCE], nL, k, lane);
         if (A < 0) break;
-        force_leaf_gather<T, COMP>(a, A, tiles[w], lane);
+        force_leaf_gather<T, COMP, NE>(a, A, tiles[w], lane);
     }
 }
 
@@ -1322,6 +1317,64 @@ static void dens_args(sph_ctx* c, const int* gate, bool graph, DensArgs& a, int&
     nb = blocks_for(nl, WAVES_PER_WG);
 }
 
+// The packed density and gather force kernels of the context's occupancy
+// target and batch size (FP64: the defaults only).
+template <typename T, bool COMP>
+static void density_packed_wb(int wpe, int ne, int nb, hipStream_t s, const DensArgs& a)
+{
+    if (ne == 16) {
+        switch (wpe) {
+        case 4: k_density_packed<T, COMP, 4, 16><<<nb, 256, 0, s>>>(a); return;
+        case 5: k_density_packed<T, COMP, 5, 16><<<nb, 256, 0, s>>>(a); return;
+        case 8: k_density_packed<T, COMP, 8, 16><<<nb, 256, 0, s>>>(a); return;
+        default: k_density_packed<T, COMP, 6, 16><<<nb, 256, 0, s>>>(a); return;
+        }
+    }
+    switch (wpe) {
+    case 4: k_density_packed<T, COMP, 4, 32><<<nb, 256, 0, s>>>(a); return;
+    case 5: k_density_packed<T, COMP, 5, 32><<<nb, 256, 0, s>>>(a); return;
+    case 8: k_density_packed<T, COMP, 8, 32><<<nb, 256, 0, s>>>(a); return;
+    default: k_density_packed<T, COMP, 6, 32><<<nb, 256, 0, s>>>(a); return;
+    }
+}
+
+static void launch_density_packed(sph_ctx* c, int nb, const DensArgs& a)
+{
+    const int wpe = c->prm.waves_density ? c->prm.waves_density : SPH_DENS_WAVES;
+    const int ne = c->prm.batch ? c->prm.batch : SPH_BATCH;
+    if (c->prm.precision == SPH_FP64) k_density_packed<double, false, SPH_DENS_WAVES, SPH_BATCH><<<nb, 256, 0, c->stream>>>(a);
+    else if (c->prm.precision == SPH_FP32C) density_packed_wb<float, true>(wpe, ne, nb, c->stream, a);
+    else density_packed_wb<float, false>(wpe, ne, nb, c->stream, a);
+}
+
+template <typename T, bool COMP>
+static void force_gather_wb(int wpe, int ne, int nb, hipStream_t s, const ForceArgs& a)
+{
+    if (ne == 16) {
+        switch (wpe) {
+        case 4: k_force_gather<T, COMP, 4, 16><<<nb, 256, 0, s>>>(a); return;
+        case 6: k_force_gather<T, COMP, 6, 16><<<nb, 256, 0, s>>>(a); return;
+        case 8: k_force_gather<T, COMP, 8, 16><<<nb, 256, 0, s>>>(a); return;
+        default: k_force_gather<T, COMP, 5, 16><<<nb, 256, 0, s>>>(a); return;
+        }
+    }
+    switch (wpe) {
+    case 4: k_force_gather<T, COMP, 4, 32><<<nb, 256, 0, s>>>(a); return;
+    case 6: k_force_gather<T, COMP, 6, 32><<<nb, 256, 0, s>>>(a); return;
+    case 8: k_force_gather<T, COMP, 8, 32><<<nb, 256, 0, s>>>(a); return;
+    default: k_force_gather<T, COMP, 5, 32><<<nb, 256, 0, s>>>(a); return;
+    }
+}
+
+static void launch_force_gather(sph_ctx* c, int nb, const ForceArgs& a)
+{
+    const int wpe = c->prm.waves_force ? c->prm.waves_force : SPH_FORCEG_WAVES;
+    const int ne = c->prm.batch ? c->prm.batch : SPH_BATCH;
+    if (c->prm.precision == SPH_FP64) k_force_gather<double, false, SPH_FORCEG_WAVES, SPH_BATCH><<<nb, 256, 0, c->stream>>>(a);
+    else if (c->prm.precision == SPH_FP32C) force_gather_wb<float, true>(wpe, ne, nb, c->stream, a);
+    else force_gather_wb<float, false>(wpe, ne, nb, c->stream, a);
+}
+
 // Density sweeps run as a grid of one wave per leaf in every execution mode:
 // the persistent queues were slower here (first sweep 10.2 against 10.0 ms
 // at 256^3, and the later sweeps, with most leaves converged, pay a pop per
@@ -1335,9 +1388,7 @@ static sph_status launch_density(sph_ctx* c, const int* gate, bool graph = false
     if (nb <= 0) return SPH_OK;
     const bool srt = c->prm.prune == SPH_PRUNE_SORTED;
     if (!srt) {
-        if (c->prm.precision == SPH_FP64) k_density_packed<double, false><<<nb, 256, 0, c->stream>>>(a);
-        else if (c->prm.precision == SPH_FP32C) k_density_packed<float, true><<<nb, 256, 0, c->stream>>>(a);
-        else k_density_packed<float, false><<<nb, 256, 0, c->stream>>>(a);
+        launch_density_packed(c, nb, a);
         SPH_CHECK_LAUNCH();
         // leaves above 64 particles (cells that cannot be split further):
         // the chunked two-phase kernel over a plain grid
@@ -1658,9 +1709,7 @@ static sph_status launch_force(sph_ctx* c, const int* gate, bool graph = false)
     int nb = 0;
     force_args(c, gate, graph, a, nb);
     if (nb > 0 && c->prm.force_mode == SPH_FORCE_GATHER) {
-        if (c->prm.precision == SPH_FP64) k_force_gather<double, false><<<nb, 256, 0, c->stream>>>(a);
-        else if (c->prm.precision == SPH_FP32C) k_force_gather<float, true><<<nb, 256, 0, c->stream>>>(a);
-        else k_force_gather<float, false><<<nb, 256, 0, c->stream>>>(a);
+        launch_force_gather(c, nb, a);
         SPH_CHECK_LAUNCH();
     } else if (nb > 0) {
         const bool srt = c->prm.prune == SPH_PRUNE_SORTED;
@@ -1826,6 +1875,9 @@ static std::vector<uint8_t> graph_key(sph_ctx* c, const double* u, const double*
     key_put(k, c->n_chunks);
     key_put(k, c->prm.lists);
     key_put(k, c->prm.tile);
+    key_put(k, c->prm.waves_density);
+    key_put(k, c->prm.waves_force);
+    key_put(k, c->prm.batch);
     return k;
 }
 

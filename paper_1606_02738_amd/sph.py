@@ -50,7 +50,8 @@ class Params(C.Structure):
                 ("precision", C.c_int), ("exec_mode", C.c_int), ("n_domains", C.c_int),
                 ("persistent_wgs", C.c_int), ("use_graph", C.c_int), ("prune", C.c_int),
                 ("rebuild_steps", C.c_int), ("h_drift", C.c_int), ("force_mode", C.c_int),
-                ("lists", C.c_int), ("tile", C.c_int), ("boxes", C.POINTER(C.c_double))]
+                ("lists", C.c_int), ("tile", C.c_int), ("waves_density", C.c_int), ("waves_force", C.c_int),
+                ("batch", C.c_int), ("boxes", C.POINTER(C.c_double))]
 
 
 class Particles(C.Structure):
@@ -234,7 +235,8 @@ class SPH:
     def __init__(self, boxes, precision="fp32c", exec_mode="grid", gamma=5.0 / 3.0, eta=1.2348,
                  kernel_gamma=math.sqrt(10.0 / 3.0), h_tol=None, max_h_iter=40, n_split=64,
                  persistent_wgs=0, prune="box", use_graph=False, rebuild_steps=0, h_drift=True, force=None,
-                 lists="cell", tile=0, workspace_bytes=None, stream=None):
+                 lists="cell", tile=0, waves_density=0, waves_force=0, batch=0, workspace_bytes=None,
+                 stream=None):
         import torch
         self._torch = torch
         b = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(-1, 3))
@@ -256,6 +258,7 @@ class SPH:
         p.force_mode = FORCE_MODES[force] if isinstance(force, str) else int(force)
         p.lists = LIST_MODES[lists] if isinstance(lists, str) else int(lists)
         p.tile = int(tile)
+        p.waves_density, p.waves_force, p.batch = int(waves_density), int(waves_force), int(batch)
         p.boxes = b.ctypes.data_as(C.POINTER(C.c_double))
         self.params = p
         s = stream if stream is not None else torch.cuda.current_stream()

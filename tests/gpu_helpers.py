@@ -21,14 +21,14 @@ def log(msg):
 
 def gpu_run(d, precision="fp32c", exec_mode="grid", n_split=64, stages=("density", "ghost", "force"),
             max_h_iter=40, h_tol=None, prune="box", use_graph=False, force="pairs", lists="cell",
-            rebuild_steps=0):
+            rebuild_steps=0, **kernel):
     """Build, sort and run the requested stages; returns (host dict in the
     original particle order, stats)."""
     import torch
     boxes = d["boxes"] if d["boxes"].shape[0] > 1 else d["box"]
     sim = S.SPH(boxes, precision=precision, exec_mode=exec_mode, n_split=n_split,
                 max_h_iter=max_h_iter, h_tol=h_tol, prune=prune, use_graph=use_graph, force=force,
-                lists=lists, rebuild_steps=rebuild_steps)
+                lists=lists, rebuild_steps=rebuild_steps, **kernel)
     t = S.to_device(d)
     sim.bind(t)
     sim.build_cells()

@@ -59,7 +59,8 @@ def _params(**kw):
                                  dict(n_split=0), dict(n_split=65), dict(precision=7),
                                  dict(exec_mode=3), dict(n_domains=0), dict(prune=2), dict(use_graph=2), dict(rebuild_steps=-1),
                                  dict(h_drift=2), dict(force_mode=2), dict(force_mode=1, prune=1),
-                                 dict(lists=2), dict(lists=1, force_mode=0), dict(tile=100)])
+                                 dict(lists=2), dict(lists=1, force_mode=0), dict(tile=100),
+                                 dict(waves_density=3), dict(waves_force=7), dict(batch=8)])
 def test_create_rejects_bad_params(L, bad):
     p, box = _params(**bad)
     h = C.c_void_p()

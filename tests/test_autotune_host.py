@@ -55,3 +55,15 @@ def test_candidates_are_valid_combinations():
             assert 1 <= c["n_split"] <= 64
     keys = {tuple(sorted(c.items())) for c in AT.candidates()}
     assert len(keys) == len(AT.candidates())
+
+
+def test_kernel_candidates_sweep_each_axis_around_the_best():
+    best = dict(n_split=64, exec_mode="persistent", persistent_wgs=2048, prune="box", use_graph=False,
+                rebuild_steps=64, force="gather")
+    cands = AT.kernel_candidates(best)
+    assert len(cands) == 2 * len(AT.KERNEL_WAVES) + len(AT.KERNEL_BATCH)
+    for c in cands:
+        assert {k: c[k] for k in best} == best
+        assert sum(1 for ax in ("waves_density", "waves_force", "batch") if c[ax]) == 1
+    assert {c["waves_density"] for c in cands} == {0, *AT.KERNEL_WAVES}
+    assert {c["batch"] for c in cands} == {0, *AT.KERNEL_BATCH}
