@@ -75,7 +75,9 @@ typedef struct {
     double kernel_gamma; /* H / h_DA for the cubic spline, sqrt(10/3) */
     double h_tol;        /* converged when |rho H^3 - C| <= h_tol * C (FP64 test); the FP32
                             modes use at least 2.5e-7 (SPH_FP32C) or 2e-6 (SPH_FP32), the
-                            resolution of their sums */
+                            resolution of their sums, and finish every converged particle
+                            with one Newton update of H whose rho and drho/dH come from
+                            the second-order expansion of the sums (no further sweep) */
     int max_h_iter;      /* smoothing-length sweeps per density call */
     int n_split;         /* split cells holding more than this many particles (<= 64) */
     int precision;       /* SPH_FP64, SPH_FP32C (cell-relative FP32, compensated sums)

@@ -314,6 +314,22 @@ __device__ inline bool dens_newton(const DensArgs& a, int i, double H, double Sw
     if (a.nngb) a.nngb[i] = cnt;
     bool left = false;
     bool done = fabs(f) <= a.h_tol * C;
+    if (done && EXTRAP && f != 0.0) {
+        // FP32 modes: the residual accepted here still moves rho by
+        // f/C |1 - 1/Omega|; one Newton update of H with rho H^3 and its
+        // H-derivative from their second-order expansion (as below) leaves
+        // only the second-order term
+        const double dH = -f / fp;
+        const double Hn = H + dH;
+        if (fabs(dH) <= 1e-3 * H && Hn <= hlA && Hn <= s0min) {
+            const double F1 = INV_PI_8 * Sw + fp * dH + 0.5 * F2 * dH * dH;
+            const double F1p = fp + F2 * dH;
+            const double H3 = Hn * Hn * Hn;
+            a.H[i] = Hn;
+            a.rho[i] = F1 / H3;
+            a.drho[i] = F1p / H3 - 3.0 * F1 / (H3 * Hn);
+        }
+    }
     if (!done) {
         double lo = a.hlo[i], hi = a.hhi[i];
         if (f < 0.0) lo = H;

@@ -244,7 +244,7 @@ class SPH:
         self._boxes = b
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         if h_tol is None:
-            h_tol = {SPH_FP64: 1e-10, SPH_FP32C: 3e-7}.get(prec, 2e-6)
+            h_tol = 1e-10 if prec == SPH_FP64 else 2e-6
         p = Params()
         p.gamma, p.eta, p.kernel_gamma, p.h_tol = gamma, eta, kernel_gamma, h_tol
         p.max_h_iter, p.n_split, p.precision = max_h_iter, n_split, prec
