@@ -60,7 +60,8 @@ def measured_traffic(kernel, workload, cfg):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     h = hashlib.sha256()
-    for src in ("paper_1606_02738_amd/csrc/sph_interact.hip", "paper_1606_02738_amd/csrc/sph_internal.h"):
+    for src in ("paper_1606_02738_amd/csrc/sph_interact.hip", "paper_1606_02738_amd/csrc/sph_device.h",
+                "paper_1606_02738_amd/csrc/sph_internal.h"):
         h.update(open(os.path.join(ROOT, src), "rb").read())
     if kv.get("sources_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in kv:
         return None
