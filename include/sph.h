@@ -287,7 +287,10 @@ sph_status sph_density_ghost_force(sph_ctx* ctx);
  * flow), cell rebuild and sort or, with rebuild_steps > 0, a refresh of the
  * kept cells, density from that start, ghost with the predicted u, force
  * with the predicted v, second half kick fused with the FP64 conservation
- * sums.  Requires a previous sph_force (forces of the current positions). */
+ * sums.  Requires a previous sph_force (forces of the current positions).
+ * A rebuild inside the step reorders the particles without carrying rho,
+ * drho_dH, omega and P along (the density and ghost stages then rewrite
+ * them); after a failed step they are undefined. */
 sph_status sph_step(sph_ctx* ctx, double dt);
 
 /* SPH interpolation, Sec. 2, eq. (interp): out[k] = sum_i m_i Q_i / rho_i

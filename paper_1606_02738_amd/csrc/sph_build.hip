@@ -510,7 +510,7 @@ __global__ __launch_bounds__(256) void k_wnodes(const Node* __restrict__ nodes, 
     o.count = nd.count;
     o.leaf = nd.leaf;
     o.hl = 0.0f;  // set with the list radii (k_node_hmax)
-    o.pad = 0;
+    o.pad = nd.n_child;
     w[k] = o;
 }
 
@@ -542,11 +542,91 @@ __device__ inline float box_dist_f(const float* alo, const float* ahi, const flo
     return sqrtf(d2);
 }
 
-// MODE 0: count the entries of each leaf; 1: write them at the scanned
-// offsets l_off (with `link`, only the leaves it marks incomplete); 2: write
-// the first list_cap entries of leaf A at A * list_cap, the rest into
-// 64-entry chunks of `ovf` taken one at a time (link: [head of each leaf's
-// chain | incomplete flag of each leaf | next chunk]), and count them all.
+// Sort direction of a listed pair: the one of the 13 most aligned with the
+// offset between the box centres (B's image).
+__device__ inline int walk_dir(const double* alo, const double* ahi, const double* blo, const double* bhi,
+                               const double* sv)
+{
+    float cv[3];
+    for (int a = 0; a < 3; a++) cv[a] = (float)(0.5 * (blo[a] + bhi[a]) + sv[a] - 0.5 * (alo[a] + ahi[a]));
+    float bv = -1.f;
+    int best = 0;
+    for (int q = 0; q < SPH_NDIR; q++) {
+        const float v = fabsf(cv[0] * c_dirs[q][0] + cv[1] * c_dirs[q][1] + cv[2] * c_dirs[q][2]);
+        if (v > bv) { bv = v; best = q; }
+    }
+    return best;
+}
+
+// Exact distance between the leaf boxes of A and B's image (shift sv), in
+// the canonical order, so that both lists of a pair hold the same value.
+__device__ inline double walk_pair_dist(int A, int B, const double* alo, const double* ahi, const double* blo,
+                                        const double* bhi, const double* sv)
+{
+    const bool fwd = A <= B;
+    double plo[3], phi[3], qlo[3], qhi[3], s[3];
+    for (int a = 0; a < 3; a++) {
+        plo[a] = fwd ? alo[a] : blo[a];
+        phi[a] = fwd ? ahi[a] : bhi[a];
+        qlo[a] = fwd ? blo[a] : alo[a];
+        qhi[a] = fwd ? bhi[a] : ahi[a];
+        s[a] = fwd ? sv[a] : -sv[a];
+    }
+    return box_dist(plo, phi, qlo, qhi, s);
+}
+
+// Output of one leaf's walk.  MODE 1: at the scanned offsets; MODE 2:
+// the first `len` entries into the leaf's slot, the rest into 64-entry
+// chunks of `ovf` taken one at a time (link: [head of each leaf's chain |
+// state of each leaf | next chunk]); a leaf that finds no free chunk keeps
+// counting and is walked again at the scanned offsets.
+struct WalkSink {
+    size_t base;
+    int len, out, cnt, last;
+    bool failed;
+};
+
+template <int MODE>
+__device__ inline void walk_put(WalkSink& s, int A, const ListEntry& e, ListEntry* list, ListEntry* ovf, int* link,
+                                int* next, int* flags, int ovf_chunks)
+{
+    ListEntry* dst = nullptr;
+    if (s.out < s.len) {
+        dst = list + s.base + s.out;
+    } else if (MODE == 2 && !s.failed) {
+        const int k = s.out - s.len;
+        if ((k & 63) == 0) {
+            const int ch = atomicAdd(flags + FI_WOVF, 1);
+            if (ch >= ovf_chunks) {
+                s.failed = true;
+            } else {
+                if (s.last < 0) link[A] = ch;
+                else next[s.last] = ch;
+                next[ch] = -1;
+                s.last = ch;
+            }
+        }
+        if (!s.failed) dst = ovf + (size_t)s.last * 64 + (k & 63);
+    }
+    if (dst) *dst = e;
+    else if (MODE == 1) atomicOr(flags, FLAG_INVALID);
+    s.out++;
+}
+
+// Closing bookkeeping of a MODE 2 walk of leaf A.
+__device__ inline void walk_close(const WalkSink& s, int A, int n_leaves, int list_cap, int* counts, int* link, int* flags)
+{
+    counts[A] = s.cnt;
+    if (s.cnt > list_cap) atomicMax(flags + FI_MAXLIST, s.cnt);
+    if (s.last < 0) link[A] = -1;
+    link[n_leaves + A] = s.failed ? 1 : 0;
+    if (s.failed) atomicAdd(flags + FI_WINC, 1);
+}
+
+// One thread per leaf A.  MODE 0: count the entries of each leaf; 1: write
+// them at the scanned offsets l_off (with `link`, only the leaves it marks
+// incomplete); 2: write into the slot and overflow chunks and count them
+// (WalkSink).
 template <int MODE>
 __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restrict__ leaf_node, const WNode* __restrict__ wn,
                                               const double* __restrict__ l_lo, const double* __restrict__ l_hi,
@@ -560,8 +640,6 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
     if (A >= n_leaves) return;
     if (MODE == 1 && link && !link[n_leaves + A]) return;
     int* next = link ? link + 2 * (size_t)n_leaves : nullptr;
-    int last = -1;          // this leaf's current overflow chunk
-    bool failed = false;    // no chunk was free: the leaf is walked again
     const DomainInfo& I = di[l_dom[A]];
     const int loc = l_top[A] - I.top_offset;
     const int tc[3] = {loc / (I.n_top[2] * I.n_top[1]), (loc / I.n_top[2]) % I.n_top[1], loc % I.n_top[2]};
@@ -574,10 +652,13 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
     const double alo[3] = {l_lo[3 * A], l_lo[3 * A + 1], l_lo[3 * A + 2]};
     const double ahi[3] = {l_hi[3 * A], l_hi[3 * A + 1], l_hi[3 * A + 2]};
     constexpr bool FILL = MODE != 0;
-    int cnt = 0;
-    const size_t out_base = MODE == 1 ? (size_t)l_off[A] : (MODE == 2 ? (size_t)A * list_cap : 0);
-    const int out_len = MODE == 1 ? l_off[A + 1] - l_off[A] : (MODE == 2 ? list_cap : 0);
-    int out = 0;
+    WalkSink s;
+    s.base = MODE == 1 ? (size_t)l_off[A] : (MODE >= 2 ? (size_t)A * list_cap : 0);
+    s.len = MODE == 1 ? l_off[A + 1] - l_off[A] : (MODE >= 2 ? list_cap : 0);
+    s.out = 0;
+    s.cnt = 0;
+    s.last = -1;
+    s.failed = false;
     for (int sx = -1; sx <= 1; sx++)
     for (int sy = -1; sy <= 1; sy++)
     for (int sz = -1; sz <= 1; sz++) {
@@ -610,68 +691,212 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
                 continue;
             }
             k = nd.next;
-            {
-                // exact distance between the leaf boxes, in the canonical order
-                const int B = nd.leaf;
-                const double blo[3] = {l_lo[3 * B], l_lo[3 * B + 1], l_lo[3 * B + 2]};
-                const double bhi[3] = {l_hi[3 * B], l_hi[3 * B + 1], l_hi[3 * B + 2]};
-                double d;
-                if (A <= B) {
-                    d = box_dist(alo, ahi, blo, bhi, sv);
-                } else {
-                    const double ms[3] = {-sv[0], -sv[1], -sv[2]};
-                    d = box_dist(blo, bhi, alo, ahi, ms);
-                }
-                if (!(d < (sym ? fmax(hA, l_hlist[B]) : hA))) continue;
-                if (FILL) {
-                    ListEntry* dst = nullptr;
-                    if (out < out_len) {
-                        dst = list + out_base + out;
-                    } else if (MODE == 2 && !failed) {
-                        const int k = out - out_len;
-                        if ((k & 63) == 0) {
-                            const int ch = atomicAdd(flags + FI_WOVF, 1);
-                            if (ch >= ovf_chunks) {
-                                failed = true;
-                            } else {
-                                if (last < 0) link[A] = ch;
-                                else next[last] = ch;
-                                next[ch] = -1;
-                                last = ch;
-                            }
-                        }
-                        if (!failed) dst = ovf + (size_t)last * 64 + (k & 63);
-                    }
-                    if (dst) {
-                        int best = 0;
-                        if (with_dir) {
-                            // sort direction: the one of 13 most aligned with the centre offset
-                            float cv[3];
-                            for (int a = 0; a < 3; a++)
-                                cv[a] = (float)(0.5 * (blo[a] + bhi[a]) + sv[a] - 0.5 * (alo[a] + ahi[a]));
-                            float bv = -1.f;
-                            for (int q = 0; q < SPH_NDIR; q++) {
-                                const float v = fabsf(cv[0] * c_dirs[q][0] + cv[1] * c_dirs[q][1] + cv[2] * c_dirs[q][2]);
-                                if (v > bv) { bv = v; best = q; }
-                            }
-                        }
-                        ListEntry e;
-                        e.B = B;
-                        e.code = code_shift | (best << 8);
-                        e.dist = d;
-                        *dst = e;
-                    } else if (MODE == 1) {
-                        atomicOr(flags, FLAG_INVALID);
-                    }
-                    out++;
-                }
-                cnt++;
+            const int B = nd.leaf;
+            const double blo[3] = {l_lo[3 * B], l_lo[3 * B + 1], l_lo[3 * B + 2]};
+            const double bhi[3] = {l_hi[3 * B], l_hi[3 * B + 1], l_hi[3 * B + 2]};
+            const double d = walk_pair_dist(A, B, alo, ahi, blo, bhi, sv);
+            if (!(d < (sym ? fmax(hA, l_hlist[B]) : hA))) continue;
+            if (FILL) {
+                ListEntry e;
+                e.B = B;
+                e.code = code_shift | ((with_dir ? walk_dir(alo, ahi, blo, bhi, sv) : 0) << 8);
+                e.dist = d;
+                walk_put<MODE>(s, A, e, list, ovf, link, next, flags, ovf_chunks);
             }
+            s.cnt++;
         }
     }
-    if (MODE != 1) counts[A] = cnt;
-    if (MODE == 2) {
-        if (cnt > list_cap) atomicMax(flags + FI_MAXLIST, cnt);
+    if (MODE == 0) counts[A] = s.cnt;
+    if (MODE >= 2) walk_close(s, A, n_leaves, list_cap, counts, link, flags);
+}
+
+// Stack entries per wave of the wave walk, and the room it keeps free: a
+// round that pops p cells pushes at most 8p children, so rounds pop no more
+// than keeps 7p below the reserve; one cell at a time (a plain depth-first
+// descent) grows the stack by at most 7 per level below the top grid.
+#define WALK_STACK 1024
+#define WALK_RESERVE (7 * (SPH_MAX_DEPTH + 1))
+static_assert(WALK_STACK - WALK_RESERVE >= 64, "a round must fit");
+
+__device__ inline void walk_wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Float cell test of the wave walk, as a squared distance with a relative
+// margin of 1e-5: it never rejects a cell that box_dist_f(...) <= r accepts
+// (the margin is far above the rounding of the square and of r^2), so the
+// wave walk reaches every cell the one-leaf walk reaches.
+__device__ inline bool walk_near_f(const float* alo, const float* ahi, const float* blo, const float* bhi,
+                                   const float* s, float r)
+{
+    float d2 = 0.f;
+    for (int a = 0; a < 3; a++) {
+        const float g = fmaxf(fmaxf((blo[a] + s[a]) - ahi[a], alo[a] - (bhi[a] + s[a])), 0.f);
+        d2 = fmaf(g, g, d2);
+    }
+    return d2 <= r * r * 1.00001f;
+}
+
+// The MODE 2 walk of one leaf A by a whole wave: the descent of k_walk from
+// the 27 top cells around A's top cell, up to 64 cells per round (one per
+// lane) popped from a stack in LDS, the exact test of each leaf cell reached
+// in its own lane, and the entries of a round appended in lane order (the
+// same order on every run).  Each leaf gets the entries of k_walk<2>: the
+// float test is looser, and every entry passes the same exact test (which
+// implies the float test).  A round's entries go to the slot, then to
+// 64-entry chunks of the pool (at most two new ones per round).  One wave
+// per leaf, four per workgroup.
+__global__ __launch_bounds__(256) void k_walk_wave(int n_leaves, const int* __restrict__ leaf_node,
+                                                   const WNode* __restrict__ wn, const double* __restrict__ l_lo,
+                                                   const double* __restrict__ l_hi, const int* __restrict__ l_dom,
+                                                   const int* __restrict__ l_top, const DomainInfo* __restrict__ di,
+                                                   const double* __restrict__ l_hlist, int* counts,
+                                                   ListEntry* __restrict__ list, int list_cap, int with_dir, int sym,
+                                                   int* flags, ListEntry* ovf, int* link, int ovf_chunks)
+{
+    __shared__ uint32_t stk[4][WALK_STACK];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int A = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + w);
+    if (A >= n_leaves) return;
+    int* next = link + 2 * (size_t)n_leaves;
+    const DomainInfo& I = di[l_dom[A]];
+    const int nt[3] = {I.n_top[0], I.n_top[1], I.n_top[2]};
+    const double L[3] = {I.L[0], I.L[1], I.L[2]};
+    const float Lf[3] = {(float)L[0], (float)L[1], (float)L[2]};
+    const int loc = l_top[A] - I.top_offset;
+    const int tc[3] = {loc / (nt[2] * nt[1]), (loc / nt[2]) % nt[1], loc % nt[2]};
+    const double hA = l_hlist[A];
+    // conservative float radius, as in k_walk
+    const float slack = (float)(1e-6 * fmax(fmax(L[0], L[1]), L[2]));
+    const float prune = (float)(hA * (1.0 + 1e-5)) + slack;
+    const WNode& WA = wn[leaf_node[A]];
+    const float wlo[3] = {WA.lo[0], WA.lo[1], WA.lo[2]}, whi[3] = {WA.hi[0], WA.hi[1], WA.hi[2]};
+    const double alo[3] = {l_lo[3 * A], l_lo[3 * A + 1], l_lo[3 * A + 2]};
+    const double ahi[3] = {l_hi[3 * A], l_hi[3 * A + 1], l_hi[3 * A + 2]};
+    // output state (wave-uniform): entries so far, chunks taken, the last one
+    int out = 0, n_chunks = 0, last = -1;
+    bool failed = false;
+    int size = 0;
+    bool first_round = true;
+    while (first_round || size > 0) {
+        int node = -1, sc = 0;
+        if (first_round) {
+            // the 27 top cells around A's and their periodic images
+            if (lane < 27) {
+                const int o[3] = {lane / 9 - 1, (lane / 3) % 3 - 1, lane % 3 - 1};
+                int cc[3], ps[3];
+                for (int a = 0; a < 3; a++) {
+                    cc[a] = tc[a] + o[a];
+                    ps[a] = cc[a] < 0 ? -1 : (cc[a] >= nt[a] ? 1 : 0);
+                    cc[a] -= ps[a] * nt[a];
+                }
+                node = I.top_offset + (cc[0] * nt[1] + cc[1]) * nt[2] + cc[2];
+                sc = shift_index(ps[0], ps[1], ps[2]);
+            }
+            first_round = false;
+        } else {
+            int p = min(min(64, size), (WALK_STACK - WALK_RESERVE - size) / 7);
+            if (p < 1) p = 1;
+            size -= p;
+            if (lane < p) {
+                const uint32_t e = stk[w][size + lane];
+                node = (int)(e >> 5);
+                sc = (int)(e & 31);
+            }
+        }
+        const int ps[3] = {sc / 9 - 1, (sc / 3) % 3 - 1, sc % 3 - 1};
+        int first = -1, n_child = 0, B = -1;
+        if (node >= 0) {
+            const WNode nd = wn[node];
+            float svf[3];
+            for (int a = 0; a < 3; a++) svf[a] = ps[a] < 0 ? -Lf[a] : (ps[a] > 0 ? Lf[a] : 0.f);
+            if (nd.count != 0 &&
+                walk_near_f(wlo, whi, nd.lo, nd.hi, svf, sym ? fmaxf(prune, nd.hl * 1.00001f + slack) : prune)) {
+                if (nd.first_child >= 0) {
+                    first = nd.first_child;
+                    n_child = nd.pad;
+                } else {
+                    B = nd.leaf;
+                }
+            }
+        }
+        // children go on the stack in lane order (a wave-wide prefix sum)
+        {
+            int pre = n_child;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int t = __shfl_up(pre, off);
+                if (lane >= off) pre += t;
+            }
+            const int total = __builtin_amdgcn_readlane(pre, 63);
+            pre -= n_child;
+            for (int j = 0; j < n_child; j++) stk[w][size + pre + j] = ((uint32_t)(first + j) << 5) | (uint32_t)sc;
+            size += total;
+        }
+        // exact test of the leaf cells reached, one per lane
+        bool hit = false;
+        ListEntry en;
+        if (B >= 0) {
+            double blo[3], bhi[3];
+            for (int a = 0; a < 3; a++) {
+                blo[a] = l_lo[3 * B + a];
+                bhi[a] = l_hi[3 * B + a];
+            }
+            const double sv[3] = {ps[0] * L[0], ps[1] * L[1], ps[2] * L[2]};
+            const double d = walk_pair_dist(A, B, alo, ahi, blo, bhi, sv);
+            hit = d < (sym ? fmax(hA, l_hlist[B]) : hA);
+            en.B = B;
+            en.code = sc | ((with_dir ? walk_dir(alo, ahi, blo, bhi, sv) : 0) << 8);
+            en.dist = d;
+        }
+        const unsigned long long hm = __ballot(hit);
+        if (hm) {
+            const int k = __popcll(hm);
+            const int pos = out + __popcll(hm & ((1ull << lane) - 1ull));
+            // ch[0]: chunk jl of the round's first position past the slot (the
+            // last chunk taken when that one is partly filled), ch[1]: jl + 1
+            const int jl = out > list_cap ? (out - list_cap) >> 6 : 0;
+            int ch[2] = {last, -1};
+            if (!failed && out + k > list_cap) {
+                const int jh = (out + k - 1 - list_cap) >> 6;
+                for (int j = n_chunks; j <= jh; j++) {
+                    int c = 0;
+                    if (lane == 0) c = atomicAdd(flags + FI_WOVF, 1);
+                    c = __builtin_amdgcn_readfirstlane(c);
+                    if (c >= ovf_chunks) {
+                        failed = true;
+                        break;
+                    }
+                    if (lane == 0) {
+                        if (last < 0) link[A] = c;
+                        else next[last] = c;
+                        next[c] = -1;
+                    }
+                    last = c;
+                    n_chunks = j + 1;
+                    ch[j - jl] = c;
+                }
+            }
+            if (hit) {
+                ListEntry* dst = nullptr;
+                if (pos < list_cap) {
+                    dst = list + (size_t)A * list_cap + pos;
+                } else {
+                    const int j = (pos - list_cap) >> 6;
+                    if (j < n_chunks) dst = ovf + (size_t)ch[j - jl] * 64 + ((pos - list_cap) & 63);
+                }
+                if (dst) *dst = en;
+            }
+            out += k;
+        }
+        // the next round reads the stack this one wrote
+        walk_wave_sync();
+    }
+    if (lane == 0) {
+        counts[A] = out;
+        if (out > list_cap) atomicMax(flags + FI_MAXLIST, out);
         if (last < 0) link[A] = -1;
         link[n_leaves + A] = failed ? 1 : 0;
         if (failed) atomicAdd(flags + FI_WINC, 1);
@@ -790,8 +1015,13 @@ static sph_status permute_all(sph_ctx* c, const uint32_t* perm)
 {
     const int64_t n = c->n;
     SPH_TRY(buf_ensure(c->tmp, (size_t)n * 8));
+    // rho, drho_dH, omega and P follow their particles unless the caller's
+    // next stages rewrite them before reading (the build inside a step)
+    const bool dens_out = !c->dens_outputs_dead;
     double* arrs[] = {c->P.x, c->P.y, c->P.z, c->P.vx, c->P.vy, c->P.vz, c->P.u, c->P.m, c->P.H,
-                      c->P.rho, c->P.drho_dH, c->P.omega, c->P.P, c->P.ax, c->P.ay, c->P.az, c->P.dudt};
+                      dens_out ? c->P.rho : nullptr, dens_out ? c->P.drho_dH : nullptr,
+                      dens_out ? c->P.omega : nullptr, dens_out ? c->P.P : nullptr,
+                      c->P.ax, c->P.ay, c->P.az, c->P.dudt};
     const int nb = blocks_for(n, 256);
     for (double* a : arrs) {
         if (!a) continue;
@@ -932,11 +1162,20 @@ sph_status relist(sph_ctx* c)
         SPH_TRY(buf_ensure(c->walk_link, (2 * (size_t)nL + ovf_chunks) * sizeof(int)));
         SPH_CHECK_HIP(hipMemsetAsync(flags + FI_MAXLIST, 0, sizeof(int), c->stream));
         SPH_CHECK_HIP(hipMemsetAsync(flags + FI_WOVF, 0, 2 * sizeof(int), c->stream));
-        k_walk<2><<<blocks_for(nL, 128), 128, 0, c->stream>>>(
-            nL, (const int*)c->leaf_node.p, (const WNode*)c->wnodes.p, (const double*)c->l_lo.p,
-            (const double*)c->l_hi.p, (const int*)c->l_dom.p, (const int*)c->l_cnt.p, (const DomainInfo*)c->dom_d.p,
-            (const double*)c->l_hlist.p, counts, nullptr, (ListEntry*)c->walk_scratch.p, cap, with_dir, sym, flags,
-            (ListEntry*)c->walk_ovf.p, (int*)c->walk_link.p, ovf_chunks);
+        // one wave per leaf (stack entries hold node << 5)
+        if (c->n_nodes < (1 << 27)) {
+            k_walk_wave<<<blocks_for(nL, 4), 256, 0, c->stream>>>(
+                nL, (const int*)c->leaf_node.p, (const WNode*)c->wnodes.p, (const double*)c->l_lo.p,
+                (const double*)c->l_hi.p, (const int*)c->l_dom.p, (const int*)c->l_cnt.p, (const DomainInfo*)c->dom_d.p,
+                (const double*)c->l_hlist.p, counts, (ListEntry*)c->walk_scratch.p, cap, with_dir, sym, flags,
+                (ListEntry*)c->walk_ovf.p, (int*)c->walk_link.p, ovf_chunks);
+        } else {
+            k_walk<2><<<blocks_for(nL, 128), 128, 0, c->stream>>>(
+                nL, (const int*)c->leaf_node.p, (const WNode*)c->wnodes.p, (const double*)c->l_lo.p,
+                (const double*)c->l_hi.p, (const int*)c->l_dom.p, (const int*)c->l_cnt.p, (const DomainInfo*)c->dom_d.p,
+                (const double*)c->l_hlist.p, counts, nullptr, (ListEntry*)c->walk_scratch.p, cap, with_dir, sym, flags,
+                (ListEntry*)c->walk_ovf.p, (int*)c->walk_link.p, ovf_chunks);
+        }
     } else {
         k_walk<0><<<blocks_for(nL, 128), 128, 0, c->stream>>>(
             nL, (const int*)c->leaf_node.p, (const WNode*)c->wnodes.p, (const double*)c->l_lo.p,

@@ -92,6 +92,7 @@ struct sph_ctx {
     DevBuf walk_scratch;          // per-leaf slots of the one-pass list walk
     DevBuf walk_ovf, walk_link;   // its overflow chunks; chunk links (head, incomplete, next)
     int walk_cap = 128;           // entries per slot (grows after an overflow)
+    bool dens_outputs_dead = false;  // the build need not permute rho, drho_dH, omega, P
     DevBuf pos4, fv4, hf;         // kernel-side particle data (T = float or double)
     // per-particle lists (lists = SPH_LISTS_PARTICLE)
     DevBuf pq, pR, plen, plist;   // fixed-point positions + mass, list radii, list lengths, entries

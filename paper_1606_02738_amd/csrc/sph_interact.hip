@@ -2125,7 +2125,12 @@ static sph_status step_impl(sph_ctx* c, double dt)
         // list skin for the coming steps: rebuild_steps times this step's
         // largest displacement
         c->skin_abs = c->prm.rebuild_steps > 0 ? c->prm.rebuild_steps * vmax * dt : 0.0;
-        SPH_TRY(build_all(c));
+        // the density and ghost stages below write rho, drho_dH, omega and P
+        // of every particle (all start unconverged) before anything reads them
+        c->dens_outputs_dead = true;
+        const sph_status sb = build_all(c);
+        c->dens_outputs_dead = false;
+        SPH_TRY(sb);
     }
     SPH_TRY(sort_all(c));
     SPH_CHECK_HIP(hipEventRecord(c->ev[7], c->stream));

@@ -61,7 +61,7 @@ struct WNode {
     int count;
     int leaf;
     float hl;         // upper bound of the list radii of the leaves below (symmetric lists)
-    int pad;
+    int pad;          // children (0 for a leaf cell)
 };
 
 // Neighbour-cell list entry of leaf A: leaf B, periodic image and the
