@@ -187,7 +187,7 @@ sph_status sph_destroy(sph_ctx* c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     DevBuf* all[] = {&c->dom_d, &c->dstat, &c->keys[0], &c->keys[1], &c->vals[0], &c->vals[1], &c->ikeys[0], &c->ikeys[1], &c->ivals[0], &c->ivals[1], &c->dranges, &c->tmp, &c->nodes, &c->wnodes,
-                     &c->nchild, &c->coff, &c->leafmark, &c->leafscan, &c->leaf_node, &c->l_begin, &c->l_count,
+                     &c->nchild, &c->coff, &c->lvl_cmap, &c->lvl_bnd, &c->leafmark, &c->leafscan, &c->leaf_node, &c->l_begin, &c->l_count,
                      &c->l_origin, &c->l_lo, &c->l_hi, &c->l_hlist, &c->l_dom, &c->l_off, &c->l_active, &c->l_sorted,
                      &c->l_cnt, &c->list, &c->pos4, &c->fv4, &c->hf, &c->skey, &c->sidx,
                      &c->hlo, &c->hhi, &c->conv, &c->flags, &c->counters,

@@ -210,8 +210,6 @@ __device__ inline int child_groups(const int* bnd, int n_split, bool allow_merge
     return n;
 }
 
-// Statistics of one cell (bounding box, largest H) and its number of
-// non-empty children if it is to be split.  One workgroup per cell.
 // Whether a cell with these statistics must be split for precision: its
 // extent exceeds h_ratio times its smallest H (FP32 cell-relative
 // coordinates keep an absolute error of ~1e-7 of the cell extent).
@@ -222,118 +220,159 @@ __device__ inline bool extent_too_large(const Node& nd, double h_ratio)
     return ext > h_ratio * nd.hmin;
 }
 
-// Statistics of one cell (bounding box, largest and smallest H) and its
-// number of children if it is to be split.  One workgroup per cell.
-__global__ __launch_bounds__(256) void k_node_stats(Node* nodes, int level_start, const uint64_t* __restrict__ keys,
-                                                    const double* __restrict__ x, const double* __restrict__ y,
-                                                    const double* __restrict__ z, const double* __restrict__ H, int D,
-                                                    int n_split, double h_ratio, int* nchild)
+// Statistics of the cells of one level (bounding box, largest and smallest
+// H) and the particle bounds of their octants, from chunks of up to
+// STATS_CHUNK particles of one cell, one wave per chunk.  Box corners and H
+// are >= 0 (validated), so their doubles order like their bit patterns as
+// signed 64-bit integers (and so do the -inf / +inf starting values): the
+// chunks meet in 64-bit integer atomics min / max, which give exactly the
+// minima and maxima of the doubles.
+#define STATS_CHUNK 1024
+
+__device__ inline void atomic_min_d(double* p, double v)
 {
-    __shared__ double red[8][256];
-    __shared__ int bnd[9];
-    const int k = blockIdx.x;
-    Node* nd = &nodes[level_start + k];
-    const int b = nd->begin, c = nd->count, tid = threadIdx.x;
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, hm = 0.0, hn = INFINITY;
-    for (int p = b + tid; p < b + c; p += 256) {
-        const double q[3] = {x[p], y[p], z[p]};
-        for (int a = 0; a < 3; a++) {
-            lo[a] = fmin(lo[a], q[a]);
-            hi[a] = fmax(hi[a], q[a]);
-        }
-        hm = fmax(hm, H[p]);
-        hn = fmin(hn, H[p]);
-    }
-    for (int a = 0; a < 3; a++) {
-        red[a][tid] = lo[a];
-        red[3 + a][tid] = hi[a];
-    }
-    red[6][tid] = hm;
-    red[7][tid] = hn;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s) {
+    atomicMin((long long*)p, __double_as_longlong(v));
+}
+__device__ inline void atomic_max_d(double* p, double v)
+{
+    atomicMax((long long*)p, __double_as_longlong(v));
+}
+
+// Chunks of each cell, and the octant bounds [bnd[0..8]] of each cell set to
+// its end (the stats pass writes every bound up to the last octant present).
+__global__ __launch_bounds__(256) void k_level_chunks(const Node* __restrict__ nodes, int level_start, int n_level,
+                                                      int* nchunk, int* bnd)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_level) return;
+    const Node& nd = nodes[level_start + k];
+    nchunk[k] = (nd.count + STATS_CHUNK - 1) / STATS_CHUNK;
+    for (int q = 0; q < 9; q++) bnd[9 * k + q] = nd.begin + nd.count;
+}
+
+__global__ __launch_bounds__(256) void k_chunk_map(const int* __restrict__ nchunk, const int* __restrict__ coff,
+                                                   int n_level, int* cmap)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_level) return;
+    for (int j = 0; j < nchunk[k]; j++) cmap[coff[k] + j] = k;
+}
+
+// One wave per chunk (grid-stride over the n_chunks[0] chunks).  Octant of a
+// particle in a cell of level `level`: key bits 3 (D - level - 1) and up; the
+// first particle of each octant present sets the bounds from the previous
+// octant present (exclusive) to its own (inclusive).
+__global__ __launch_bounds__(256) void k_level_stats(Node* nodes, int level_start, int level, const int* __restrict__ coff,
+                                                     const int* __restrict__ cmap, const int* __restrict__ n_chunks,
+                                                     const uint64_t* __restrict__ keys, const double* __restrict__ x,
+                                                     const double* __restrict__ y, const double* __restrict__ z,
+                                                     const double* __restrict__ H, int D, int* bnd)
+{
+    const int lane = threadIdx.x & 63;
+    const int T = __builtin_amdgcn_readfirstlane(*n_chunks);
+    const int shift = 3 * (D - level - 1);
+    for (int q = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6)); q < T; q += gridDim.x * 4) {
+        const int k = __builtin_amdgcn_readfirstlane(cmap[q]);
+        Node* nd = &nodes[level_start + k];
+        const int b = nd->begin, c = nd->count;
+        const bool octants = level < D && !nd->merged;
+        const int i0 = b + (q - coff[k]) * STATS_CHUNK, i1 = min(b + c, i0 + STATS_CHUNK);
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        double hm = 0.0, hn = INFINITY;
+        for (int i = i0 + lane; i < i1; i += 64) {
+            const double p[3] = {x[i], y[i], z[i]}, h = H[i];
             for (int a = 0; a < 3; a++) {
-                red[a][tid] = fmin(red[a][tid], red[a][tid + s]);
-                red[3 + a][tid] = fmax(red[3 + a][tid], red[3 + a][tid + s]);
+                lo[a] = fmin(lo[a], p[a]);
+                hi[a] = fmax(hi[a], p[a]);
             }
-            red[6][tid] = fmax(red[6][tid], red[6][tid + s]);
-            red[7][tid] = fmin(red[7][tid], red[7][tid + s]);
+            hm = fmax(hm, h);
+            hn = fmin(hn, h);
+            if (octants) {
+                const int o = (int)((keys[i] >> shift) & 7);
+                const int op = i > b ? (int)((keys[i - 1] >> shift) & 7) : -1;
+                for (int r = op + 1; r <= o; r++) bnd[9 * k + r] = i;
+            }
         }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        for (int a = 0; a < 3; a++) {
-            nd->lo[a] = red[a][0];
-            nd->hi[a] = red[3 + a][0];
+        for (int off = 32; off > 0; off >>= 1) {
+            for (int a = 0; a < 3; a++) {
+                lo[a] = fmin(lo[a], __shfl_xor(lo[a], off));
+                hi[a] = fmax(hi[a], __shfl_xor(hi[a], off));
+            }
+            hm = fmax(hm, __shfl_xor(hm, off));
+            hn = fmin(hn, __shfl_xor(hn, off));
         }
-        nd->hmax = red[6][0];
-        nd->hmin = red[7][0];
-    }
-    __syncthreads();
-    const bool wide = extent_too_large(*nd, h_ratio);
-    const bool split = !nd->merged && nd->level < D && (c > n_split || wide);
-    if (split && tid < 9) {
-        const uint64_t step = 1ull << (3 * (D - nd->level - 1));
-        bnd[tid] = (tid == 0) ? b : (tid == 8 ? b + c : lower_bound_u64(keys, b, b + c, nd->key_lo + step * tid));
-    }
-    __syncthreads();
-    if (tid == 0) {
-        int nc = 0;
-        if (split) {
-            int gq[8], gb[8], gc[8];
-            nc = child_groups(bnd, n_split, !wide, gq, gb, gc);
+        if (lane == 0) {
+            for (int a = 0; a < 3; a++) {
+                atomic_min_d(&nd->lo[a], lo[a]);
+                atomic_max_d(&nd->hi[a], hi[a]);
+            }
+            atomic_max_d(&nd->hmax, hm);
+            atomic_min_d(&nd->hmin, hn);
         }
-        nchild[k] = nc;
-        nd->n_child = nc;
-        nd->first_child = -1;
     }
 }
 
-__global__ __launch_bounds__(64) void k_emit_children(Node* nodes, int level_start, int n_level, const int* __restrict__ coff,
-                                                      int child_base, const uint64_t* __restrict__ keys, int D, int n_split,
-                                                      double h_ratio)
+// Whether each cell of the level is split and into how many children.  One
+// thread per cell.
+__global__ __launch_bounds__(256) void k_level_split(Node* nodes, int level_start, int n_level, int D, int n_split,
+                                                     double h_ratio, const int* __restrict__ bnd, int* nchild)
 {
-    const int k = blockIdx.x;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_level) return;
+    Node* nd = &nodes[level_start + k];
+    const bool wide = extent_too_large(*nd, h_ratio);
+    const bool split = !nd->merged && nd->level < D && (nd->count > n_split || wide);
+    int nc = 0;
+    if (split) {
+        int bq[9], gq[8], gb[8], gc[8];
+        for (int q = 0; q < 9; q++) bq[q] = bnd[9 * k + q];
+        nc = child_groups(bq, n_split, !wide, gq, gb, gc);
+    }
+    nchild[k] = nc;
+    nd->n_child = nc;
+    nd->first_child = -1;
+}
+
+// The children of the split cells, at the scanned offsets.  One thread per
+// cell.
+__global__ __launch_bounds__(256) void k_emit_children(Node* nodes, int level_start, int n_level, const int* __restrict__ coff,
+                                                       int child_base, int D, int n_split, double h_ratio,
+                                                       const int* __restrict__ bnd)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_level) return;
     Node* nd = &nodes[level_start + k];
     if (nd->n_child == 0) return;
-    __shared__ int bnd[9];
-    const int tid = threadIdx.x;
-    const int b = nd->begin, c = nd->count;
     const uint64_t step = 1ull << (3 * (D - nd->level - 1));
-    if (tid < 9) bnd[tid] = (tid == 0) ? b : (tid == 8 ? b + c : lower_bound_u64(keys, b, b + c, nd->key_lo + step * tid));
-    __syncthreads();
-    if (tid == 0) {
-        int gq[8], gb[8], gc[8];
-        const int ng = child_groups(bnd, n_split, !extent_too_large(*nd, h_ratio), gq, gb, gc);
-        const int out = child_base + coff[k];
-        nd->first_child = out;
-        for (int g = 0; g < ng; g++) {
-            const int q = gq[g];
-            Node ch;
-            ch.key_lo = nd->key_lo + step * q;
-            ch.begin = gb[g];
-            ch.count = gc[g];
-            ch.first_child = -1;
-            ch.n_child = 0;
-            ch.level = nd->level + 1;
-            ch.domain = nd->domain;
-            ch.leaf = -1;
-            ch.top = nd->top;
-            const int o[3] = {(q >> 2) & 1, (q >> 1) & 1, q & 1};
-            for (int a = 0; a < 3; a++) {
-                ch.c_sz[a] = 0.5 * nd->c_sz[a];
-                ch.c_lo[a] = nd->c_lo[a] + o[a] * ch.c_sz[a];
-                ch.lo[a] = INFINITY;
-                ch.hi[a] = -INFINITY;
-            }
-            ch.hmax = 0.0;
-            ch.hmin = INFINITY;
-            ch.merged = (q + 1 < 8 && gb[g] + gc[g] > bnd[q + 1]) ? 1 : 0;
-            ch.pad = 0;
-            nodes[out + g] = ch;
+    int bq[9], gq[8], gb[8], gc[8];
+    for (int q = 0; q < 9; q++) bq[q] = bnd[9 * k + q];
+    const int ng = child_groups(bq, n_split, !extent_too_large(*nd, h_ratio), gq, gb, gc);
+    const int out = child_base + coff[k];
+    nd->first_child = out;
+    for (int g = 0; g < ng; g++) {
+        const int q = gq[g];
+        Node ch;
+        ch.key_lo = nd->key_lo + step * q;
+        ch.begin = gb[g];
+        ch.count = gc[g];
+        ch.first_child = -1;
+        ch.n_child = 0;
+        ch.level = nd->level + 1;
+        ch.domain = nd->domain;
+        ch.leaf = -1;
+        ch.top = nd->top;
+        const int o[3] = {(q >> 2) & 1, (q >> 1) & 1, q & 1};
+        for (int a = 0; a < 3; a++) {
+            ch.c_sz[a] = 0.5 * nd->c_sz[a];
+            ch.c_lo[a] = nd->c_lo[a] + o[a] * ch.c_sz[a];
+            ch.lo[a] = INFINITY;
+            ch.hi[a] = -INFINITY;
         }
+        ch.hmax = 0.0;
+        ch.hmin = INFINITY;
+        ch.merged = (q + 1 < 8 && gb[g] + gc[g] > bq[q + 1]) ? 1 : 0;
+        ch.pad = 0;
+        nodes[out + g] = ch;
     }
 }
 
@@ -1368,10 +1407,27 @@ sph_status build_all(sph_ctx* c)
     int level_start = 0, n_level = top, n_nodes = top;
     c->depth = 0;
     for (int level = 0; level <= D; level++) {
+        // chunks of the level: one per STATS_CHUNK particles of each cell, at
+        // most n / STATS_CHUNK + the level's cells
+        SPH_TRY(buf_ensure(c->lvl_cmap, ((size_t)n / STATS_CHUNK + n_level + 1) * sizeof(int)));
         SPH_TRY(buf_ensure(c->nchild, (size_t)(n_level + 1) * sizeof(int)));
+        SPH_TRY(buf_ensure(c->coff, (size_t)(n_level + 1) * sizeof(int)));
+        SPH_TRY(buf_ensure(c->lvl_bnd, (size_t)n_level * 9 * sizeof(int)));
         int* nchild = (int*)c->nchild.p;
-        k_node_stats<<<n_level, 256, 0, c->stream>>>((Node*)c->nodes.p, level_start, keys, c->P.x, c->P.y, c->P.z,
-                                                     c->P.H, D, c->prm.n_split, h_ratio, nchild);
+        int* ccoff = (int*)c->coff.p;
+        int* bnd = (int*)c->lvl_bnd.p;
+        const int nbl = blocks_for(n_level, 256);
+        k_level_chunks<<<nbl, 256, 0, c->stream>>>((const Node*)c->nodes.p, level_start, n_level, nchild, bnd);
+        SPH_CHECK_LAUNCH();
+        SPH_TRY(scan_exclusive(c, nchild, ccoff, n_level, flags + FI_NCHUNK));
+        k_chunk_map<<<nbl, 256, 0, c->stream>>>(nchild, ccoff, n_level, (int*)c->lvl_cmap.p);
+        SPH_CHECK_LAUNCH();
+        k_level_stats<<<2048, 256, 0, c->stream>>>((Node*)c->nodes.p, level_start, level, ccoff,
+                                                   (const int*)c->lvl_cmap.p, flags + FI_NCHUNK, keys, c->P.x, c->P.y,
+                                                   c->P.z, c->P.H, D, bnd);
+        SPH_CHECK_LAUNCH();
+        k_level_split<<<nbl, 256, 0, c->stream>>>((Node*)c->nodes.p, level_start, n_level, D, c->prm.n_split, h_ratio,
+                                                  bnd, nchild);
         SPH_CHECK_LAUNCH();
         SPH_TRY(scan_exclusive(c, nchild, nchild, n_level, flags + FI_NCHILD));
         int total = 0;
@@ -1389,8 +1445,8 @@ sph_status build_all(sph_ctx* c)
             c->nodes = nb2;
             cap = ncap;
         }
-        k_emit_children<<<n_level, 64, 0, c->stream>>>((Node*)c->nodes.p, level_start, n_level, nchild, n_nodes, keys, D,
-                                                       c->prm.n_split, h_ratio);
+        k_emit_children<<<nbl, 256, 0, c->stream>>>((Node*)c->nodes.p, level_start, n_level, nchild, n_nodes, D,
+                                                     c->prm.n_split, h_ratio, bnd);
         SPH_CHECK_LAUNCH();
         level_start = n_nodes;
         n_level = total;

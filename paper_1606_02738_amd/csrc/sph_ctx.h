@@ -83,7 +83,8 @@ struct sph_ctx {
     DevBuf dranges;               // per-box particle ranges [n_domains + 1]
     const void* keys_sorted = nullptr;  // sorted Morton keys of the last build
     DevBuf tmp;                   // permutation scratch (8 B per particle)
-    DevBuf nodes, nchild, coff;   // octree
+    DevBuf nodes, nchild, coff;   // octree; per level: children, chunk offsets
+    DevBuf lvl_cmap, lvl_bnd;     // per level: chunk -> cell, octant bounds (9 per cell)
     DevBuf wnodes;                // compact cells for the list walk
     DevBuf leafmark, leafscan;    // per particle
     DevBuf leaf_node;             // leaf -> node

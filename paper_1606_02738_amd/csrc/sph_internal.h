@@ -124,7 +124,7 @@ enum {
 
 // Slots of the int[64] flags buffer.
 enum { FI_FLAGS = 0, FI_SCRATCH = 8, FI_NCHILD = 9, FI_NLEAVES = 10, FI_NLIST = 11, FI_GATE = 12, FI_MAXLEAF = 13, FI_MAXLIST = 14, FI_PLROWS = 15, FI_WOVF = 16,
-       FI_WINC = 17, FI_NFLAGS = 64 };
+       FI_WINC = 17, FI_NCHUNK = 18, FI_NFLAGS = 64 };
 
 // Counters written by kernels (device, int64).
 enum { CNT_UNCONV = 0, CNT_NDENS = 1, CNT_NFORCE = 2, CNT_NPLIST = 3, CNT_DEVAL = 5, CNT_NPAIR = 6, CNT_NDENS_F = 7, CNT_GSWEEPS = 8, CNT_UHIST = 9, CNT_N = 16 };
