@@ -42,32 +42,54 @@ __global__ __launch_bounds__(256) void k_validate(int64_t n, const double* __res
     bool bad = false;
     const int64_t per = (n + gridDim.x - 1) / gridDim.x;
     const int64_t b0 = (int64_t)blockIdx.x * per, b1 = min(n, b0 + per);
-    for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
-        const int d = dom ? dom[i] : 0;
-        if (d < 0 || d >= ndom) {
-            bad = true;
-            continue;
+    // four particles per thread and round, their loads issued together
+    constexpr int U = 4;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += U * blockDim.x) {
+        double px[U], py[U], pz[U], h[U], mm[U];
+        int d[U];
+        for (int u = 0; u < U; u++) {
+            const int64_t j = min(i + (int64_t)u * blockDim.x, b1 - 1);
+            d[u] = dom ? dom[j] : 0;
+            px[u] = x[j];
+            py[u] = y[j];
+            pz[u] = z[j];
+            h[u] = H[j];
+            mm[u] = m[j];
         }
-        const double* L = di[d].L;
-        const double px = x[i], py = y[i], pz = z[i], h = H[i], mm = m[i];
-        const bool good = isfinite(px) && isfinite(py) && isfinite(pz) && px >= 0.0 && px < L[0] && py >= 0.0 &&
-                          py < L[1] && pz >= 0.0 && pz < L[2] && isfinite(h) && h > 0.0 && isfinite(mm) && mm > 0.0;
-        if (!good) {
-            bad = true;
-            continue;
+        for (int u = 0; u < U; u++) {
+            if (i + (int64_t)u * blockDim.x >= b1) break;
+            if (d[u] < 0 || d[u] >= ndom) {
+                bad = true;
+                continue;
+            }
+            const double* L = di[d[u]].L;
+            const bool good = isfinite(px[u]) && isfinite(py[u]) && isfinite(pz[u]) && px[u] >= 0.0 && px[u] < L[0] &&
+                              py[u] >= 0.0 && py[u] < L[1] && pz[u] >= 0.0 && pz[u] < L[2] && isfinite(h[u]) &&
+                              h[u] > 0.0 && isfinite(mm[u]) && mm[u] > 0.0;
+            if (!good) {
+                bad = true;
+                continue;
+            }
+            if (d[u] != dcur) {
+                if (dcur >= 0) flush_hrange(dstat, dcur, hmx, hmn, cnt);
+                dcur = d[u];
+                hmx = 0.0;
+                hmn = INFINITY;
+                cnt = 0;
+            }
+            hmx = fmax(hmx, h[u]);
+            hmn = fmin(hmn, h[u]);
+            cnt++;
         }
-        if (d != dcur) {
-            if (dcur >= 0) flush_hrange(dstat, dcur, hmx, hmn, cnt);
-            dcur = d;
-            hmx = 0.0;
-            hmn = INFINITY;
-            cnt = 0;
-        }
-        hmx = fmax(hmx, h);
-        hmn = fmin(hmn, h);
-        cnt++;
     }
     if (bad) atomicOr(flags, FLAG_INVALID);
+    // all lanes of a wave on one box: reduce across the wave, and across the
+    // workgroup when its four waves share that box (one atomic triple per
+    // workgroup: all of them meet on the same address when there is one box)
+    __shared__ int wd[4];
+    __shared__ double wmx[4], wmn[4];
+    __shared__ unsigned long long wcnt[4];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int d0 = __shfl(dcur, 0);
     const bool uni = __ballot(dcur != d0) == 0ull;
     if (uni && d0 >= 0) {
@@ -76,7 +98,22 @@ __global__ __launch_bounds__(256) void k_validate(int64_t n, const double* __res
             hmn = fmin(hmn, __shfl_xor(hmn, off));
             cnt += __shfl_xor(cnt, off);
         }
-        if ((threadIdx.x & 63) == 0) flush_hrange(dstat, d0, hmx, hmn, cnt);
+    }
+    if (lane == 0) {
+        wd[w] = uni ? d0 : -2;  // -2: the wave flushes lane by lane
+        wmx[w] = hmx;
+        wmn[w] = hmn;
+        wcnt[w] = cnt;
+    }
+    __syncthreads();
+    const int db = wd[0];
+    const bool block_uni = db >= 0 && wd[1] == db && wd[2] == db && wd[3] == db && blockDim.x == 256;
+    if (block_uni) {
+        if (threadIdx.x == 0)
+            flush_hrange(dstat, db, fmax(fmax(wmx[0], wmx[1]), fmax(wmx[2], wmx[3])),
+                         fmin(fmin(wmn[0], wmn[1]), fmin(wmn[2], wmn[3])), wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3]);
+    } else if (uni && d0 >= 0) {
+        if (lane == 0) flush_hrange(dstat, d0, hmx, hmn, cnt);
     } else if (dcur >= 0) {
         flush_hrange(dstat, dcur, hmx, hmn, cnt);
     }
@@ -127,12 +164,37 @@ struct FeatRow {
 };
 static_assert(sizeof(FeatRow) == SPH_MLP_XSTRIDE * sizeof(float), "feature row");
 
+// dst[i] = src[perm[i]]: four consecutive i per thread, so that four
+// independent loads are in flight (perm is 16-byte aligned).
 template <typename V>
 __global__ __launch_bounds__(256) void k_gather(int64_t n, const uint32_t* __restrict__ perm, const V* __restrict__ src,
                                                 V* __restrict__ dst)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = src[perm[i]];
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (i0 + 4 <= n) {
+        const uint4 p = *(const uint4*)(perm + i0);
+        const V a = src[p.x], b = src[p.y], c = src[p.z], d = src[p.w];
+        dst[i0] = a;
+        dst[i0 + 1] = b;
+        dst[i0 + 2] = c;
+        dst[i0 + 3] = d;
+    } else {
+        for (int64_t i = i0; i < n; i++) dst[i] = src[perm[i]];
+    }
+}
+
+// dst[i] = src[i] for n 8-byte elements, 32 bytes per thread (both buffers
+// 16-byte aligned).
+__global__ __launch_bounds__(256) void k_copy8(int64_t n, const uint64_t* __restrict__ src, uint64_t* __restrict__ dst)
+{
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (i0 + 4 <= n) {
+        const uint4 a = *(const uint4*)(src + i0), b = *(const uint4*)(src + i0 + 2);
+        *(uint4*)(dst + i0) = a;
+        *(uint4*)(dst + i0 + 2) = b;
+    } else {
+        for (int64_t i = i0; i < n; i++) dst[i] = src[i];
+    }
 }
 
 __device__ inline int lower_bound_u64(const uint64_t* a, int lo, int hi, uint64_t v)
@@ -1061,30 +1123,40 @@ static sph_status permute_all(sph_ctx* c, const uint32_t* perm)
                       dens_out ? c->P.rho : nullptr, dens_out ? c->P.drho_dH : nullptr,
                       dens_out ? c->P.omega : nullptr, dens_out ? c->P.P : nullptr,
                       c->P.ax, c->P.ay, c->P.az, c->P.dudt};
-    const int nb = blocks_for(n, 256);
+    const int nb4 = blocks_for((n + 3) / 4, 256);
+    // the caller's arrays are 8-byte aligned: the vector copy needs 16
+    auto copy_back = [&](void* dst) -> sph_status {
+        if (((uintptr_t)dst & 15) == 0) {
+            k_copy8<<<nb4, 256, 0, c->stream>>>(n, (const uint64_t*)c->tmp.p, (uint64_t*)dst);
+            SPH_CHECK_LAUNCH();
+        } else {
+            SPH_CHECK_HIP(hipMemcpyAsync(dst, c->tmp.p, (size_t)n * 8, hipMemcpyDeviceToDevice, c->stream));
+        }
+        return SPH_OK;
+    };
     for (double* a : arrs) {
         if (!a) continue;
-        k_gather<double><<<nb, 256, 0, c->stream>>>(n, perm, a, (double*)c->tmp.p);
+        k_gather<double><<<nb4, 256, 0, c->stream>>>(n, perm, a, (double*)c->tmp.p);
         SPH_CHECK_LAUNCH();
-        SPH_CHECK_HIP(hipMemcpyAsync(a, c->tmp.p, (size_t)n * 8, hipMemcpyDeviceToDevice, c->stream));
+        SPH_TRY(copy_back(a));
     }
     if (c->P.id) {
-        k_gather<int64_t><<<nb, 256, 0, c->stream>>>(n, perm, c->P.id, (int64_t*)c->tmp.p);
+        k_gather<int64_t><<<nb4, 256, 0, c->stream>>>(n, perm, c->P.id, (int64_t*)c->tmp.p);
         SPH_CHECK_LAUNCH();
-        SPH_CHECK_HIP(hipMemcpyAsync(c->P.id, c->tmp.p, (size_t)n * 8, hipMemcpyDeviceToDevice, c->stream));
+        SPH_TRY(copy_back(c->P.id));
     }
     if (c->P.domain) {
-        k_gather<int32_t><<<nb, 256, 0, c->stream>>>(n, perm, c->P.domain, (int32_t*)c->tmp.p);
+        k_gather<int32_t><<<nb4, 256, 0, c->stream>>>(n, perm, c->P.domain, (int32_t*)c->tmp.p);
         SPH_CHECK_LAUNCH();
         SPH_CHECK_HIP(hipMemcpyAsync(c->P.domain, c->tmp.p, (size_t)n * 4, hipMemcpyDeviceToDevice, c->stream));
     }
     if (c->mlp_pending) {
         // predictor features and previous H of this step follow their particles
-        k_gather<double><<<nb, 256, 0, c->stream>>>(n, perm, (const double*)c->mlp_hprev.p, (double*)c->tmp.p);
+        k_gather<double><<<nb4, 256, 0, c->stream>>>(n, perm, (const double*)c->mlp_hprev.p, (double*)c->tmp.p);
         SPH_CHECK_LAUNCH();
         SPH_CHECK_HIP(hipMemcpyAsync(c->mlp_hprev.p, c->tmp.p, (size_t)n * 8, hipMemcpyDeviceToDevice, c->stream));
         SPH_TRY(buf_ensure(c->tmp, (size_t)n * sizeof(float4) * 2));
-        k_gather<FeatRow><<<nb, 256, 0, c->stream>>>(n, perm, (const FeatRow*)c->mlp_X.p, (FeatRow*)c->tmp.p);
+        k_gather<FeatRow><<<nb4, 256, 0, c->stream>>>(n, perm, (const FeatRow*)c->mlp_X.p, (FeatRow*)c->tmp.p);
         SPH_CHECK_LAUNCH();
         SPH_CHECK_HIP(hipMemcpyAsync(c->mlp_X.p, c->tmp.p, (size_t)n * sizeof(FeatRow), hipMemcpyDeviceToDevice,
                                      c->stream));

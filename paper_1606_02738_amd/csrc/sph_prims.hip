@@ -108,16 +108,25 @@ __global__ __launch_bounds__(256) void k_rs_hist(const uint64_t* __restrict__ ke
     hist[(long)tid * nb + blockIdx.x] = h[tid];
 }
 
+// The tile's keys are ranked stably by digit into LDS (local order: wave,
+// round, lane, i.e. input order within each digit), then written out in
+// that order: consecutive lanes write consecutive positions of one digit's
+// run, so the stores coalesce into runs of ~RS_TILE / 256 keys.
 __global__ __launch_bounds__(256) void k_rs_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                     uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, int n,
                                                     int shift, const int* __restrict__ offs, int nb)
 {
     __shared__ int wcount[RS_WAVES][256];
     __shared__ int wbase[RS_WAVES][256];
+    __shared__ int gshift[256];  // global position - local position, per digit
+    __shared__ int wsum[RS_WAVES];
+    __shared__ uint64_t sk[RS_TILE];
+    __shared__ uint32_t sv[RS_TILE];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     for (int q = tid; q < RS_WAVES * 256; q += 256) (&wcount[0][0])[q] = 0;
     __syncthreads();
-    const long wstart = (long)blockIdx.x * RS_TILE + (long)w * 64 * RS_ITEMS;
+    const long tile = (long)blockIdx.x * RS_TILE;
+    const long wstart = tile + (long)w * 64 * RS_ITEMS;
     uint64_t k[RS_ITEMS];
     uint32_t v[RS_ITEMS];
 #pragma unroll
@@ -134,8 +143,22 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint64_t* __restrict__
     }
     __syncthreads();
     {
-        const int d = tid;  // 256 threads = 256 digits
-        int run = offs[(long)d * nb + blockIdx.x];
+        // local start of digit d: exclusive scan over the digits of the
+        // tile's counts (one digit per thread: wave scans, then wave sums)
+        const int d = tid;
+        int cnt = 0;
+        for (int q = 0; q < RS_WAVES; q++) cnt += wcount[q][d];
+        int inc = cnt;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int t = __shfl_up(inc, off);
+            if (lane >= off) inc += t;
+        }
+        if (lane == 63) wsum[w] = inc;
+        __syncthreads();
+        int start = inc - cnt;
+        for (int q = 0; q < w; q++) start += wsum[q];
+        gshift[d] = offs[(long)d * nb + blockIdx.x] - start;
+        int run = start;
         for (int q = 0; q < RS_WAVES; q++) {
             wbase[q][d] = run;
             run += wcount[q][d];
@@ -162,10 +185,17 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint64_t* __restrict__
         if (valid && rank == 0) wbase[w][d] = base + __popcll(mask);
         __builtin_amdgcn_wave_barrier();
         if (valid) {
-            const int pos = base + rank;
-            kout[pos] = k[r];
-            vout[pos] = v[r];
+            sk[base + rank] = k[r];
+            sv[base + rank] = v[r];
         }
+    }
+    __syncthreads();
+    const int in_tile = (int)min((long)RS_TILE, (long)n - tile);
+    for (int e = tid; e < in_tile; e += 256) {
+        const uint64_t kk = sk[e];
+        const int pos = gshift[(int)((kk >> shift) & 255u)] + e;
+        kout[pos] = kk;
+        vout[pos] = sv[e];
     }
 }
 
