@@ -550,8 +550,8 @@ def main():
     sim.run()
     torch.cuda.synchronize()
     st0 = sim.stats()
-    log("cold start: %.2f s, sweeps=%d leaves=%d depth=%d" % (time.perf_counter() - t0, st0["sweeps"],
-                                                              st0["n_leaves"], st0["depth"]))
+    log("cold start: %.2f s, sweeps=%d leaves=%d depth=%d list=%d" % (
+        time.perf_counter() - t0, st0["sweeps"], st0["n_leaves"], st0["depth"], st0["n_list"]))
     H = t["H"]
     Hs = H[::max(1, n // 2_000_000)].float()
     q = torch.quantile(Hs, torch.tensor([0.001, 0.999], device=Hs.device)).cpu().numpy()
