@@ -849,8 +849,9 @@ __device__ inline bool walk_near_f(const float* alo, const float* ahi, const flo
 // float test is looser, and every entry passes the same exact test (which
 // implies the float test).  A round's entries go to the slot, then to
 // 64-entry chunks of the pool (at most two new ones per round).  One wave
-// per leaf, four per workgroup.
-__global__ __launch_bounds__(256) void k_walk_wave(int n_leaves, const int* __restrict__ leaf_node,
+// per leaf, four per workgroup, eight waves per SIMD (64 VGPRs, no spills;
+// the walk waits on its loads).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_walk_wave(int n_leaves, const int* __restrict__ leaf_node,
                                                    const WNode* __restrict__ wn, const double* __restrict__ l_lo,
                                                    const double* __restrict__ l_hi, const int* __restrict__ l_dom,
                                                    const int* __restrict__ l_top, const DomainInfo* __restrict__ di,
