@@ -596,7 +596,8 @@ __constant__ float c_dirs[SPH_NDIR][3] = {
     {0.57735027f, 0.57735027f, 0.57735027f}, {0.57735027f, 0.57735027f, -0.57735027f},
     {0.57735027f, -0.57735027f, 0.57735027f}, {0.57735027f, -0.57735027f, -0.57735027f}};
 
-__global__ __launch_bounds__(256) void k_wnodes(const Node* __restrict__ nodes, int n_nodes, WNode* __restrict__ w)
+__global__ __launch_bounds__(256) void k_wnodes(const Node* __restrict__ nodes, int n_nodes, double skin_abs,
+                                                WNode* __restrict__ w)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_nodes) return;
@@ -610,7 +611,8 @@ __global__ __launch_bounds__(256) void k_wnodes(const Node* __restrict__ nodes, 
     o.next = -1;
     o.count = nd.count;
     o.leaf = nd.leaf;
-    o.hl = 0.0f;  // set with the list radii (k_node_hmax)
+    // float bound of the subtree's list radii (as k_node_hmax sets it)
+    o.hl = __double2float_ru((nd.hmax * (1.0 + SPH_LIST_SKIN) + skin_abs) * (1.0 + 1e-6));
     o.pad = nd.n_child;
     w[k] = o;
 }
@@ -1252,7 +1254,8 @@ sph_status relist(sph_ctx* c)
 {
     // particle lists: radii and skins from the current H
     if (c->prm.lists == SPH_LISTS_PARTICLE) SPH_TRY(plist_ext(c, true, nullptr));
-    SPH_TRY(node_hmax_all(c, true));
+    if (!c->radii_fresh) SPH_TRY(node_hmax_all(c, true));
+    c->radii_fresh = false;
     const int nL = c->n_leaves;
     int* counts = (int*)c->l_off.p;
     int* flags = (int*)c->flags.p;
@@ -1577,7 +1580,8 @@ sph_status build_all(sph_ctx* c)
     // list extents plus the largest skin)
     if (c->prm.lists == SPH_LISTS_PARTICLE) c->skin_abs = c->skin_max;
     SPH_TRY(buf_ensure(c->wnodes, (size_t)n_nodes * sizeof(WNode)));
-    k_wnodes<<<blocks_for(n_nodes, 256), 256, 0, c->stream>>>((const Node*)c->nodes.p, n_nodes, (WNode*)c->wnodes.p);
+    k_wnodes<<<blocks_for(n_nodes, 256), 256, 0, c->stream>>>((const Node*)c->nodes.p, n_nodes, c->skin_abs,
+                                                                (WNode*)c->wnodes.p);
     SPH_CHECK_LAUNCH();
     for (size_t l = 0; l + 1 < c->level_off.size(); l++) {
         const int ls = c->level_off[l], nl = c->level_off[l + 1] - ls;
@@ -1585,6 +1589,10 @@ sph_status build_all(sph_ctx* c)
         k_wnext<<<blocks_for(nl, 256), 256, 0, c->stream>>>((const Node*)c->nodes.p, ls, nl, (WNode*)c->wnodes.p);
         SPH_CHECK_LAUNCH();
     }
+    // with cell lists the cells' largest H (octree statistics), the leaves'
+    // list radii (leaf fill) and the walk nodes' bounds are those of the
+    // current H: the relist need not recompute them
+    c->radii_fresh = c->prm.lists == SPH_LISTS_CELL;
     SPH_TRY(relist(c));
     SPH_TRY(read_int(c, flags, &fl));
     if (fl & FLAG_INVALID) return SPH_ERR_INVALID;

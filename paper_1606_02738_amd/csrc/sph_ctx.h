@@ -94,6 +94,7 @@ struct sph_ctx {
     DevBuf walk_ovf, walk_link;   // its overflow chunks; chunk links (head, incomplete, next)
     int walk_cap = 128;           // entries per slot (grows after an overflow)
     bool dens_outputs_dead = false;  // the build need not permute rho, drho_dH, omega, P
+    bool radii_fresh = false;        // list radii and walk bounds are those of the current H
     DevBuf pos4, fv4, hf;         // kernel-side particle data (T = float or double)
     // per-particle lists (lists = SPH_LISTS_PARTICLE)
     DevBuf pq, pR, plen, plist;   // fixed-point positions + mass, list radii, list lengths, entries
