@@ -128,6 +128,43 @@ def test_small_leaves(n_split):
     assert_close(g, o, TOL_FP64, stats=st)
 
 
+@pytest.mark.parametrize("force", ["gather", "pairs"])
+def test_walk_overflow_pool_exhausted(force):
+    """Initial H 2.5x too large and leaves of at most 8 particles: every
+    leaf's list holds hundreds of leaves, far more than its slot (32
+    entries at these sizes) plus the shared pool of 64-entry chunks can
+    take, so the leaves that find no free chunk are walked again at their
+    scanned offsets; the converged state must still be the oracle's."""
+    log("case lattice24 n_split=8 H x2.5 %s" % force)
+    d = gen.lattice(24, vsigma=0.1, seed=11)
+    d["H"] = d["H"] * 2.5
+    g, st = gpu_run(d, precision="fp64", n_split=8, force=force)
+    # the build's slot size (128 entries, halved while the slots exceed 64 B
+    # per particle) and pool (at least 1024 chunks of 64): the entries past
+    # the slots exceed the pool
+    n, nL = d["x"].size, st["n_leaves"]
+    cap = 128
+    while cap > 16 and nL * cap * 16 > n * 64:
+        cap //= 2
+    assert st["n_list"] - cap * nL > max(1024, n * 16 // 1024) * 64
+    o = oracle_run(d)
+    assert st["n_unconverged"] == 0
+    assert_close(g, o, TOL_FP64, counts_exact=True, stats=st)
+
+
+def test_walk_two_pass_one_particle_leaves():
+    """Leaves of one particle: the one-pass slots (16 entries per leaf at
+    least) would exceed their memory bound, so the lists are counted by one
+    walk and written at the scanned offsets by a second."""
+    log("case lattice32 n_split=1")
+    d = gen.lattice(32, vsigma=0.1, seed=13)
+    g, st = gpu_run(d, precision="fp64", n_split=1, force="gather")
+    # the smallest slots (16 entries of 16 B) exceed 64 B per particle + 1 MiB
+    assert st["n_leaves"] * 16 * 16 > d["x"].size * 64 + (1 << 20)
+    o = oracle_run(d)
+    assert_close(g, o, TOL_FP64, counts_exact=True, stats=st)
+
+
 def test_sod_small_fp32c():
     log("case sod 20/10 fp32c")
     d = gen.sod(20)
