@@ -572,7 +572,6 @@ __global__ __launch_bounds__(256) void k_leaf_refresh(int n_leaves, const int* _
 // pruning cells whose box lies farther away than h_A (and than the largest
 // list radius below them, for symmetric lists).
 // ---------------------------------------------------------------------------
-#define WALK_STACK 160
 
 __device__ inline double box_dist(const double* alo, const double* ahi, const double* blo, const double* bhi,
                                   const double* s)
