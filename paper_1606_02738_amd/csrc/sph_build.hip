@@ -1302,6 +1302,9 @@ sph_status relist(sph_ctx* c)
     SPH_CHECK_HIP(hipMemcpyAsync(hf, flags + FI_NLIST, sizeof(hf), hipMemcpyDeviceToHost, c->stream));
     SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
     const int total = hf[0], incomplete = one_pass ? hf[FI_WINC - FI_NLIST] : 0;
+    // particles in the fullest leaf above 64 (0: none), set by the leaf fill
+    // of the last build (only a build clears the flags past FI_FLAGS)
+    c->max_leaf = hf[FI_MAXLEAF - FI_NLIST];
     if (total < 0) return SPH_ERR_WORKSPACE;
     SPH_TRY(buf_ensure(c->list, (size_t)std::max(total, 1) * sizeof(ListEntry)));
     if (one_pass) {
@@ -1505,24 +1508,35 @@ sph_status build_all(sph_ctx* c)
                                                   bnd, nchild);
         SPH_CHECK_LAUNCH();
         SPH_TRY(scan_exclusive(c, nchild, nchild, n_level, flags + FI_NCHILD));
+        // the children go at the scanned offsets, whatever their total: when
+        // the node buffer holds 8 per cell of the level (the most a split
+        // makes), they are written while the host reads the total
+        const bool early = (size_t)n_nodes + 8 * (size_t)n_level <= cap;
+        if (early) {
+            k_emit_children<<<nbl, 256, 0, c->stream>>>((Node*)c->nodes.p, level_start, n_level, nchild, n_nodes, D,
+                                                         c->prm.n_split, h_ratio, bnd);
+            SPH_CHECK_LAUNCH();
+        }
         int total = 0;
         SPH_TRY(read_int(c, flags + FI_NCHILD, &total));
         c->level_off.push_back(n_nodes);
         if (total == 0) break;
-        if ((size_t)(n_nodes + total) > cap) {
-            size_t ncap = std::max((size_t)(n_nodes + total) * 3 / 2, cap * 2);
-            DevBuf nb2;
-            SPH_TRY(buf_ensure(nb2, ncap * sizeof(Node)));
-            SPH_CHECK_HIP(hipMemcpyAsync(nb2.p, c->nodes.p, (size_t)n_nodes * sizeof(Node), hipMemcpyDeviceToDevice,
-                                         c->stream));
-            SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
-            buf_free(c->nodes);
-            c->nodes = nb2;
-            cap = ncap;
+        if (!early) {
+            if ((size_t)(n_nodes + total) > cap) {
+                size_t ncap = std::max((size_t)(n_nodes + total) * 3 / 2, cap * 2);
+                DevBuf nb2;
+                SPH_TRY(buf_ensure(nb2, ncap * sizeof(Node)));
+                SPH_CHECK_HIP(hipMemcpyAsync(nb2.p, c->nodes.p, (size_t)n_nodes * sizeof(Node),
+                                             hipMemcpyDeviceToDevice, c->stream));
+                SPH_CHECK_HIP(hipStreamSynchronize(c->stream));
+                buf_free(c->nodes);
+                c->nodes = nb2;
+                cap = ncap;
+            }
+            k_emit_children<<<nbl, 256, 0, c->stream>>>((Node*)c->nodes.p, level_start, n_level, nchild, n_nodes, D,
+                                                         c->prm.n_split, h_ratio, bnd);
+            SPH_CHECK_LAUNCH();
         }
-        k_emit_children<<<nbl, 256, 0, c->stream>>>((Node*)c->nodes.p, level_start, n_level, nchild, n_nodes, D,
-                                                     c->prm.n_split, h_ratio, bnd);
-        SPH_CHECK_LAUNCH();
         level_start = n_nodes;
         n_level = total;
         n_nodes += total;
@@ -1558,7 +1572,7 @@ sph_status build_all(sph_ctx* c)
         (int*)c->l_count.p, (double*)c->l_origin.p, (double*)c->l_lo.p, (double*)c->l_hi.p, (double*)c->l_hlist.p,
         (int*)c->l_dom.p, (int*)c->l_cnt.p, c->skin_abs, flags + FI_MAXLEAF);
     SPH_CHECK_LAUNCH();
-    SPH_TRY(read_int(c, flags + FI_MAXLEAF, &c->max_leaf));
+    // (the fullest leaf's count is read back with the list totals)
 
     // 6. cell-relative coordinates
     const int es = c->elem_size();
