@@ -288,16 +288,21 @@ __device__ inline bool extent_too_large(const Node& nd, double h_ratio)
 // are >= 0 (validated), so their doubles order like their bit patterns as
 // signed 64-bit integers (and so do the -inf / +inf starting values): the
 // chunks meet in 64-bit integer atomics min / max, which give exactly the
-// minima and maxima of the doubles.
+// minima and maxima of the doubles.  A -0 (which passes the validation)
+// enters as +0: its bit pattern would order below -inf.
 #define STATS_CHUNK 1024
 
+__device__ inline long long stats_bits(double v)
+{
+    return __double_as_longlong(v == 0.0 ? 0.0 : v);
+}
 __device__ inline void atomic_min_d(double* p, double v)
 {
-    atomicMin((long long*)p, __double_as_longlong(v));
+    atomicMin((long long*)p, stats_bits(v));
 }
 __device__ inline void atomic_max_d(double* p, double v)
 {
-    atomicMax((long long*)p, __double_as_longlong(v));
+    atomicMax((long long*)p, stats_bits(v));
 }
 
 // Chunks of each cell, and the octant bounds [bnd[0..8]] of each cell set to

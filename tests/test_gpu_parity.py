@@ -165,6 +165,20 @@ def test_walk_two_pass_one_particle_leaves():
     assert_close(g, o, TOL_FP64, counts_exact=True, stats=st)
 
 
+def test_negative_zero_positions():
+    """Coordinates of -0 (valid: inside [0, L)) in leaves of one particle:
+    the cells' boxes must hold them as 0 (their bit patterns order below
+    -inf in the integer min / max of the box statistics)."""
+    log("case lattice16 x = -0 layer, n_split=1")
+    d = gen.lattice(16, vsigma=0.1, seed=17)
+    first = d["x"] < 1.0 / 16
+    d["x"][first] = -0.0
+    assert np.signbit(d["x"][first]).all()
+    g, st = gpu_run(d, precision="fp64", n_split=1, force="gather")
+    o = oracle_run(d)
+    assert_close(g, o, TOL_FP64, counts_exact=True, stats=st)
+
+
 def test_sod_small_fp32c():
     log("case sod 20/10 fp32c")
     d = gen.sod(20)
