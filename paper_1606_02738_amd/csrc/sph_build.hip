@@ -823,7 +823,7 @@ __global__ __launch_bounds__(128) void k_walk(int n_leaves, const int* __restric
 // descent) grows the stack by at most 7 per level below the top grid.
 #define WALK_STACK 1024
 #define WALK_RESERVE (7 * (SPH_MAX_DEPTH + 1))
-static_assert(WALK_STACK - WALK_RESERVE >= 64, "a round must fit");
+static_assert(WALK_STACK - WALK_RESERVE >= 8 * 27, "the first round's children must fit");
 
 __device__ inline void walk_wave_sync()
 {
@@ -857,13 +857,11 @@ __device__ inline bool walk_near_f(const float* alo, const float* ahi, const flo
 // 64-entry chunks of the pool (at most two new ones per round).  One wave
 // per leaf, four per workgroup, eight waves per SIMD (64 VGPRs, no spills;
 // the walk waits on its loads).
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_walk_wave(int n_leaves, const int* __restrict__ leaf_node,
-                                                   const WNode* __restrict__ wn, const double* __restrict__ l_lo,
-                                                   const double* __restrict__ l_hi, const int* __restrict__ l_dom,
-                                                   const int* __restrict__ l_top, const DomainInfo* __restrict__ di,
-                                                   const double* __restrict__ l_hlist, int* counts,
-                                                   ListEntry* __restrict__ list, int list_cap, int with_dir, int sym,
-                                                   int* flags, ListEntry* ovf, int* link, int ovf_chunks)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_walk_wave(
+    int n_leaves, const int* __restrict__ leaf_node, const WNode* __restrict__ wn, const double* __restrict__ l_lo,
+    const double* __restrict__ l_hi, const int* __restrict__ l_dom, const int* __restrict__ l_top,
+    const DomainInfo* __restrict__ di, const double* __restrict__ l_hlist, int* counts, ListEntry* __restrict__ list,
+    int list_cap, int with_dir, int sym, int* flags, ListEntry* ovf, int* link, int ovf_chunks)
 {
     __shared__ uint32_t stk[4][WALK_STACK];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
