@@ -171,6 +171,19 @@ sph_status sph_create(const sph_params* params, void* workspace, size_t bytes, v
         if (hipEventCreate(&c->ev[k]) != hipSuccess) s = SPH_ERR_HIP;
     for (int k = 0; k < 4 && s == SPH_OK; k++)
         if (hipEventCreate(&c->kev[k]) != hipSuccess) s = SPH_ERR_HIP;
+    // a second stream for the build's permutation (optional: without it the
+    // permutation stays on the caller's stream)
+    if (s == SPH_OK) {
+        if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&c->side_ev[0], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->side_ev[1], hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            if (c->side) (void)hipStreamDestroy(c->side);
+            for (hipEvent_t& e : c->side_ev)
+                if (e) (void)hipEventDestroy(e), e = nullptr;
+            c->side = nullptr;
+        }
+    }
     if (s == SPH_OK && hipMemsetAsync(c->flags.p, 0, FI_NFLAGS * sizeof(int), c->stream) != hipSuccess) s = SPH_ERR_HIP;
     if (s == SPH_OK && hipMemsetAsync(c->counters.p, 0, CNT_ALLOC * 8, c->stream) != hipSuccess) s = SPH_ERR_HIP;
     if (s != SPH_OK) {
@@ -186,6 +199,12 @@ sph_status sph_destroy(sph_ctx* c)
     if (!c) return SPH_OK;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
+    if (c->side) {
+        (void)hipStreamSynchronize(c->side);
+        (void)hipStreamDestroy(c->side);
+    }
+    for (hipEvent_t e : c->side_ev)
+        if (e) (void)hipEventDestroy(e);
     DevBuf* all[] = {&c->dom_d, &c->dstat, &c->keys[0], &c->keys[1], &c->vals[0], &c->vals[1], &c->ikeys[0], &c->ikeys[1], &c->ivals[0], &c->ivals[1], &c->dranges, &c->tmp, &c->nodes, &c->wnodes,
                      &c->nchild, &c->coff, &c->lvl_cmap, &c->lvl_bnd, &c->leafmark, &c->leafscan, &c->leaf_node, &c->l_begin, &c->l_count,
                      &c->l_origin, &c->l_lo, &c->l_hi, &c->l_hlist, &c->l_dom, &c->l_off, &c->l_active, &c->l_sorted,

@@ -1117,44 +1117,57 @@ static sph_status read_int(sph_ctx* c, const int* dptr, int* out)
     return SPH_OK;
 }
 
-static sph_status permute_all(sph_ctx* c, const uint32_t* perm)
+// Permutes the caller's arrays by perm.  x, y, z and H, which the octree
+// reads next, on the context's stream; the other arrays, when the context
+// has a second stream and side_tmp (8 bytes per particle) is given, on that
+// stream, after the sort (an event) and joined back by perm_join before
+// their first reader, so that they move while the octree is built.
+static sph_status permute_all(sph_ctx* c, const uint32_t* perm, void* side_tmp)
 {
     const int64_t n = c->n;
     SPH_TRY(buf_ensure(c->tmp, (size_t)n * 8));
     // rho, drho_dH, omega and P follow their particles unless the caller's
     // next stages rewrite them before reading (the build inside a step)
     const bool dens_out = !c->dens_outputs_dead;
-    double* arrs[] = {c->P.x, c->P.y, c->P.z, c->P.vx, c->P.vy, c->P.vz, c->P.u, c->P.m, c->P.H,
+    double* geo[] = {c->P.x, c->P.y, c->P.z, c->P.H};
+    double* rest[] = {c->P.vx, c->P.vy, c->P.vz, c->P.u, c->P.m,
                       dens_out ? c->P.rho : nullptr, dens_out ? c->P.drho_dH : nullptr,
                       dens_out ? c->P.omega : nullptr, dens_out ? c->P.P : nullptr,
                       c->P.ax, c->P.ay, c->P.az, c->P.dudt};
     const int nb4 = blocks_for((n + 3) / 4, 256);
-    // the caller's arrays are 8-byte aligned: the vector copy needs 16
-    auto copy_back = [&](void* dst) -> sph_status {
-        if (((uintptr_t)dst & 15) == 0) {
-            k_copy8<<<nb4, 256, 0, c->stream>>>(n, (const uint64_t*)c->tmp.p, (uint64_t*)dst);
+    const bool split = c->side && side_tmp;
+    hipStream_t s2 = split ? c->side : c->stream;
+    void* t2 = split ? side_tmp : c->tmp.p;
+    if (split) {
+        SPH_CHECK_HIP(hipEventRecord(c->side_ev[0], c->stream));
+        SPH_CHECK_HIP(hipStreamWaitEvent(c->side, c->side_ev[0], 0));
+        c->side_pending = true;
+    }
+    // gather into tmp, then back (the caller's arrays are 8-byte aligned:
+    // the vector copy needs 16)
+    auto permute8 = [&](void* a, bool is_id, hipStream_t st, void* tmp) -> sph_status {
+        if (is_id) k_gather<int64_t><<<nb4, 256, 0, st>>>(n, perm, (const int64_t*)a, (int64_t*)tmp);
+        else k_gather<double><<<nb4, 256, 0, st>>>(n, perm, (const double*)a, (double*)tmp);
+        SPH_CHECK_LAUNCH();
+        if (((uintptr_t)a & 15) == 0) {
+            k_copy8<<<nb4, 256, 0, st>>>(n, (const uint64_t*)tmp, (uint64_t*)a);
             SPH_CHECK_LAUNCH();
         } else {
-            SPH_CHECK_HIP(hipMemcpyAsync(dst, c->tmp.p, (size_t)n * 8, hipMemcpyDeviceToDevice, c->stream));
+            SPH_CHECK_HIP(hipMemcpyAsync(a, tmp, (size_t)n * 8, hipMemcpyDeviceToDevice, st));
         }
         return SPH_OK;
     };
-    for (double* a : arrs) {
-        if (!a) continue;
-        k_gather<double><<<nb4, 256, 0, c->stream>>>(n, perm, a, (double*)c->tmp.p);
-        SPH_CHECK_LAUNCH();
-        SPH_TRY(copy_back(a));
-    }
-    if (c->P.id) {
-        k_gather<int64_t><<<nb4, 256, 0, c->stream>>>(n, perm, c->P.id, (int64_t*)c->tmp.p);
-        SPH_CHECK_LAUNCH();
-        SPH_TRY(copy_back(c->P.id));
-    }
+    for (double* a : rest)
+        if (a) SPH_TRY(permute8(a, false, s2, t2));
+    if (c->P.id) SPH_TRY(permute8(c->P.id, true, s2, t2));
     if (c->P.domain) {
-        k_gather<int32_t><<<nb4, 256, 0, c->stream>>>(n, perm, c->P.domain, (int32_t*)c->tmp.p);
+        k_gather<int32_t><<<nb4, 256, 0, s2>>>(n, perm, c->P.domain, (int32_t*)t2);
         SPH_CHECK_LAUNCH();
-        SPH_CHECK_HIP(hipMemcpyAsync(c->P.domain, c->tmp.p, (size_t)n * 4, hipMemcpyDeviceToDevice, c->stream));
+        SPH_CHECK_HIP(hipMemcpyAsync(c->P.domain, t2, (size_t)n * 4, hipMemcpyDeviceToDevice, s2));
     }
+    if (split) SPH_CHECK_HIP(hipEventRecord(c->side_ev[1], c->side));
+    for (double* a : geo)
+        if (a) SPH_TRY(permute8(a, false, c->stream, c->tmp.p));
     if (c->mlp_pending) {
         // predictor features and previous H of this step follow their particles
         k_gather<double><<<nb4, 256, 0, c->stream>>>(n, perm, (const double*)c->mlp_hprev.p, (double*)c->tmp.p);
@@ -1167,6 +1180,14 @@ static sph_status permute_all(sph_ctx* c, const uint32_t* perm)
                                      c->stream));
     }
     return SPH_OK;
+}
+
+// The context's stream waits for the arrays permuted on the second stream.
+static void perm_join(sph_ctx* c)
+{
+    if (!c->side_pending) return;
+    (void)hipStreamWaitEvent(c->stream, c->side_ev[1], 0);
+    c->side_pending = false;
 }
 
 // Unordered pair tasks of the neighbour-cell lists: the entries a leaf owns.
@@ -1469,7 +1490,13 @@ sph_status build_all(sph_ctx* c)
     SPH_TRY(radix_sort(c, (int)n, c->key_bits, c->keys, c->vals, &res));
     const uint64_t* keys = (const uint64_t*)c->keys[res].p;
     c->keys_sorted = keys;
-    SPH_TRY(permute_all(c, (const uint32_t*)c->vals[res].p));
+    // the other key buffer is free until the next sort: the second stream's
+    // scratch; whatever path leaves this build, the stream waits for it
+    struct PermJoin {
+        sph_ctx* c;
+        ~PermJoin() { perm_join(c); }
+    } join_on_exit{c};
+    SPH_TRY(permute_all(c, (const uint32_t*)c->vals[res].p, c->keys[res ^ 1].p));
     SPH_TRY(buf_ensure(c->dranges, (size_t)(nd + 1) * sizeof(int)));
     SPH_TRY(domain_ranges(c));
 
@@ -1577,7 +1604,9 @@ sph_status build_all(sph_ctx* c)
     SPH_CHECK_LAUNCH();
     // (the fullest leaf's count is read back with the list totals)
 
-    // 6. cell-relative coordinates
+    // 6. cell-relative coordinates (the masses and every later stage need the
+    // arrays permuted on the second stream)
+    perm_join(c);
     const int es = c->elem_size();
     SPH_TRY(buf_ensure(c->pos4, (size_t)n * 4 * es));
     SPH_TRY(buf_ensure(c->fv4, (size_t)n * 4 * es));

@@ -95,6 +95,9 @@ struct sph_ctx {
     int walk_cap = 128;           // entries per slot (grows after an overflow)
     bool dens_outputs_dead = false;  // the build need not permute rho, drho_dH, omega, P
     bool radii_fresh = false;        // list radii and walk bounds are those of the current H
+    hipStream_t side = nullptr;      // second stream of the build (permutation), default priority
+    hipEvent_t side_ev[2] = {};      // sort done (context stream), permutation done (second stream)
+    bool side_pending = false;       // the context stream has not yet waited for side_ev[1]
     DevBuf pos4, fv4, hf;         // kernel-side particle data (T = float or double)
     // per-particle lists (lists = SPH_LISTS_PARTICLE)
     DevBuf pq, pR, plen, plist;   // fixed-point positions + mass, list radii, list lengths, entries
