@@ -228,7 +228,12 @@ sph_status sph_workspace_size(const sph_params* params, int64_t n, size_t* bytes
  * workspace: DEVICE memory of `bytes` bytes owned by the caller (e.g. a torch
  * uint8 tensor), at least SPH_WORKSPACE_MIN; the context carves all its
  * device buffers from it and the caller must keep it until sph_destroy.
- * hip_stream: a hipStream_t (NULL = default stream). */
+ * hip_stream: a hipStream_t (NULL = default stream); every call's work is
+ * ordered on it.  The context also creates one stream of its own (default
+ * priority, non-blocking) on which a build permutes the arrays the octree
+ * does not read; it is ordered after the sort and joined back into
+ * hip_stream by events before the build returns, and destroyed by
+ * sph_destroy (without it the permutation stays on hip_stream). */
 sph_status sph_create(const sph_params* params, void* workspace, size_t bytes, void* hip_stream, sph_ctx** out);
 
 /* Release the context (its workspace returns to the caller).  Safe on NULL. */
